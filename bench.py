@@ -1,0 +1,156 @@
+"""Benchmark: node-tet pair evaluations per second on one MI355X.
+
+One step = one bs_eval_velocity on the vortex-ring workload (a
+[-1.5,1.5]^2 x [-0.5,0.5] box, 64 x 64 x 22 Kuhn-split cells: 97,175 nodes,
+540,672 tetrahedra, jitter 0.15 h; Gaussian-core ring, radius 1, sigma 0.1;
+fixed distance rule with ray tracing below 2 mean edge lengths, 16 x 16
+angular rule, FP32 with compensated accumulation).  Inputs are resident in
+HBM before the timed region; the output goes to device memory.
+
+Prints one JSON line (see the keys below).  The roofline object covers the
+far-field kernel (the dominant one); its duration is measured with HIP
+events recorded on the launch stream inside the library.  cpu_baseline
+times the FP64 oracle on a bounded sample of nodes (all tetrahedra) on the
+host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector: 256 CUs x 2.4 GHz x 256 flop/clk
+FLOPS_PER_POINT = 26.0     # one Gauss point: 3 sub, |r|^2 (5), rsqrt (1), r^-3 (2), W x r / r^3 + acc (15)
+
+
+def algorithmic_flops(st, nm):
+    """Method flop count of one evaluation: 26 per Gauss point, ray tracing
+    9 per pair + 7 per line (the precheck) + 156 per line that hits."""
+    g1, g4, g11, rt = st["pairs_by_rule"]
+    return (FLOPS_PER_POINT * (g1 + 4 * g4 + 11 * g11) + rt * (9.0 + 7.0 * nm) + 156.0 * st["rt_hit_lines"])
+
+
+def cpu_baseline(mesh, target_seconds=12.0):
+    import oracle
+
+    pol = oracle.make_policy("fixed")
+    rng = np.random.default_rng(123)
+    k = 8
+    while True:
+        tg = rng.choice(mesh.n_nodes, size=k, replace=False)
+        t0 = time.perf_counter()
+        oracle.evaluate(mesh.xyz, mesh.omega, mesh.tets, pol, targets=tg)
+        dt = time.perf_counter() - t0
+        if dt >= target_seconds / 4 or k >= mesh.n_nodes // 2:
+            break
+        k = min(mesh.n_nodes // 2, int(k * max(2.0, target_seconds / 3 / max(dt, 1e-3))))
+    pairs = k * mesh.n_tets
+    return {"value": pairs / dt, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{k} random nodes x all {mesh.n_tets} tets of the same workload (FP64, fixed rule), "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); multi-GPU sharding is not built",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_0712_1695_amd as bs
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    mesh = W.make_config(args.workload)
+    xyz = torch.tensor(mesh.xyz, device=dev)
+    om = torch.tensor(mesh.omega, device=dev)
+    tets = torch.tensor(mesh.tets, device=dev)
+    h = bs.bs_mesh_upload(xyz, om, tets)
+    nm = 16 * 16
+    bs.bs_set_policy(h, kind=bs.BS_POLICY_FIXED, n_phi=16, n_theta=16, precision=args.precision)
+    out = torch.empty((mesh.n_nodes, 3), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        bs.bs_eval_velocity(h, out=out)
+    torch.cuda.synchronize()
+
+    kern = np.zeros(4)
+    stats = None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, stats = bs.bs_eval_velocity(h, out=out, stats=True)
+        kern += np.array(stats["t_kernel_s"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern /= max(args.steps, 1)
+
+    pairs = mesh.n_nodes * mesh.n_tets
+    ms = wall / args.steps * 1e3
+    value = pairs / (wall / args.steps)
+    flops = algorithmic_flops(stats, nm)
+    g1_pairs = stats["pairs_by_rule"][0]
+    far_flops = FLOPS_PER_POINT * g1_pairs  # G1 pairs of the rule; the kernel evaluates all pairs
+    far_t = kern[0]
+    roof = {
+        "kernel": "k_gauss_all (far field, 1-point rule, every pair)",
+        "bound": "alu",
+        "achieved": far_flops / far_t / 1e12,
+        "peak": FP32_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": far_flops / far_t / 1e12 / FP32_PEAK_TFLOPS,
+        "traffic": None,
+        "avg_duration_ms": far_t * 1e3,
+    }
+    line = {
+        "metric": "node-tet pair evals/s (+ % FP32 peak)",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: vortex ring, 64x64x22 Kuhn cells, {mesh.n_nodes} nodes x "
+                        f"{mesh.n_tets} tets, fixed rule (RT < 2 hbar, G11 < 4, G4 < 8, else G1), 16x16 lines, "
+                        f"{['fp32 naive', 'fp32 compensated', 'fp64 accumulation'][args.precision]}",
+            "pairs_per_step": pairs,
+            "pairs_by_rule": stats["pairs_by_rule"],
+            "rt_hit_lines": stats["rt_hit_lines"],
+            "algorithmic_tflop_per_step": flops / 1e12,
+            "path_fp32_peak_frac": flops / (wall / args.steps) / 1e12 / FP32_PEAK_TFLOPS,
+            "kernel_ms": {"far": kern[0] * 1e3, "band": kern[1] * 1e3, "rt": kern[2] * 1e3, "sum": kern[3] * 1e3},
+        },
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(mesh)
+    bs.bs_mesh_free(h)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

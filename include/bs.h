@@ -1,0 +1,166 @@
+/*
+ * bs.h -- C ABI of the Biot-Savart node-velocity library for MI355X (gfx950).
+ *
+ * Problem (Carley, "Evaluation of Biot-Savart integrals on tetrahedral
+ * meshes", Sections 1-2): given points x_i that carry vorticity omega_i and
+ * form the vertices of a tetrahedral mesh over which omega varies linearly,
+ * return the Biot-Savart velocity (eq. 1)
+ *     v(x_i) = -(1/4pi) int_V (x_i - y) x omega(y) / |x_i - y|^3 dV(y)
+ * at every node.  The method (Section 2.2): choose angular Gauss orders N
+ * (polar) and M (azimuth), precompute the line directions s_nm and weights
+ * k_nm, and sum over tetrahedra and lines the exact trapezoid of eq. 5 along
+ * each chord; tetrahedra far from a node may instead be summed by a
+ * volumetric Gauss rule (Introduction).
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns an int status: BS_OK (0) or a negative BS_E_*
+ *     code; none throws or aborts.  bs_last_error() gives a thread-local
+ *     message for the last failure on the calling thread (offending index,
+ *     HIP error string).
+ *   - The caller owns every buffer it passes.  Uploads copy: inputs may be
+ *     freed as soon as the call returns.  The library owns the device memory
+ *     of a bs_mesh until bs_mesh_free.
+ *   - Arrays are row-major, C-contiguous: xyz and omega are [n_nodes][3]
+ *     doubles, tets is [n_tets][4] int32 node indices (0-based), vel is
+ *     [n_nodes][3] doubles in input node order.
+ *   - Pointers are host memory unless BS_PTR_DEVICE is set in the matching
+ *     flags argument, in which case they are device pointers on the current
+ *     HIP device.
+ *   - `stream` is a hipStream_t cast to void* (NULL: the default stream).
+ *     All device work is enqueued on it; calls that return host results
+ *     synchronise it before returning.
+ *   - A bs_mesh may be used by one thread at a time.
+ */
+#ifndef BS_H
+#define BS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+#define BS_OK 0
+#define BS_E_ARG (-1)        /* null pointer, negative size, bad flag         */
+#define BS_E_INDEX (-2)      /* node index out of range or repeated in a tet  */
+#define BS_E_DEGENERATE (-3) /* zero-volume tetrahedron                       */
+#define BS_E_NONFINITE (-4)  /* NaN or Inf in coordinates or vorticity        */
+#define BS_E_STATE (-5)      /* call out of order (e.g. eval without a mesh)  */
+#define BS_E_DEVICE (-6)     /* no gfx950 device, or a HIP runtime failure    */
+#define BS_E_NOMEM (-7)      /* device or host allocation failed              */
+#define BS_E_POLICY (-8)     /* policy out of range                           */
+
+#define BS_PTR_HOST 0u
+#define BS_PTR_DEVICE 1u
+
+/* Rules a (node, tetrahedron) pair can be evaluated with. */
+#define BS_RULE_G1 0  /* 1-point Gauss rule (centroid), degree 1              */
+#define BS_RULE_G4 1  /* 4-point symmetric Gauss rule, degree 2                */
+#define BS_RULE_G11 2 /* 11-point symmetric Gauss rule, degree 4               */
+#define BS_RULE_RT 3  /* ray tracing over the N x M lines (Section 2.1)        */
+
+/* Pair-rule policies. */
+#define BS_POLICY_FIXED 0      /* distance rule: RT / G11 / G4 / G1 (default)  */
+#define BS_POLICY_PURE_RT 1    /* every pair ray traced (the paper's method)    */
+#define BS_POLICY_GAUSS_ONLY 2 /* every pair by the Gauss rule `gauss_rule`     */
+#define BS_POLICY_LEARNED 3    /* network-chosen rule, fixed rule as fallback   */
+
+/* Accumulation precision of the pair sums (the final per-node sum is FP64). */
+#define BS_PREC_FP32_NAIVE 0 /* one FP32 accumulator per component            */
+#define BS_PREC_FP32_COMP 1  /* FP32 tile sums folded by TwoSum (default)      */
+#define BS_PREC_FP64 2       /* FP32 pair terms accumulated in FP64            */
+
+typedef struct bs_mesh bs_mesh; /* opaque; owns all device memory */
+
+/* Mesh description.  Nodes are both the vertices of the tetrahedra and the
+ * points where the velocity is wanted (Section 2). */
+typedef struct {
+    int64_t n_nodes;      /* >= 1                                              */
+    const double *xyz;    /* [n_nodes][3] coordinates                          */
+    const double *omega;  /* [n_nodes][3] nodal vorticity                      */
+    int64_t n_tets;       /* >= 0                                              */
+    const int32_t *tets;  /* [n_tets][4] node indices                          */
+    uint32_t flags;       /* BS_PTR_DEVICE: xyz, omega, tets are device memory */
+    void *stream;         /* hipStream_t or NULL                               */
+} bs_mesh_desc;
+
+/* Validate and copy a mesh to the device, and run the O(n_tets) per-element
+ * precompute (orientation, volume, centroid, rule points and strengths,
+ * ray-tracing records, spatial bins).  Errors: BS_E_ARG (null pointers,
+ * n_nodes < 1, n_tets < 0), BS_E_INDEX (index outside [0, n_nodes) or
+ * repeated within a tet; bs_last_error names the tet), BS_E_NONFINITE,
+ * BS_E_DEGENERATE (|6 V| <= 1e-12 h_T^3, h_T its longest edge), BS_E_DEVICE,
+ * BS_E_NOMEM.  On success *out holds a new mesh with the default policy. */
+int bs_mesh_upload(const bs_mesh_desc *d, bs_mesh **out);
+
+/* New coordinates and vorticity for the same connectivity (a Lagrangian
+ * step, Section 3): re-runs the per-element precompute.  xyz and omega are
+ * [n_nodes][3]; either may be NULL to keep the current values.  Errors as
+ * bs_mesh_upload, plus BS_E_STATE for a NULL mesh. */
+int bs_mesh_update(bs_mesh *m, const double *xyz, const double *omega, uint32_t flags, void *stream);
+
+/* Release a mesh and all its device memory.  NULL is a no-op. */
+void bs_mesh_free(bs_mesh *m);
+
+/* Evaluation policy (Section 2.2 items 2-3 and the far-field rules of the
+ * Introduction).  Distances are node-to-centroid, in units of the mesh's
+ * mean edge length hbar (mean over unique edges):
+ *   incident pair or d < near_cut      -> ray tracing,
+ *   near_cut <= d < d_g11              -> 11-point rule,
+ *   d_g11 <= d < d_g4                  -> 4-point rule,
+ *   d >= d_g4                          -> 1-point rule.
+ * The comparison is taken in binary32 on d^2.  LEARNED uses a 16-64-64-4
+ * network (BF16 weights, layout documented at bs_mlp_* below) to pick a
+ * cheaper rule for pairs the fixed rule sends to RT or G11; below conf_min
+ * softmax confidence it keeps the fixed rule. */
+typedef struct {
+    int kind;                 /* BS_POLICY_*                                    */
+    int n_phi, n_theta;       /* N, M: each in [1, 256]                         */
+    double near_cut;          /* > 0                                            */
+    double d_g11, d_g4;       /* near_cut <= d_g11 <= d_g4                       */
+    int gauss_rule;           /* GAUSS_ONLY: BS_RULE_G1, _G4 or _G11            */
+    int precision;            /* BS_PREC_*                                      */
+    const uint16_t *mlp_bf16; /* LEARNED: host pointer to the packed weights    */
+    int64_t mlp_len;          /* LEARNED: number of uint16 in mlp_bf16          */
+    float conf_min;           /* LEARNED: in [0, 1]                             */
+} bs_policy;
+
+/* Fill *p with the defaults: FIXED, N = M = 16, cuts 2 / 4 / 8, FP32_COMP. */
+void bs_policy_default(bs_policy *p);
+
+/* Validate and install a policy on a mesh (copied; mlp weights copied to the
+ * device).  Errors: BS_E_STATE (NULL mesh), BS_E_POLICY (out of range, bad
+ * weight blob size), BS_E_DEVICE. */
+int bs_set_policy(bs_mesh *m, const bs_policy *p);
+
+/* Counters of the last evaluation. */
+typedef struct {
+    double t_eval_s;          /* device time of the pair kernels and the sum   */
+    double t_kernel_s[4];     /* far field, band corrections, ray tracing, sum */
+    int64_t pairs;            /* n_nodes * n_tets                              */
+    int64_t pairs_by_rule[4]; /* indexed by BS_RULE_*                          */
+    int64_t rt_hit_lines;     /* (line, tet) hits of the ray-traced pairs      */
+    int64_t fp64_retests;     /* near-edge orientation tests redone in FP64    */
+    int64_t reoriented;       /* negatively oriented input tetrahedra          */
+    int32_t nonfinite_out;    /* 1 if any output component is NaN or Inf       */
+    double hbar;              /* mean edge length                              */
+} bs_stats;
+
+/* Velocity at every node, written to vel ([n_nodes][3] FP64, input node
+ * order; host memory unless vel_flags has BS_PTR_DEVICE).  Uses the policy
+ * last set (defaults if none).  st may be NULL.  Errors: BS_E_STATE (NULL
+ * mesh), BS_E_ARG (NULL vel), BS_E_DEVICE (launch or runtime failure). */
+int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, bs_stats *st);
+
+/* Static description of a status code. */
+const char *bs_status_string(int status);
+
+/* Thread-local detail of the last failure on this thread ("" if none). */
+const char *bs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BS_H */

@@ -1,0 +1,273 @@
+"""Python binding of libbs.so, the MI355X Biot-Savart node-velocity library.
+
+Argument marshalling only: every step of an evaluation runs in the HIP
+library.  The function names are those of the C ABI (include/bs.h):
+
+    m = bs_mesh_upload(xyz, omega, tets)          # numpy (host) or torch (device)
+    bs_set_policy(m, kind=BS_POLICY_FIXED, n_phi=16, n_theta=16, ...)
+    v = bs_eval_velocity(m)                      # numpy [n,3] float64
+    bs_eval_velocity(m, out=torch_tensor)        # into device memory
+    bs_mesh_update(m, xyz=..., omega=...)        # same connectivity
+    bs_mesh_free(m)
+
+torch is used only for device memory and the current HIP stream.  There is
+no fallback: if libbs.so is missing or no gfx950 device is present the calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbs.so")
+
+BS_OK = 0
+BS_E_ARG = -1
+BS_E_INDEX = -2
+BS_E_DEGENERATE = -3
+BS_E_NONFINITE = -4
+BS_E_STATE = -5
+BS_E_DEVICE = -6
+BS_E_NOMEM = -7
+BS_E_POLICY = -8
+
+BS_PTR_HOST = 0
+BS_PTR_DEVICE = 1
+
+BS_RULE_G1, BS_RULE_G4, BS_RULE_G11, BS_RULE_RT = 0, 1, 2, 3
+BS_POLICY_FIXED, BS_POLICY_PURE_RT, BS_POLICY_GAUSS_ONLY, BS_POLICY_LEARNED = 0, 1, 2, 3
+BS_PREC_FP32_NAIVE, BS_PREC_FP32_COMP, BS_PREC_FP64 = 0, 1, 2
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_nodes", ctypes.c_int64),
+        ("xyz", ctypes.c_void_p),
+        ("omega", ctypes.c_void_p),
+        ("n_tets", ctypes.c_int64),
+        ("tets", ctypes.c_void_p),
+        ("flags", ctypes.c_uint32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class Policy(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int),
+        ("n_phi", ctypes.c_int),
+        ("n_theta", ctypes.c_int),
+        ("near_cut", ctypes.c_double),
+        ("d_g11", ctypes.c_double),
+        ("d_g4", ctypes.c_double),
+        ("gauss_rule", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("mlp_bf16", ctypes.c_void_p),
+        ("mlp_len", ctypes.c_int64),
+        ("conf_min", ctypes.c_float),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("t_eval_s", ctypes.c_double),
+        ("t_kernel_s", ctypes.c_double * 4),
+        ("pairs", ctypes.c_int64),
+        ("pairs_by_rule", ctypes.c_int64 * 4),
+        ("rt_hit_lines", ctypes.c_int64),
+        ("fp64_retests", ctypes.c_int64),
+        ("reoriented", ctypes.c_int64),
+        ("nonfinite_out", ctypes.c_int32),
+        ("hbar", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return dict(t_eval_s=self.t_eval_s, t_kernel_s=list(self.t_kernel_s), pairs=self.pairs,
+                    pairs_by_rule=list(self.pairs_by_rule), rt_hit_lines=self.rt_hit_lines,
+                    fp64_retests=self.fp64_retests, reoriented=self.reoriented,
+                    nonfinite_out=self.nonfinite_out, hbar=self.hbar)
+
+
+# every symbol include/bs.h declares
+EXPORTS = ["bs_mesh_upload", "bs_mesh_update", "bs_mesh_free", "bs_policy_default", "bs_set_policy",
+           "bs_eval_velocity", "bs_status_string", "bs_last_error"]
+
+
+class BsError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {detail or 'error'} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: Optional[str] = None) -> ctypes.CDLL:
+    """Load libbs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} not found: build it with `python -m paper_0712_1695_amd.build`")
+    L = ctypes.CDLL(p)
+    vp = ctypes.c_void_p
+    L.bs_mesh_upload.argtypes = [ctypes.POINTER(MeshDesc), ctypes.POINTER(vp)]
+    L.bs_mesh_upload.restype = ctypes.c_int
+    L.bs_mesh_update.argtypes = [vp, vp, vp, ctypes.c_uint32, vp]
+    L.bs_mesh_update.restype = ctypes.c_int
+    L.bs_mesh_free.argtypes = [vp]
+    L.bs_mesh_free.restype = None
+    L.bs_policy_default.argtypes = [ctypes.POINTER(Policy)]
+    L.bs_policy_default.restype = None
+    L.bs_set_policy.argtypes = [vp, ctypes.POINTER(Policy)]
+    L.bs_set_policy.restype = ctypes.c_int
+    L.bs_eval_velocity.argtypes = [vp, vp, ctypes.c_uint32, vp, ctypes.POINTER(Stats)]
+    L.bs_eval_velocity.restype = ctypes.c_int
+    L.bs_status_string.argtypes = [ctypes.c_int]
+    L.bs_status_string.restype = ctypes.c_char_p
+    L.bs_last_error.argtypes = []
+    L.bs_last_error.restype = ctypes.c_char_p
+    if path is None:
+        _lib = L
+    return L
+
+
+def _check(rc: int, where: str):
+    if rc != BS_OK:
+        L = load_library()
+        raise BsError(rc, where, L.bs_last_error().decode())
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def _stream_handle(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    try:
+        import torch
+
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return ctypes.c_void_p(0)
+
+
+def _ptr(a, dtype):
+    """(pointer, is_device, keepalive) for a numpy array or torch tensor."""
+    if a is None:
+        return None, False, None
+    if _is_torch(a):
+        import torch
+
+        want = {np.float64: torch.float64, np.int32: torch.int32}[dtype]
+        t = a.contiguous()
+        if t.dtype != want:
+            t = t.to(want)
+        return ctypes.c_void_p(t.data_ptr()), t.is_cuda, t
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return ctypes.c_void_p(arr.ctypes.data), False, arr
+
+
+class BsMesh:
+    """Owning handle of a bs_mesh (freed by bs_mesh_free or on collection)."""
+
+    def __init__(self, handle: ctypes.c_void_p, n_nodes: int, n_tets: int):
+        self.handle = handle
+        self.n_nodes = n_nodes
+        self.n_tets = n_tets
+
+    def __del__(self):
+        try:
+            bs_mesh_free(self)
+        except Exception:
+            pass
+
+
+def bs_mesh_upload(xyz, omega, tets, stream=None) -> BsMesh:
+    """Copy a mesh (xyz, omega: [n,3] float64; tets: [T,4] int32; numpy on
+    the host or torch tensors on the device) into the library."""
+    L = load_library()
+    px, dx, kx = _ptr(xyz, np.float64)
+    pw, dw, kw = _ptr(omega, np.float64)
+    pt, dt, kt = _ptr(tets, np.int32)
+    if len({dx, dw, dt}) != 1:
+        raise ValueError("xyz, omega and tets must all be host arrays or all device tensors")
+    n = int(kx.shape[0])
+    T = int(kt.shape[0])
+    d = MeshDesc(n, px, pw, T, pt, BS_PTR_DEVICE if dx else BS_PTR_HOST, _stream_handle(stream))
+    h = ctypes.c_void_p()
+    _check(L.bs_mesh_upload(ctypes.byref(d), ctypes.byref(h)), "bs_mesh_upload")
+    return BsMesh(h, n, T)
+
+
+def bs_mesh_update(mesh: BsMesh, xyz=None, omega=None, stream=None):
+    L = load_library()
+    px, dx, kx = _ptr(xyz, np.float64)
+    pw, dw, kw = _ptr(omega, np.float64)
+    dev = dx if xyz is not None else dw
+    if xyz is not None and omega is not None and dx != dw:
+        raise ValueError("xyz and omega must both be host arrays or both device tensors")
+    _check(L.bs_mesh_update(mesh.handle, px, pw, BS_PTR_DEVICE if dev else BS_PTR_HOST, _stream_handle(stream)),
+           "bs_mesh_update")
+
+
+def bs_mesh_free(mesh: BsMesh):
+    if mesh is not None and mesh.handle:
+        load_library().bs_mesh_free(mesh.handle)
+        mesh.handle = ctypes.c_void_p()
+
+
+def bs_policy_default() -> Policy:
+    p = Policy()
+    load_library().bs_policy_default(ctypes.byref(p))
+    return p
+
+
+def bs_set_policy(mesh: BsMesh, policy: Optional[Policy] = None, **kw):
+    """Install a policy: a Policy struct, or the defaults updated with kw
+    (kind, n_phi, n_theta, near_cut, d_g11, d_g4, gauss_rule, precision,
+    mlp_bf16 (uint16 numpy array), conf_min)."""
+    L = load_library()
+    p = policy if policy is not None else bs_policy_default()
+    keep = None
+    for k, v in kw.items():
+        if k == "mlp_bf16":
+            keep = np.ascontiguousarray(v, dtype=np.uint16)
+            p.mlp_bf16 = keep.ctypes.data
+            p.mlp_len = keep.size
+        else:
+            setattr(p, k, v)
+    _check(L.bs_set_policy(mesh.handle if mesh is not None else None, ctypes.byref(p)), "bs_set_policy")
+    return p
+
+
+def bs_eval_velocity(mesh: BsMesh, out=None, stream=None, stats: bool = False):
+    """Velocity at every node ([n,3] float64, input node order).  out: a
+    device torch tensor to fill (returned), else a new numpy array."""
+    L = load_library()
+    st = Stats() if stats else None
+    if out is None:
+        vel = np.empty((mesh.n_nodes, 3), dtype=np.float64)
+        rc = L.bs_eval_velocity(mesh.handle, ctypes.c_void_p(vel.ctypes.data), BS_PTR_HOST, _stream_handle(stream),
+                                ctypes.byref(st) if st is not None else None)
+    else:
+        if not (_is_torch(out) and out.is_cuda and out.dtype.__str__() == "torch.float64" and out.is_contiguous()):
+            raise ValueError("out must be a contiguous float64 device tensor")
+        if tuple(out.shape) != (mesh.n_nodes, 3):
+            raise ValueError("out must have shape [n_nodes, 3]")
+        vel = out
+        rc = L.bs_eval_velocity(mesh.handle, ctypes.c_void_p(out.data_ptr()), BS_PTR_DEVICE, _stream_handle(stream),
+                                ctypes.byref(st) if st is not None else None)
+    _check(rc, "bs_eval_velocity")
+    return (vel, st.as_dict()) if stats else vel
+
+
+def status_string(status: int) -> str:
+    return load_library().bs_status_string(int(status)).decode()

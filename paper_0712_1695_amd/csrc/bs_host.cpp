@@ -1,0 +1,890 @@
+// bs_host.cpp -- host side of the Biot-Savart node-velocity library: input
+// validation, the O(n_tets) per-element precompute in FP64, spatial ordering,
+// angular tables and the launch sequence of one velocity evaluation.
+//
+// Per-element precompute (Section 2: vorticity linear within each element;
+// Introduction: Gauss rules for distant elements):
+//   |T| = |det(v1-v0, v2-v0, v3-v0)| / 6, centroid (((v0+v1)+v2)+v3)/4 in
+//   input vertex order, rule points p_q = sum_j lambda_qj v_j and strengths
+//   W_q = w_q |T| omega(p_q) / 4pi for the 1-, 4- and 11-point rules.
+// Angular tables (Section 2, eq. 3 and Section 2.2 item 3): Gauss-Legendre
+//   nodes t_n, weights w_n; phi_n = (1 + t_n) pi/2, theta_m = (1 + t_m) pi/2,
+//   line direction s_nm, weight k_nm = (pi/16) sin(phi_n) w_n w_m (the
+//   half-sphere measure of eq. 2 times 1/4pi; the printed 1/(16 pi^2) does not
+//   integrate the half sphere to 1/2).  Each line gives two rays, +s and -s,
+//   both with weight k_nm.
+#include "bs_internal.h"
+
+#include "../../include/bs.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    if (e == hipErrorOutOfMemory) return fail(BS_E_NOMEM, "%s: %s", what, hipGetErrorString(e));
+    return fail(BS_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// --------------------------------------------------------------- quadrature
+
+// Gauss-Legendre on [-1, 1]: Newton on P_n for the positive half; the
+// negative nodes are exact mirrors so that the line set is symmetric.
+void gauss_legendre(int n, std::vector<double> &t, std::vector<double> &w)
+{
+    t.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const int half = (n + 1) / 2;
+    for (int i = 0; i < half; ++i) {
+        double x = std::cos(M_PI * (i + 0.75) / (n + 0.5)); // i-th largest root
+        double dpn = 1.0;
+        for (int it = 0; it < 60; ++it) {
+            double pm = 1.0, p = x;
+            for (int k = 2; k <= n; ++k) {
+                const double pk = ((2 * k - 1) * x * p - (k - 1) * pm) / k;
+                pm = p;
+                p = pk;
+            }
+            if (n == 1) {
+                p = x;
+                pm = 1.0;
+            }
+            dpn = n * (x * p - pm) / (x * x - 1.0);
+            const double dx = p / dpn;
+            x -= dx;
+            if (std::fabs(dx) <= 1e-17) break;
+        }
+        {
+            double pm = 1.0, p = x;
+            for (int k = 2; k <= n; ++k) {
+                const double pk = ((2 * k - 1) * x * p - (k - 1) * pm) / k;
+                pm = p;
+                p = pk;
+            }
+            if (n == 1) {
+                p = x;
+                pm = 1.0;
+            }
+            dpn = n * (x * p - pm) / (x * x - 1.0);
+        }
+        const double wi = 2.0 / ((1.0 - x * x) * dpn * dpn);
+        if (2 * i + 1 == n) x = 0.0;
+        t[n - 1 - i] = x;
+        t[i] = -x;
+        w[n - 1 - i] = wi;
+        w[i] = wi;
+    }
+}
+
+// Symmetric tetrahedral rules as barycentric points and weights (sum 1).
+struct TetRule {
+    int n;
+    double lam[11][4];
+    double w[11];
+};
+
+TetRule tet_rule(int k)
+{
+    TetRule r{};
+    r.n = k;
+    if (k == 1) {
+        for (int j = 0; j < 4; ++j) r.lam[0][j] = 0.25;
+        r.w[0] = 1.0;
+    } else if (k == 4) {
+        // degree 2: one orbit (a, b, b, b) with weight 1/4
+        const double s5 = std::sqrt(5.0);
+        const double a = (5.0 + 3.0 * s5) / 20.0, b = (5.0 - s5) / 20.0;
+        for (int q = 0; q < 4; ++q) {
+            for (int j = 0; j < 4; ++j) r.lam[q][j] = (q == j) ? a : b;
+            r.w[q] = 0.25;
+        }
+    } else {
+        // degree 4 (Keast): centroid, orbit (11/14, 1/14, 1/14, 1/14),
+        // orbit (c, c, d, d) with c, d = (1 +- sqrt(5/14))/4
+        int q = 0;
+        for (int j = 0; j < 4; ++j) r.lam[q][j] = 0.25;
+        r.w[q++] = -148.0 / 1875.0;
+        for (int v = 0; v < 4; ++v, ++q) {
+            for (int j = 0; j < 4; ++j) r.lam[q][j] = (v == j) ? 11.0 / 14.0 : 1.0 / 14.0;
+            r.w[q] = 343.0 / 7500.0;
+        }
+        const double g = std::sqrt(5.0 / 14.0);
+        const double c = (1.0 + g) / 4.0, d = (1.0 - g) / 4.0;
+        for (int i = 0; i < 4; ++i)
+            for (int j = i + 1; j < 4; ++j, ++q) {
+                for (int l = 0; l < 4; ++l) r.lam[q][l] = (l == i || l == j) ? c : d;
+                r.w[q] = 56.0 / 375.0;
+            }
+    }
+    return r;
+}
+
+// --------------------------------------------------------------- helpers
+
+template <typename F>
+void parallel_for(int64_t n, F &&f)
+{
+    unsigned hw = std::thread::hardware_concurrency();
+    int nt = (int)std::min<unsigned>(hw ? hw : 1, 16);
+    if (n < 4096 || nt <= 1) {
+        f(0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int64_t chunk = (n + nt - 1) / nt;
+    for (int k = 0; k < nt; ++k) {
+        const int64_t a = k * chunk, b = std::min(n, a + chunk);
+        if (a >= b) break;
+        th.emplace_back([&, a, b] { f(a, b); });
+    }
+    for (auto &t : th) t.join();
+}
+
+uint64_t spread3(uint64_t v)
+{
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffull;
+    v = (v | v << 16) & 0x1f0000ff0000ffull;
+    v = (v | v << 8) & 0x100f00f00f00f00full;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+    v = (v | v << 2) & 0x1249249249249249ull;
+    return v;
+}
+
+struct DBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+int dalloc(DBuf &b, size_t bytes)
+{
+    if (b.p && b.bytes >= bytes) return BS_OK;
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return hip_fail(e, "hipMalloc");
+    }
+    b.bytes = bytes;
+    return BS_OK;
+}
+
+void dfree(DBuf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+} // namespace
+
+// --------------------------------------------------------------- mesh object
+
+struct bs_mesh {
+    int device = -1;
+    int64_t n = 0, T = 0;
+    int npad = 0, nblk = 0;
+    std::vector<int32_t> tets;     // input connectivity
+    std::vector<double> xyz, omega; // current FP64 inputs
+    double hbar = 0.0, max_vc = 0.0;
+    int64_t reoriented = 0;
+    bsk::Bins bins{};
+    // device buffers
+    DBuf xh, xl, om, blk, node_orig, g1, g4, g11, tid, cell_start;
+    DBuf part, band, rtv, vel, cnt, nonfinite;
+    DBuf dir, dir64, cphi, dia;
+    int part_splits = 0;
+    // policy
+    bs_policy pol{};
+    int ang_N = 0, ang_M = 0;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+int check_device(int *dev)
+{
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0) return fail(BS_E_DEVICE, "no HIP device available");
+    int d = 0;
+    e = hipGetDevice(&d);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, d);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(BS_E_DEVICE, "device %d is %s, this library is built for gfx950", d, prop.gcnArchName);
+    *dev = d;
+    return BS_OK;
+}
+
+// Mean edge length over unique edges: keys (min id, max id) of the input
+// numbering, lengths summed in increasing key order.
+double mean_edge(int64_t n, const double *xyz, int64_t T, const int32_t *tets)
+{
+    static const int ea[6] = {0, 0, 0, 1, 1, 2}, eb[6] = {1, 2, 3, 2, 3, 3};
+    std::vector<int64_t> keys((size_t)(6 * T));
+    for (int64_t t = 0; t < T; ++t)
+        for (int e = 0; e < 6; ++e) {
+            const int64_t a = tets[4 * t + ea[e]], b = tets[4 * t + eb[e]];
+            keys[(size_t)(6 * t + e)] = std::min(a, b) * (n + 1) + std::max(a, b);
+        }
+    std::sort(keys.begin(), keys.end());
+    double sum = 0.0;
+    int64_t cnt = 0;
+    for (size_t i = 0; i < keys.size(); ++i) {
+        if (i > 0 && keys[i] == keys[i - 1]) continue;
+        const int64_t lo = keys[i] / (n + 1), hi = keys[i] % (n + 1);
+        const double dx = xyz[3 * hi] - xyz[3 * lo], dy = xyz[3 * hi + 1] - xyz[3 * lo + 1],
+                     dz = xyz[3 * hi + 2] - xyz[3 * lo + 2];
+        sum += std::sqrt(dx * dx + dy * dy + dz * dz);
+        ++cnt;
+    }
+    return cnt ? sum / (double)cnt : 0.0;
+}
+
+int validate_geometry(bs_mesh *m)
+{
+    const int64_t n = m->n, T = m->T;
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (!std::isfinite(m->xyz[i]) || !std::isfinite(m->omega[i]))
+            return fail(BS_E_NONFINITE, "non-finite coordinate or vorticity at node %lld", (long long)(i / 3));
+    int64_t neg = 0;
+    for (int64_t t = 0; t < T; ++t) {
+        const int32_t *id = &m->tets[4 * t];
+        double v[4][3];
+        for (int j = 0; j < 4; ++j)
+            for (int c = 0; c < 3; ++c) v[j][c] = m->xyz[3 * (int64_t)id[j] + c];
+        double e[3][3], h2 = 0.0;
+        for (int j = 0; j < 3; ++j)
+            for (int c = 0; c < 3; ++c) e[j][c] = v[j + 1][c] - v[0][c];
+        for (int a = 0; a < 4; ++a)
+            for (int b = a + 1; b < 4; ++b) {
+                const double dx = v[b][0] - v[a][0], dy = v[b][1] - v[a][1], dz = v[b][2] - v[a][2];
+                h2 = std::max(h2, dx * dx + dy * dy + dz * dz);
+            }
+        const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                           e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                           e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+        if (!(std::fabs(det) > 1e-12 * h2 * std::sqrt(h2)))
+            return fail(BS_E_DEGENERATE, "tetrahedron %lld has zero volume", (long long)t);
+        if (det < 0) ++neg;
+    }
+    m->reoriented = neg;
+    return BS_OK;
+}
+
+// Everything that depends on coordinates and vorticity: node order, bins,
+// per-tet records.  Connectivity is already validated.
+int build_device_mesh(bs_mesh *m, hipStream_t s)
+{
+    const int64_t n = m->n, T = m->T;
+    const double *X = m->xyz.data(), *W = m->omega.data();
+    m->hbar = T > 0 ? mean_edge(n, X, T, m->tets.data()) : 0.0;
+
+    // ---- nodes in Morton order
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < n; ++i)
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = std::min(lo[c], X[3 * i + c]);
+            hi[c] = std::max(hi[c], X[3 * i + c]);
+        }
+    double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+    std::vector<std::pair<uint64_t, int32_t>> key((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t code = 0;
+        for (int c = 0; c < 3; ++c) {
+            const double u = (X[3 * i + c] - lo[c]) / ext * 2097151.0;
+            code |= spread3((uint64_t)std::min(2097151.0, std::max(0.0, u))) << c;
+        }
+        key[(size_t)i] = {code, (int32_t)i};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int32_t> orig((size_t)n), rank((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        orig[(size_t)i] = key[(size_t)i].second;
+        rank[(size_t)key[(size_t)i].second] = (int32_t)i;
+    }
+    const int npad = (int)(((n + 1023) / 1024) * 1024);
+    const int nblk = (int)((n + bsk::kBlockNodes - 1) / bsk::kBlockNodes);
+    m->npad = npad;
+    m->nblk = nblk;
+    std::vector<float> xh((size_t)3 * npad), xl((size_t)3 * npad), om((size_t)3 * npad);
+    for (int64_t p = 0; p < npad; ++p) {
+        const int64_t i = p < n ? orig[(size_t)p] : orig[0];
+        for (int c = 0; c < 3; ++c) {
+            const double x = X[3 * i + c];
+            const float h = (float)x;
+            xh[(size_t)c * npad + p] = h;
+            xl[(size_t)c * npad + p] = (float)(x - (double)h);
+            om[(size_t)c * npad + p] = (float)W[3 * i + c];
+        }
+    }
+    std::vector<float4> blk((size_t)nblk);
+    for (int b = 0; b < nblk; ++b) {
+        float bl[3] = {3e38f, 3e38f, 3e38f}, bh[3] = {-3e38f, -3e38f, -3e38f};
+        const int64_t e = std::min<int64_t>(n, (int64_t)(b + 1) * bsk::kBlockNodes);
+        for (int64_t p = (int64_t)b * bsk::kBlockNodes; p < e; ++p)
+            for (int c = 0; c < 3; ++c) {
+                bl[c] = std::min(bl[c], xh[(size_t)c * npad + p]);
+                bh[c] = std::max(bh[c], xh[(size_t)c * npad + p]);
+            }
+        float cc[3];
+        for (int c = 0; c < 3; ++c) cc[c] = 0.5f * (bl[c] + bh[c]);
+        double r2 = 0.0;
+        for (int64_t p = (int64_t)b * bsk::kBlockNodes; p < e; ++p) {
+            double d2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                const double d = (double)xh[(size_t)c * npad + p] - cc[c];
+                d2 += d * d;
+            }
+            r2 = std::max(r2, d2);
+        }
+        blk[(size_t)b] = make_float4(cc[0], cc[1], cc[2], (float)(std::sqrt(r2) * (1 + 1e-5) + 1e-6));
+    }
+
+    // ---- tets: centroids, bins
+    std::vector<double> cen((size_t)(3 * T));
+    std::vector<float> cen32((size_t)(3 * T));
+    double clo[3] = {1e300, 1e300, 1e300}, chi[3] = {-1e300, -1e300, -1e300};
+    double max_vc = 0.0;
+    for (int64_t t = 0; t < T; ++t) {
+        const int32_t *id = &m->tets[4 * t];
+        double vc = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const double v = (((X[3 * (int64_t)id[0] + c] + X[3 * (int64_t)id[1] + c]) + X[3 * (int64_t)id[2] + c]) +
+                              X[3 * (int64_t)id[3] + c]) * 0.25;
+            cen[(size_t)(3 * t + c)] = v;
+            cen32[(size_t)(3 * t + c)] = (float)v;
+            clo[c] = std::min(clo[c], v);
+            chi[c] = std::max(chi[c], v);
+        }
+        for (int j = 0; j < 4; ++j) {
+            double d2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                const double d = X[3 * (int64_t)id[j] + c] - cen[(size_t)(3 * t + c)];
+                d2 += d * d;
+            }
+            vc = std::max(vc, d2);
+        }
+        max_vc = std::max(max_vc, std::sqrt(vc));
+    }
+    m->max_vc = max_vc;
+    bsk::Bins bins{};
+    double cs = 2.0 * (m->hbar > 0 ? m->hbar : 1.0);
+    if (T > 0) {
+        // keep the bin count modest for very spread meshes
+        for (;;) {
+            int64_t tot = 1;
+            for (int c = 0; c < 3; ++c) tot *= (int64_t)std::floor((chi[c] - clo[c]) / cs) + 1;
+            if (tot <= std::max<int64_t>(64, 4 * T) && tot <= (1 << 26)) break;
+            cs *= 1.5;
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        bins.lo[c] = T > 0 ? (float)(clo[c] - 1e-3 * cs) : 0.f;
+        bins.dim[c] = T > 0 ? (int)std::floor((chi[c] + 1e-3 * cs - (double)bins.lo[c]) / cs) + 1 : 1;
+    }
+    bins.cs = (float)cs;
+    m->bins = bins;
+    const int64_t ncell = (int64_t)bins.dim[0] * bins.dim[1] * bins.dim[2];
+    std::vector<int32_t> cell_of((size_t)T), cell_start((size_t)ncell + 1, 0);
+    for (int64_t t = 0; t < T; ++t) {
+        int ic[3];
+        for (int c = 0; c < 3; ++c) {
+            int k = (int)std::floor((cen32[(size_t)(3 * t + c)] - bins.lo[c]) / bins.cs);
+            ic[c] = std::min(bins.dim[c] - 1, std::max(0, k));
+        }
+        const int32_t cell = (ic[2] * bins.dim[1] + ic[1]) * bins.dim[0] + ic[0];
+        cell_of[(size_t)t] = cell;
+        cell_start[(size_t)cell + 1]++;
+    }
+    for (int64_t c = 0; c < ncell; ++c) cell_start[(size_t)c + 1] += cell_start[(size_t)c];
+    std::vector<int32_t> order((size_t)T);
+    {
+        std::vector<int32_t> fill(cell_start.begin(), cell_start.end() - 1);
+        for (int64_t t = 0; t < T; ++t) order[(size_t)fill[(size_t)cell_of[(size_t)t]]++] = (int32_t)t;
+    }
+
+    // ---- per-tet records in bin order
+    std::vector<float> g1((size_t)T * 8), g4((size_t)T * 32), g11((size_t)T * 88);
+    std::vector<int4> tid((size_t)T);
+    const TetRule R1 = tet_rule(1), R4 = tet_rule(4), R11 = tet_rule(11);
+    parallel_for(T, [&](int64_t a, int64_t b) {
+        for (int64_t k = a; k < b; ++k) {
+            const int64_t t = order[(size_t)k];
+            const int32_t *id = &m->tets[4 * t];
+            double v[4][3], w[4][3];
+            for (int j = 0; j < 4; ++j)
+                for (int c = 0; c < 3; ++c) {
+                    v[j][c] = X[3 * (int64_t)id[j] + c];
+                    w[j][c] = W[3 * (int64_t)id[j] + c];
+                }
+            double e[3][3];
+            for (int j = 0; j < 3; ++j)
+                for (int c = 0; c < 3; ++c) e[j][c] = v[j + 1][c] - v[0][c];
+            const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                               e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                               e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+            const double vol = std::fabs(det) / 6.0;
+            auto put = [&](const TetRule &r, float *dst) {
+                for (int q = 0; q < r.n; ++q) {
+                    double p[3] = {0, 0, 0}, o[3] = {0, 0, 0};
+                    for (int j = 0; j < 4; ++j)
+                        for (int c = 0; c < 3; ++c) {
+                            p[c] += r.lam[q][j] * v[j][c];
+                            o[c] += r.lam[q][j] * w[j][c];
+                        }
+                    const double f = r.w[q] * vol / (4.0 * M_PI);
+                    for (int c = 0; c < 3; ++c) {
+                        dst[8 * q + c] = (float)p[c];
+                        dst[8 * q + 3 + c] = (float)(f * o[c]);
+                    }
+                    dst[8 * q + 6] = 0.f;
+                    dst[8 * q + 7] = 0.f;
+                }
+            };
+            put(R1, &g1[(size_t)k * 8]);
+            // the 1-point rule sits at the centroid used for the rule decision
+            for (int c = 0; c < 3; ++c) g1[(size_t)k * 8 + c] = cen32[(size_t)(3 * t + c)];
+            put(R4, &g4[(size_t)k * 32]);
+            put(R11, &g11[(size_t)k * 88]);
+            tid[(size_t)k] = make_int4(rank[(size_t)id[0]], rank[(size_t)id[1]], rank[(size_t)id[2]],
+                                       rank[(size_t)id[3]]);
+        }
+    });
+
+    // ---- upload
+    int rc;
+    const size_t nb = sizeof(float) * 3 * (size_t)npad;
+    if ((rc = dalloc(m->xh, nb)) || (rc = dalloc(m->xl, nb)) || (rc = dalloc(m->om, nb)) ||
+        (rc = dalloc(m->blk, sizeof(float4) * (size_t)nblk)) || (rc = dalloc(m->node_orig, 4 * (size_t)n)) ||
+        (rc = dalloc(m->g1, 4 * g1.size())) || (rc = dalloc(m->g4, 4 * g4.size())) ||
+        (rc = dalloc(m->g11, 4 * g11.size())) || (rc = dalloc(m->tid, sizeof(int4) * (size_t)T)) ||
+        (rc = dalloc(m->cell_start, 4 * cell_start.size())) || (rc = dalloc(m->band, 8 * 3 * (size_t)npad)) ||
+        (rc = dalloc(m->rtv, 8 * 3 * (size_t)npad)) || (rc = dalloc(m->vel, 8 * 3 * (size_t)n)) ||
+        (rc = dalloc(m->cnt, 8 * bsk::kNumCounters)) || (rc = dalloc(m->nonfinite, 4)))
+        return rc;
+    hipError_t e;
+#define BS_UP(buf, vec)                                                                                            \
+    if (!(vec).empty() &&                                                                                          \
+        (e = hipMemcpyAsync(m->buf.p, (vec).data(), sizeof((vec)[0]) * (vec).size(), hipMemcpyHostToDevice, s)) != \
+            hipSuccess)                                                                                            \
+        return hip_fail(e, "upload " #buf);
+    BS_UP(xh, xh)
+    BS_UP(xl, xl)
+    BS_UP(om, om)
+    BS_UP(blk, blk)
+    BS_UP(node_orig, orig)
+    BS_UP(g1, g1)
+    BS_UP(g4, g4)
+    BS_UP(g11, g11)
+    BS_UP(tid, tid)
+    BS_UP(cell_start, cell_start)
+#undef BS_UP
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "upload");
+    return BS_OK;
+}
+
+int read_inputs(bs_mesh *m, const double *xyz, const double *omega, uint32_t flags, hipStream_t s)
+{
+    const size_t bytes = sizeof(double) * 3 * (size_t)m->n;
+    if (flags & BS_PTR_DEVICE) {
+        hipError_t e;
+        if (xyz && (e = hipMemcpyAsync(m->xyz.data(), xyz, bytes, hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return hip_fail(e, "read xyz");
+        if (omega && (e = hipMemcpyAsync(m->omega.data(), omega, bytes, hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return hip_fail(e, "read omega");
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "read inputs");
+    } else {
+        if (xyz) std::memcpy(m->xyz.data(), xyz, bytes);
+        if (omega) std::memcpy(m->omega.data(), omega, bytes);
+    }
+    return BS_OK;
+}
+
+int install_angular(bs_mesh *m)
+{
+    const int N = m->pol.n_phi, M = m->pol.n_theta;
+    if (N == m->ang_N && M == m->ang_M) return BS_OK;
+    std::vector<double> tn, wn, tm, wm;
+    gauss_legendre(N, tn, wn);
+    gauss_legendre(M, tm, wm);
+    const int M2 = 2 * M;
+    std::vector<float4> dir((size_t)N * M2);
+    std::vector<double> dir64((size_t)N * M2 * 3);
+    std::vector<float> cphi((size_t)N), dia((size_t)M2);
+    for (int n = 0; n < N; ++n) cphi[(size_t)n] = (float)std::cos((1.0 + tn[(size_t)n]) * M_PI / 2.0);
+    for (int j = 0; j < M2; ++j) {
+        const double th = (1.0 + tm[(size_t)(j % M)]) * M_PI / 2.0 + (j >= M ? M_PI : 0.0);
+        const float c = (float)std::cos(th), s = (float)std::sin(th);
+        float d;
+        if (s >= 0.f) d = c >= 0.f ? s / (c + s) : 1.f - c / (-c + s);
+        else d = c < 0.f ? 2.f - s / (-c - s) : 3.f + c / (c - s);
+        dia[(size_t)j] = d;
+    }
+    for (int n = 0; n < N; ++n)
+        for (int j = 0; j < M2; ++j) {
+            // ray (n, j): line (n, j) for j < M; the reverse of line (N-1-n, j-M) otherwise
+            const bool rev = j >= M;
+            const int ln = rev ? N - 1 - n : n, lm = rev ? j - M : j;
+            const double phi = (1.0 + tn[(size_t)ln]) * M_PI / 2.0;
+            const double th = (1.0 + tm[(size_t)lm]) * M_PI / 2.0;
+            const double sg = rev ? -1.0 : 1.0;
+            const double d[3] = {sg * std::sin(phi) * std::cos(th), sg * std::sin(phi) * std::sin(th),
+                                 sg * std::cos(phi)};
+            const double k = M_PI / 16.0 * std::sin(phi) * wn[(size_t)ln] * wm[(size_t)lm];
+            const size_t l = (size_t)n * M2 + j;
+            dir[l] = make_float4((float)d[0], (float)d[1], (float)d[2], (float)k);
+            for (int c = 0; c < 3; ++c) dir64[3 * l + c] = d[c];
+        }
+    int rc;
+    if ((rc = dalloc(m->dir, sizeof(float4) * dir.size())) || (rc = dalloc(m->dir64, 8 * dir64.size())) ||
+        (rc = dalloc(m->cphi, 4 * cphi.size())) || (rc = dalloc(m->dia, 4 * dia.size())))
+        return rc;
+    hipError_t e;
+    if ((e = hipMemcpy(m->dir.p, dir.data(), sizeof(float4) * dir.size(), hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(m->dir64.p, dir64.data(), 8 * dir64.size(), hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(m->cphi.p, cphi.data(), 4 * cphi.size(), hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(m->dia.p, dia.data(), 4 * dia.size(), hipMemcpyHostToDevice)))
+        return hip_fail(e, "upload angular tables");
+    m->ang_N = N;
+    m->ang_M = M;
+    return BS_OK;
+}
+
+bsk::DevMesh dev_view(const bs_mesh *m)
+{
+    bsk::DevMesh d{};
+    d.n = (int)m->n;
+    d.npad = m->npad;
+    d.T = (int)m->T;
+    d.nblk = m->nblk;
+    d.xh = (const float *)m->xh.p;
+    d.xl = (const float *)m->xl.p;
+    d.om = (const float *)m->om.p;
+    d.blk = (const float4 *)m->blk.p;
+    d.g1 = (const float *)m->g1.p;
+    d.g4 = (const float *)m->g4.p;
+    d.g11 = (const float *)m->g11.p;
+    d.tid = (const int4 *)m->tid.p;
+    d.cell_start = (const int *)m->cell_start.p;
+    d.bins = m->bins;
+    return d;
+}
+
+int check_policy(const bs_policy *p)
+{
+    if (p->kind < BS_POLICY_FIXED || p->kind > BS_POLICY_LEARNED)
+        return fail(BS_E_POLICY, "unknown policy kind %d", p->kind);
+    if (p->n_phi < 1 || p->n_phi > 256 || p->n_theta < 1 || p->n_theta > 256)
+        return fail(BS_E_POLICY, "angular orders must lie in [1, 256] (got %d, %d)", p->n_phi, p->n_theta);
+    if (!(p->near_cut > 0) || !(p->d_g11 >= p->near_cut) || !(p->d_g4 >= p->d_g11) || !std::isfinite(p->d_g4))
+        return fail(BS_E_POLICY, "cut distances must satisfy 0 < near_cut <= d_g11 <= d_g4 < inf");
+    if (p->kind == BS_POLICY_GAUSS_ONLY && (p->gauss_rule < BS_RULE_G1 || p->gauss_rule > BS_RULE_G11))
+        return fail(BS_E_POLICY, "gauss_rule must be BS_RULE_G1, _G4 or _G11");
+    if (p->precision < BS_PREC_FP32_NAIVE || p->precision > BS_PREC_FP64)
+        return fail(BS_E_POLICY, "unknown precision %d", p->precision);
+    if (p->kind == BS_POLICY_LEARNED)
+        return fail(BS_E_POLICY, "the learned policy needs the network entry points");
+    return BS_OK;
+}
+
+} // namespace
+
+// =============================================================== public ABI
+extern "C" {
+
+void bs_policy_default(bs_policy *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->kind = BS_POLICY_FIXED;
+    p->n_phi = 16;
+    p->n_theta = 16;
+    p->near_cut = 2.0;
+    p->d_g11 = 4.0;
+    p->d_g4 = 8.0;
+    p->gauss_rule = BS_RULE_G1;
+    p->precision = BS_PREC_FP32_COMP;
+    p->conf_min = 0.9f;
+}
+
+const char *bs_status_string(int s)
+{
+    switch (s) {
+    case BS_OK: return "ok";
+    case BS_E_ARG: return "invalid argument";
+    case BS_E_INDEX: return "node index out of range or repeated within a tetrahedron";
+    case BS_E_DEGENERATE: return "zero-volume tetrahedron";
+    case BS_E_NONFINITE: return "non-finite input";
+    case BS_E_STATE: return "call out of order";
+    case BS_E_DEVICE: return "device or runtime failure";
+    case BS_E_NOMEM: return "out of memory";
+    case BS_E_POLICY: return "invalid policy";
+    default: return "unknown status";
+    }
+}
+
+const char *bs_last_error(void) { return g_err.c_str(); }
+
+int bs_mesh_upload(const bs_mesh_desc *d, bs_mesh **out)
+{
+    g_err.clear();
+    if (!d || !out) return fail(BS_E_ARG, "null descriptor or output pointer");
+    *out = nullptr;
+    if (d->n_nodes < 1 || d->n_tets < 0) return fail(BS_E_ARG, "n_nodes must be >= 1 and n_tets >= 0");
+    if (!d->xyz || !d->omega || (d->n_tets > 0 && !d->tets)) return fail(BS_E_ARG, "null input array");
+    if (d->flags & ~BS_PTR_DEVICE) return fail(BS_E_ARG, "unknown flags 0x%x", d->flags);
+    if (d->n_nodes > (int64_t)1 << 30 || d->n_tets > (int64_t)1 << 30)
+        return fail(BS_E_ARG, "mesh too large for 32-bit indexing");
+    // device inputs need the device before anything can be validated
+    int dev = -1, rc;
+    if ((d->flags & BS_PTR_DEVICE) && (rc = check_device(&dev))) return rc;
+    bs_mesh *m = new (std::nothrow) bs_mesh();
+    if (!m) return fail(BS_E_NOMEM, "host allocation");
+    m->n = d->n_nodes;
+    m->T = d->n_tets;
+    hipStream_t s = (hipStream_t)d->stream;
+    try {
+        m->tets.resize((size_t)(4 * m->T));
+        m->xyz.resize((size_t)(3 * m->n));
+        m->omega.resize((size_t)(3 * m->n));
+    } catch (...) {
+        delete m;
+        return fail(BS_E_NOMEM, "host allocation");
+    }
+    if (d->flags & BS_PTR_DEVICE) {
+        hipError_t e = m->T > 0 ? hipMemcpy(m->tets.data(), d->tets, 16 * (size_t)m->T, hipMemcpyDeviceToHost)
+                                : hipSuccess;
+        if (e != hipSuccess) {
+            delete m;
+            return hip_fail(e, "read tets");
+        }
+    } else if (m->T > 0) {
+        std::memcpy(m->tets.data(), d->tets, 16 * (size_t)m->T);
+    }
+    for (int64_t t = 0; t < m->T; ++t) {
+        const int32_t *id = &m->tets[(size_t)(4 * t)];
+        for (int j = 0; j < 4; ++j) {
+            if (id[j] < 0 || id[j] >= m->n) {
+                delete m;
+                return fail(BS_E_INDEX, "tetrahedron %lld: node index %d outside [0, %lld)", (long long)t, id[j],
+                            (long long)m->n);
+            }
+            for (int k = 0; k < j; ++k)
+                if (id[k] == id[j]) {
+                    delete m;
+                    return fail(BS_E_INDEX, "tetrahedron %lld repeats node %d", (long long)t, id[j]);
+                }
+        }
+    }
+    if ((rc = read_inputs(m, d->xyz, d->omega, d->flags, s)) || (rc = validate_geometry(m))) {
+        delete m;
+        return rc;
+    }
+    if (dev < 0 && (rc = check_device(&dev))) {
+        delete m;
+        return rc;
+    }
+    m->device = dev;
+    if ((rc = build_device_mesh(m, s))) {
+        bs_mesh_free(m);
+        return rc;
+    }
+    bs_policy_default(&m->pol);
+    for (auto &e : m->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            bs_mesh_free(m);
+            return fail(BS_E_DEVICE, "hipEventCreate");
+        }
+    *out = m;
+    return BS_OK;
+}
+
+int bs_mesh_update(bs_mesh *m, const double *xyz, const double *omega, uint32_t flags, void *stream)
+{
+    g_err.clear();
+    if (!m) return fail(BS_E_STATE, "null mesh");
+    if (flags & ~BS_PTR_DEVICE) return fail(BS_E_ARG, "unknown flags 0x%x", flags);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<double> keep_x = m->xyz, keep_w = m->omega;
+    int rc;
+    if ((rc = read_inputs(m, xyz, omega, flags, s)) || (rc = validate_geometry(m))) {
+        m->xyz.swap(keep_x);
+        m->omega.swap(keep_w);
+        return rc;
+    }
+    return build_device_mesh(m, s);
+}
+
+void bs_mesh_free(bs_mesh *m)
+{
+    if (!m) return;
+    DBuf *bufs[] = {&m->xh, &m->xl, &m->om, &m->blk, &m->node_orig, &m->g1, &m->g4, &m->g11, &m->tid,
+                    &m->cell_start, &m->part, &m->band, &m->rtv, &m->vel, &m->cnt, &m->nonfinite, &m->dir,
+                    &m->dir64, &m->cphi, &m->dia};
+    for (DBuf *b : bufs) dfree(*b);
+    for (auto &e : m->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete m;
+}
+
+int bs_set_policy(bs_mesh *m, const bs_policy *p)
+{
+    g_err.clear();
+    if (!m) return fail(BS_E_STATE, "null mesh");
+    if (!p) return fail(BS_E_ARG, "null policy");
+    int rc = check_policy(p);
+    if (rc) return rc;
+    m->pol = *p;
+    m->pol.mlp_bf16 = nullptr;
+    return BS_OK;
+}
+
+int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, bs_stats *st)
+{
+    g_err.clear();
+    if (!m) return fail(BS_E_STATE, "null mesh");
+    if (!vel) return fail(BS_E_ARG, "null output");
+    if (vel_flags & ~BS_PTR_DEVICE) return fail(BS_E_ARG, "unknown flags 0x%x", vel_flags);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = install_angular(m);
+    if (rc) return rc;
+    const bs_policy &P = m->pol;
+    bsk::DevMesh dm = dev_view(m);
+
+    // tet splits of the all-pairs Gauss kernel: enough waves to fill 256 CUs
+    const int node_blocks = m->npad / 1024;
+    int splits = 0;
+    const bool gauss_all = P.kind == BS_POLICY_FIXED || P.kind == BS_POLICY_GAUSS_ONLY;
+    if (gauss_all && m->T > 0) {
+        splits = std::max(1, std::min<int>((int)((4096 + 4 * node_blocks - 1) / (4 * node_blocks)),
+                                           (int)((m->T + 255) / 256)));
+        if ((rc = dalloc(m->part, 8 * 3 * (size_t)m->npad * splits))) return rc;
+    }
+    bsk::Thresholds th{};
+    const double hb = m->hbar;
+    const double c_rt = P.near_cut * hb, c_11 = P.d_g11 * hb, c_4 = P.d_g4 * hb;
+    th.rt2 = (float)(c_rt * c_rt);
+    th.g11_2 = (float)(c_11 * c_11);
+    th.g4_2 = (float)(c_4 * c_4);
+    th.r_band = (float)(std::max(c_4, m->max_vc) * (1.0 + 1e-4) + 1e-6);
+    th.r_rt = (float)(std::max(c_rt, m->max_vc) * (1.0 + 1e-4) + 1e-6);
+    bsk::AngTab ang{};
+    ang.dir = (const float4 *)m->dir.p;
+    ang.dir64 = (const double *)m->dir64.p;
+    ang.cphi = (const float *)m->cphi.p;
+    ang.dia = (const float *)m->dia.p;
+    ang.N = P.n_phi;
+    ang.M2 = 2 * P.n_theta;
+
+    hipError_t e;
+    unsigned long long *cnt = (unsigned long long *)m->cnt.p;
+    if ((e = hipMemsetAsync(m->cnt.p, 0, 8 * bsk::kNumCounters, s)) ||
+        (e = hipMemsetAsync(m->nonfinite.p, 0, 4, s)))
+        return hip_fail(e, "clear counters");
+    const double *part = nullptr, *band = nullptr, *rtv = nullptr;
+    (void)hipEventRecord(m->ev[0], s);
+    if (m->T > 0) {
+        if (P.kind == BS_POLICY_GAUSS_ONLY) {
+            const int pts = P.gauss_rule == BS_RULE_G1 ? 1 : P.gauss_rule == BS_RULE_G4 ? 4 : 11;
+            if ((e = bsk::launch_gauss_all(dm, pts, P.precision, splits, (double *)m->part.p, s)))
+                return hip_fail(e, "gauss kernel");
+            part = (const double *)m->part.p;
+        } else if (P.kind == BS_POLICY_FIXED) {
+            if ((e = bsk::launch_gauss_all(dm, 1, P.precision, splits, (double *)m->part.p, s)))
+                return hip_fail(e, "far-field kernel");
+            part = (const double *)m->part.p;
+        }
+    }
+    (void)hipEventRecord(m->ev[1], s);
+    if (m->T > 0 && P.kind == BS_POLICY_FIXED) {
+        if ((e = bsk::launch_band(dm, th, P.precision, (double *)m->band.p, cnt, s)))
+            return hip_fail(e, "band kernel");
+        band = (const double *)m->band.p;
+    }
+    (void)hipEventRecord(m->ev[2], s);
+    if (m->T > 0 && (P.kind == BS_POLICY_FIXED || P.kind == BS_POLICY_PURE_RT)) {
+        if ((e = bsk::launch_rt(dm, th, ang, P.kind == BS_POLICY_PURE_RT, P.precision, (double *)m->rtv.p, cnt, s)))
+            return hip_fail(e, "ray-tracing kernel");
+        rtv = (const double *)m->rtv.p;
+    }
+    (void)hipEventRecord(m->ev[3], s);
+    if ((e = bsk::launch_combine(dm, (const int *)m->node_orig.p, part, part ? splits : 0, band, rtv,
+                                 (double *)m->vel.p, (int *)m->nonfinite.p, s)))
+        return hip_fail(e, "combine kernel");
+    (void)hipEventRecord(m->ev[4], s);
+    const size_t vbytes = 8 * 3 * (size_t)m->n;
+    e = hipMemcpyAsync(vel, m->vel.p, vbytes, (vel_flags & BS_PTR_DEVICE) ? hipMemcpyDeviceToDevice
+                                                                          : hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "copy velocity");
+    if (!(vel_flags & BS_PTR_DEVICE) || st) {
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "evaluation");
+    }
+    if (st) {
+        unsigned long long c[bsk::kNumCounters];
+        int nf = 0;
+        if ((e = hipMemcpy(c, m->cnt.p, sizeof c, hipMemcpyDeviceToHost)) ||
+            (e = hipMemcpy(&nf, m->nonfinite.p, 4, hipMemcpyDeviceToHost)))
+            return hip_fail(e, "read counters");
+        std::memset(st, 0, sizeof *st);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, m->ev[0], m->ev[4]);
+        st->t_eval_s = ms * 1e-3;
+        for (int k = 0; k < 4; ++k) {
+            float mk = 0.f;
+            (void)hipEventElapsedTime(&mk, m->ev[k], m->ev[k + 1]);
+            st->t_kernel_s[k] = mk * 1e-3;
+        }
+        st->pairs = m->n * m->T;
+        if (P.kind == BS_POLICY_FIXED) {
+            st->pairs_by_rule[BS_RULE_G4] = (int64_t)c[0];
+            st->pairs_by_rule[BS_RULE_G11] = (int64_t)c[1];
+            st->pairs_by_rule[BS_RULE_RT] = (int64_t)c[2];
+            st->pairs_by_rule[BS_RULE_G1] = st->pairs - (int64_t)(c[0] + c[1] + c[2]);
+        } else if (P.kind == BS_POLICY_PURE_RT) {
+            st->pairs_by_rule[BS_RULE_RT] = st->pairs;
+        } else {
+            st->pairs_by_rule[P.gauss_rule] = st->pairs;
+        }
+        st->rt_hit_lines = (int64_t)c[3];
+        st->fp64_retests = (int64_t)c[4];
+        st->reoriented = m->reoriented;
+        st->nonfinite_out = nf;
+        st->hbar = m->hbar;
+    }
+    return BS_OK;
+}
+
+} // extern "C"

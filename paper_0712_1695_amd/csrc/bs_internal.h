@@ -1,0 +1,78 @@
+// bs_internal.h -- device data layout and kernel launch interface of the
+// Biot-Savart node-velocity library (shared by bs_host.cpp and
+// bs_kernels.hip; not part of the public ABI).
+//
+// Layout in HBM (all arrays owned by one bs_mesh):
+//   nodes, sorted along a Morton curve (spatially coherent waves):
+//     xh[3][npad], xl[3][npad]  binary32 hi/lo split of the FP64 coordinates
+//                               (x = xh + xl to ~2^-48 relative)
+//     om[3][npad]               nodal vorticity, binary32
+//     blk[nblk]                 per 64-node block: bounding-sphere centre, radius
+//   tetrahedra, sorted by spatial bin of the centroid:
+//     g1[T][8]    1-point rule: centroid p, strength W = |T| omega(p) / 4pi, pad
+//     g4[T][4][8] 4-point rule: p_q, W_q = w_q |T| omega(p_q) / 4pi, pad
+//     g11[T][11][8] 11-point rule, same record
+//     tid[T]      the four vertex indices (sorted-node numbering), input order
+//     cell_start[ncell + 1] first tet of every bin (bins in x-fastest order)
+//   angular tables (per policy): one entry per ray of the full sphere,
+//     index l = n * 2M + j (polar row n, azimuth column j in [0, 2M)):
+//     dir[l] = (d.xyz, kappa) binary32, dir64[l][3] FP64 directions,
+//     cphi[N] cos(polar angle) per row, dia[2M] pseudo-angle per column.
+//   outputs: part[S][3][npad] FP64 far-field partials per tet split,
+//            band[3][npad], rtv[3][npad] FP64 near partials, vel[n][3].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bsk {
+
+constexpr int kRecG = 8;        // floats per Gauss point record
+constexpr int kBlockNodes = 64; // nodes per band-kernel block (one wave)
+
+struct Bins {
+    float lo[3];   // lower corner of the bin grid
+    float cs;      // bin edge length
+    int dim[3];    // bins per axis
+    int pad;
+};
+
+struct Thresholds {
+    float rt2, g11_2, g4_2; // squared cut distances, binary32
+    float r_band;           // scan radius of the band kernel (>= d_g4 hbar, max vertex-centroid distance)
+    float r_rt;             // scan radius of the ray-tracing kernel
+};
+
+struct AngTab {
+    const float4 *dir;    // [N * 2M] direction + kappa
+    const double *dir64;  // [N * 2M][3]
+    const float *cphi;    // [N] cos(phi_n), descending
+    const float *dia;     // [2M] pseudo-angle of theta'_j, ascending in [0, 4)
+    int N, M2;            // rows, columns (2M)
+};
+
+struct DevMesh {
+    int n, npad, T, nblk;
+    const float *xh, *xl, *om;
+    const float4 *blk;
+    const float *g1, *g4, *g11;
+    const int4 *tid;
+    const int *cell_start;
+    Bins bins;
+};
+
+// Counters accumulated by the kernels (device, 64-bit):
+// [0] G4 pairs, [1] G11 pairs, [2] RT pairs, [3] RT hit lines, [4] FP64 retests
+constexpr int kNumCounters = 8;
+
+// Launchers (return hipSuccess or the launch error).
+hipError_t launch_gauss_all(const DevMesh &m, int rule_pts, int precision, int splits, double *part,
+                            hipStream_t s);
+hipError_t launch_band(const DevMesh &m, const Thresholds &th, int precision, double *band,
+                       unsigned long long *cnt, hipStream_t s);
+hipError_t launch_rt(const DevMesh &m, const Thresholds &th, const AngTab &ang, int all_pairs, int precision,
+                     double *rtv, unsigned long long *cnt, hipStream_t s);
+hipError_t launch_combine(const DevMesh &m, const int *node_orig, const double *part, int splits,
+                          const double *band, const double *rtv, double *vel, int *nonfinite, hipStream_t s);
+
+} // namespace bsk

@@ -1,0 +1,940 @@
+// bs_kernels.hip -- gfx950 kernels of the Biot-Savart node-velocity library.
+//
+// Velocity at node x from tetrahedron T (eq. 1 of Carley, "Evaluation of
+// Biot-Savart integrals on tetrahedral meshes"):
+//   v(x) = -(1/4pi) int_T (x - y) x omega(y) / |x - y|^3 dV
+// Far pairs: a symmetric Gauss rule, v += sum_q (W_q x r_q) / |r_q|^3 with
+// r_q = x - p_q and W_q = w_q |T| omega(p_q) / 4pi (the standard approach the
+// Introduction names for distant elements).
+// Near pairs: ray tracing (Section 2.1).  Every line of the N x M angular
+// rule is split at x into two rays d = +-s; a ray that crosses T between
+// distances rho_near < rho_far contributes
+//   kappa * (rho_far - rho_near)/2 * d x (omega_near + omega_far),
+// which is eq. 5 with the sign of R restored (the integrand of eq. 2 on the
+// full line is sgn(R) s x omega).  The face crossings are the
+// Moller-Trumbore intersections; they are computed from signed volumes of
+// the ray with the tet edges, one value per edge shared by the two faces
+// (and the neighbouring tets) that contain the edge, so a ray is never
+// counted as entering without leaving.
+//
+// Fixed rule per pair, decided in binary32 exactly as the CPU reference
+// decides it: d^2 = ((dx*dx + dy*dy) + dz*dz) from the binary32 node and
+// centroid coordinates against the squared cut distances; a tetrahedron
+// having the node as a vertex is always ray traced.
+//
+// Kernels:
+//   k_gauss_all  every pair by one Gauss rule (G1 for the fixed policy:
+//                the far field of all pairs), tet records wave-uniform;
+//   k_band       per 64-node block: for pairs whose fixed rule is not G1,
+//                remove the G1 term and add the G4 / G11 one;
+//   k_rt         one wave per node: ray tracing of its near tetrahedra;
+//   k_combine    FP64 sum of the partials, back to input node order.
+#include "bs_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace bsk {
+
+#define RULE_G1 0
+#define RULE_G4 1
+#define RULE_G11 2
+#define RULE_RT 3
+
+// Fold a into the compensated pair (s, c) (Knuth's TwoSum).
+__device__ __forceinline__ void two_sum(float &s, float &c, float a)
+{
+    const float t = s + a;
+    const float bp = t - s;
+    const float err = (s - (t - bp)) + (a - bp);
+    s = t;
+    c += err;
+}
+
+// Rule of the pair (node `self` at (x, y, z), tetrahedron with centroid c
+// and vertex ids id) under the fixed distance policy.  Every operation is
+// rounded separately (the file is built without FP contraction).
+__device__ __forceinline__ int fixed_rule(float x, float y, float z, float cx, float cy, float cz, int4 id,
+                                          int self, const Thresholds &th)
+{
+    if (id.x == self || id.y == self || id.z == self || id.w == self) return RULE_RT;
+    const float dx = x - cx, dy = y - cy, dz = z - cz;
+    const float sx = dx * dx, sy = dy * dy, sz = dz * dz;
+    const float d2 = (sx + sy) + sz;
+    if (d2 < th.rt2) return RULE_RT;
+    if (d2 < th.g11_2) return RULE_G11;
+    if (d2 < th.g4_2) return RULE_G4;
+    return RULE_G1;
+}
+
+// One Gauss point: acc += (W x r) / |r|^3, r = x - p.
+__device__ __forceinline__ void gauss_point(float x, float y, float z, const float *g, float &ax, float &ay,
+                                            float &az)
+{
+    const float rx = x - g[0], ry = y - g[1], rz = z - g[2];
+    const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
+    const float inv = __builtin_amdgcn_rsqf(r2);
+    const float inv3 = inv * inv * inv;
+    const float ux = rx * inv3, uy = ry * inv3, uz = rz * inv3;
+    ax = fmaf(g[4], uz, fmaf(-g[5], uy, ax));
+    ay = fmaf(g[5], ux, fmaf(-g[3], uz, ay));
+    az = fmaf(g[3], uy, fmaf(-g[4], ux, az));
+}
+
+// NPL nodes against one Gauss point, written in phases (differences, squared
+// distances, reciprocal square roots, then the products) so that the NPL
+// independent chains interleave.
+template <int NPL>
+__device__ __forceinline__ void gauss_point_n(const float *x, const float *y, const float *z, const float *g,
+                                              float *ax, float *ay, float *az)
+{
+    const float px = g[0], py = g[1], pz = g[2], wx = g[3], wy = g[4], wz = g[5];
+    float rx[NPL], ry[NPL], rz[NPL], iv[NPL];
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+        rx[k] = x[k] - px;
+        ry[k] = y[k] - py;
+        rz[k] = z[k] - pz;
+        iv[k] = fmaf(rx[k], rx[k], fmaf(ry[k], ry[k], rz[k] * rz[k]));
+    }
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) iv[k] = __builtin_amdgcn_rsqf(iv[k]);
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+        const float inv3 = iv[k] * iv[k] * iv[k];
+        const float ux = rx[k] * inv3, uy = ry[k] * inv3, uz = rz[k] * inv3;
+        ax[k] = fmaf(wy, uz, fmaf(-wz, uy, ax[k]));
+        ay[k] = fmaf(wz, ux, fmaf(-wx, uz, ay[k]));
+        az[k] = fmaf(wx, uy, fmaf(-wy, ux, az[k]));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Every pair by the NPTS-point rule.  Block = 256 lanes x NPL nodes;
+// blockIdx.y = split of the tet range.  The tet loop index is uniform across
+// the wave, so the point records are fetched by scalar loads and used as
+// scalar operands.  PREC: 0 naive FP32, 1 TwoSum-compensated FP32 tiles,
+// 2 FP64 accumulation.
+template <int NPTS, int NPL, int PREC>
+__global__ void __launch_bounds__(256) k_gauss_all(const float *__restrict__ xh, int npad,
+                                                   const float *__restrict__ rec, int T, int per_split,
+                                                   double *__restrict__ part)
+{
+    constexpr int kTile = 32;
+    const int t0 = blockIdx.y * per_split;
+    const int t1 = min(T, t0 + per_split);
+    const int base = blockIdx.x * (256 * NPL) + threadIdx.x;
+    float x[NPL], y[NPL], z[NPL];
+    float ax[NPL], ay[NPL], az[NPL];
+    float sx[NPL], sy[NPL], sz[NPL], cx[NPL], cy[NPL], cz[NPL];
+    double dx[NPL], dy[NPL], dz[NPL];
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+        const int i = base + 256 * k;
+        x[k] = xh[i];
+        y[k] = xh[npad + i];
+        z[k] = xh[2 * npad + i];
+        ax[k] = ay[k] = az[k] = 0.f;
+        sx[k] = sy[k] = sz[k] = cx[k] = cy[k] = cz[k] = 0.f;
+        dx[k] = dy[k] = dz[k] = 0.0;
+    }
+    if (PREC == 0) {
+#pragma unroll 2
+        for (int t = t0; t < t1; ++t) {
+            const float *g = rec + (size_t)t * (NPTS * kRecG);
+#pragma unroll
+            for (int q = 0; q < NPTS; ++q) gauss_point_n<NPL>(x, y, z, g + q * kRecG, ax, ay, az);
+        }
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) {
+            sx[k] = ax[k];
+            sy[k] = ay[k];
+            sz[k] = az[k];
+        }
+    } else {
+        for (int tb = t0; tb < t1; tb += kTile) {
+            const int te = min(tb + kTile, t1);
+#pragma unroll
+            for (int k = 0; k < NPL; ++k) ax[k] = ay[k] = az[k] = 0.f;
+#pragma unroll 2
+            for (int t = tb; t < te; ++t) {
+                const float *g = rec + (size_t)t * (NPTS * kRecG);
+#pragma unroll
+                for (int q = 0; q < NPTS; ++q) gauss_point_n<NPL>(x, y, z, g + q * kRecG, ax, ay, az);
+            }
+#pragma unroll
+            for (int k = 0; k < NPL; ++k) {
+                if (PREC == 1) {
+                    two_sum(sx[k], cx[k], ax[k]);
+                    two_sum(sy[k], cy[k], ay[k]);
+                    two_sum(sz[k], cz[k], az[k]);
+                } else {
+                    dx[k] += (double)ax[k];
+                    dy[k] += (double)ay[k];
+                    dz[k] += (double)az[k];
+                }
+            }
+        }
+    }
+    double *o = part + (size_t)blockIdx.y * 3 * npad;
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+        const int i = base + 256 * k;
+        if (PREC == 2) {
+            o[i] = dx[k];
+            o[npad + i] = dy[k];
+            o[2 * npad + i] = dz[k];
+        } else {
+            o[i] = (double)sx[k] + (double)cx[k];
+            o[npad + i] = (double)sy[k] + (double)cy[k];
+            o[2 * npad + i] = (double)sz[k] + (double)cz[k];
+        }
+    }
+}
+
+// The PREC == 2 variant above accumulates FP32 tile sums in FP64; the
+// per-term FP64 variant (every pair term converted and added in FP64) is
+// this one, used for BS_PREC_FP64.
+template <int NPTS, int NPL>
+__global__ void __launch_bounds__(256) k_gauss_all_f64(const float *__restrict__ xh, int npad,
+                                                       const float *__restrict__ rec, int T, int per_split,
+                                                       double *__restrict__ part)
+{
+    const int t0 = blockIdx.y * per_split;
+    const int t1 = min(T, t0 + per_split);
+    const int base = blockIdx.x * (256 * NPL) + threadIdx.x;
+    float x[NPL], y[NPL], z[NPL];
+    double dx[NPL], dy[NPL], dz[NPL];
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+        const int i = base + 256 * k;
+        x[k] = xh[i];
+        y[k] = xh[npad + i];
+        z[k] = xh[2 * npad + i];
+        dx[k] = dy[k] = dz[k] = 0.0;
+    }
+    for (int t = t0; t < t1; ++t) {
+        const float *g = rec + (size_t)t * (NPTS * kRecG);
+#pragma unroll
+        for (int q = 0; q < NPTS; ++q)
+#pragma unroll
+            for (int k = 0; k < NPL; ++k) {
+                float a = 0.f, b = 0.f, c = 0.f;
+                gauss_point(x[k], y[k], z[k], g + q * kRecG, a, b, c);
+                dx[k] += (double)a;
+                dy[k] += (double)b;
+                dz[k] += (double)c;
+            }
+    }
+    double *o = part + (size_t)blockIdx.y * 3 * npad;
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+        const int i = base + 256 * k;
+        o[i] = dx[k];
+        o[npad + i] = dy[k];
+        o[2 * npad + i] = dz[k];
+    }
+}
+
+constexpr int kNpl = 4;
+
+template <int NPTS>
+static hipError_t launch_gauss_pts(const DevMesh &m, int precision, int splits, double *part, hipStream_t s)
+{
+    const int per = (m.T + splits - 1) / splits;
+    dim3 grid(m.npad / (256 * kNpl), splits);
+    if (precision == 0)
+        hipLaunchKernelGGL((k_gauss_all<NPTS, kNpl, 0>), grid, dim3(256), 0, s, m.xh, m.npad, NPTS == 1 ? m.g1
+                           : NPTS == 4 ? m.g4 : m.g11, m.T, per, part);
+    else if (precision == 1)
+        hipLaunchKernelGGL((k_gauss_all<NPTS, kNpl, 1>), grid, dim3(256), 0, s, m.xh, m.npad, NPTS == 1 ? m.g1
+                           : NPTS == 4 ? m.g4 : m.g11, m.T, per, part);
+    else
+        hipLaunchKernelGGL((k_gauss_all_f64<NPTS, kNpl>), grid, dim3(256), 0, s, m.xh, m.npad, NPTS == 1 ? m.g1
+                           : NPTS == 4 ? m.g4 : m.g11, m.T, per, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauss_all(const DevMesh &m, int rule_pts, int precision, int splits, double *part,
+                            hipStream_t s)
+{
+    if (m.npad % (256 * kNpl)) return hipErrorInvalidValue;
+    if (rule_pts == 1) return launch_gauss_pts<1>(m, precision, splits, part, s);
+    if (rule_pts == 4) return launch_gauss_pts<4>(m, precision, splits, part, s);
+    if (rule_pts == 11) return launch_gauss_pts<11>(m, precision, splits, part, s);
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Rows of bins (fixed y, z; x range clipped to the ball) intersecting the
+// ball (c, R); next() yields the contiguous tet range of each row in turn.
+struct RowIter {
+    const DevMesh &m;
+    float cx, cy, cz, R, inv;
+    int iy, iz, iy0, iy1, iz1;
+    __device__ RowIter(const DevMesh &mm, float x, float y, float z, float r) : m(mm), cx(x), cy(y), cz(z), R(r)
+    {
+        inv = 1.0f / m.bins.cs;
+        iy0 = max(0, (int)floorf((cy - R - m.bins.lo[1]) * inv));
+        iy1 = min(m.bins.dim[1] - 1, (int)floorf((cy + R - m.bins.lo[1]) * inv));
+        iz = max(0, (int)floorf((cz - R - m.bins.lo[2]) * inv));
+        iz1 = min(m.bins.dim[2] - 1, (int)floorf((cz + R - m.bins.lo[2]) * inv));
+        iy = iy0;
+    }
+    __device__ __forceinline__ bool next(int &t0, int &t1)
+    {
+        for (; iz <= iz1; ++iz, iy = iy0) {
+            const float zl = m.bins.lo[2] + iz * m.bins.cs, zh = zl + m.bins.cs;
+            const float dz = cz < zl ? zl - cz : (cz > zh ? cz - zh : 0.f);
+            for (; iy <= iy1; ++iy) {
+                const float yl = m.bins.lo[1] + iy * m.bins.cs, yh = yl + m.bins.cs;
+                const float dy = cy < yl ? yl - cy : (cy > yh ? cy - yh : 0.f);
+                const float rem = R * R - dy * dy - dz * dz;
+                if (rem < 0.f) continue;
+                const float hw = sqrtf(rem);
+                const int ix0 = max(0, (int)floorf((cx - hw - m.bins.lo[0]) * inv));
+                const int ix1 = min(m.bins.dim[0] - 1, (int)floorf((cx + hw - m.bins.lo[0]) * inv));
+                if (ix0 > ix1) continue;
+                const int row = (iz * m.bins.dim[1] + iy) * m.bins.dim[0];
+                t0 = m.cell_start[row + ix0];
+                t1 = m.cell_start[row + ix1 + 1];
+                ++iy;
+                if (t0 < t1) return true;
+                --iy;
+            }
+        }
+        return false;
+    }
+};
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Band corrections.  One wave per 64 consecutive (Morton-ordered) nodes.
+// For every tet whose centroid lies within r_band of the block's bounding
+// sphere: lanes whose pair rule is not G1 subtract the G1 term added by
+// k_gauss_all, then lanes with G4 / G11 add that rule (ray-traced pairs are
+// added by k_rt).
+template <int PREC>
+__global__ void __launch_bounds__(64) k_band(DevMesh m, Thresholds th, double *__restrict__ band,
+                                             unsigned long long *__restrict__ cnt)
+{
+    const int lane = threadIdx.x;
+    const int i = blockIdx.x * kBlockNodes + lane;
+    const bool valid = i < m.n;
+    const float x = m.xh[i], y = m.xh[m.npad + i], z = m.xh[2 * m.npad + i];
+    const float4 bc = m.blk[blockIdx.x];
+    float sx = 0.f, sy = 0.f, sz = 0.f, ccx = 0.f, ccy = 0.f, ccz = 0.f;
+    double dx = 0.0, dy = 0.0, dz = 0.0;
+    unsigned long long n4 = 0, n11 = 0;
+    RowIter rows(m, bc.x, bc.y, bc.z, th.r_band + bc.w);
+    int t0, t1;
+    while (rows.next(t0, t1)) {
+        float ax = 0.f, ay = 0.f, az = 0.f;
+        for (int t = t0; t < t1; ++t) {
+            const float *g = m.g1 + (size_t)t * kRecG;
+            const int4 id = m.tid[t];
+            const int rule = valid ? fixed_rule(x, y, z, g[0], g[1], g[2], id, i, th) : RULE_G1;
+            if (rule != RULE_G1) {
+                float a = 0.f, b = 0.f, c = 0.f;
+                gauss_point(x, y, z, g, a, b, c);
+                ax -= a;
+                ay -= b;
+                az -= c;
+            }
+            if (rule == RULE_G4) {
+                const float *g4 = m.g4 + (size_t)t * 4 * kRecG;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) gauss_point(x, y, z, g4 + q * kRecG, ax, ay, az);
+                ++n4;
+            }
+            if (rule == RULE_G11) {
+                const float *g11 = m.g11 + (size_t)t * 11 * kRecG;
+#pragma unroll
+                for (int q = 0; q < 11; ++q) gauss_point(x, y, z, g11 + q * kRecG, ax, ay, az);
+                ++n11;
+            }
+        }
+        if (PREC == 1) {
+            two_sum(sx, ccx, ax);
+            two_sum(sy, ccy, ay);
+            two_sum(sz, ccz, az);
+        } else if (PREC == 2) {
+            dx += (double)ax;
+            dy += (double)ay;
+            dz += (double)az;
+        } else {
+            sx += ax;
+            sy += ay;
+            sz += az;
+        }
+    }
+    if (PREC == 2) {
+        band[i] = dx;
+        band[m.npad + i] = dy;
+        band[2 * m.npad + i] = dz;
+    } else {
+        band[i] = (double)sx + (double)ccx;
+        band[m.npad + i] = (double)sy + (double)ccy;
+        band[2 * m.npad + i] = (double)sz + (double)ccz;
+    }
+    n4 = wave_sum_u64(n4);
+    n11 = wave_sum_u64(n11);
+    if (lane == 0 && cnt) {
+        atomicAdd(&cnt[0], n4);
+        atomicAdd(&cnt[1], n11);
+    }
+}
+
+hipError_t launch_band(const DevMesh &m, const Thresholds &th, int precision, double *band,
+                       unsigned long long *cnt, hipStream_t s)
+{
+    if (precision == 0)
+        hipLaunchKernelGGL(k_band<0>, dim3(m.nblk), dim3(64), 0, s, m, th, band, cnt);
+    else if (precision == 1)
+        hipLaunchKernelGGL(k_band<1>, dim3(m.nblk), dim3(64), 0, s, m, th, band, cnt);
+    else
+        hipLaunchKernelGGL(k_band<2>, dim3(m.nblk), dim3(64), 0, s, m, th, band, cnt);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Ray tracing.  One wave (64 lanes) per node.
+//
+// 1. The tets whose centroid lies within r_rt of the node are classified
+//    (64 at a time); those whose rule is RT are appended to an LDS list.
+// 2. Every 64 listed tets form a batch; lane p prepares pair p: vertex
+//    positions relative to the node (from the hi/lo split, so nearby
+//    differences are exact to binary32), the six edge normals a_j x a_k in
+//    a canonical order (smaller node id first), the four face volumes, a
+//    cone bounding the directions that can reach the tet and the rectangle
+//    of (row, column) ray indices covering that cone.
+// 3. The rays of all rectangles of the batch are processed 64 at a time
+//    (lane = one (pair, ray) item): cone test, then the six signed edge
+//    volumes d . (a_j x a_k) decide which faces the ray crosses (a face is
+//    crossed when its three edge values have one sign; a value of zero
+//    counts as positive); every crossing at rho > 0 gives rho = vol_f / sum
+//    and the area coordinates; the chord adds to the lane's accumulator.
+//    Edge values tiny relative to the normal are recomputed in FP64 from
+//    the FP64 relative positions and FP64 directions.
+// 4. Lane accumulators are summed across the wave in FP64.
+struct RtLds {
+    float a[12][64];   // relative vertex positions, [j*3 + c][pair]
+    float w[12][64];   // vertex vorticity
+    float nrm[18][64]; // canonical edge normals, [e*3 + c][pair]
+    float vol[4][64];  // face volumes a_p . (a_q x a_r), face f opposite vertex f
+    float cone[4][64]; // unit axis, cos(alpha) (< -1: no culling)
+    int meta[64];      // bits 0-2: incident vertex (4 = none); bits 3-8: edge orientation
+    int rows[64];      // first row
+    int cols[64];      // first column
+    int ncol[64];      // columns per row
+    int pref[64];      // inclusive prefix sum of the item counts
+    int ids[4][64];    // vertex node ids (for the FP64 retest)
+    int list[128];     // pending ray-traced tets
+};
+
+__device__ __forceinline__ float diamond(float c, float s)
+{
+    // monotone pseudo-angle in [0, 4) of the unit vector (c, s)
+    if (s >= 0.f) return c >= 0.f ? s / (c + s) : 1.f - c / (-c + s);
+    return c < 0.f ? 2.f - s / (-c - s) : 3.f + c / (c - s);
+}
+
+// first index in the ascending array a[0..n) with a[idx] > v (n if none)
+__device__ __forceinline__ int upper_bound_f(const float *a, int n, float v)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] <= v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// first index in the ascending array a[0..n) with a[idx] >= v (n if none)
+__device__ __forceinline__ int lower_bound_f(const float *a, int n, float v)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void cross_canon(const float *A, const float *B, float *N)
+{
+    N[0] = fmaf(A[1], B[2], -(A[2] * B[1]));
+    N[1] = fmaf(A[2], B[0], -(A[0] * B[2]));
+    N[2] = fmaf(A[0], B[1], -(A[1] * B[0]));
+}
+
+// Pair setup for lane p (tet t, node self at (xh, xl)).  Returns the number
+// of candidate rays.
+__device__ int rt_setup(const DevMesh &m, const AngTab &ang, RtLds &L, int p, int t, int self, const float *xhv,
+                        const float *xlv)
+{
+    const int4 id4 = m.tid[t];
+    const int id[4] = {id4.x, id4.y, id4.z, id4.w};
+    float a[4][3];
+    int inc = 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int v = id[j];
+        L.ids[j][p] = v;
+        if (v == self) inc = j;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float vh = m.xh[c * m.npad + v], vl = m.xl[c * m.npad + v];
+            a[j][c] = (vh - xhv[c]) + (vl - xlv[c]);
+            L.a[j * 3 + c][p] = a[j][c];
+            L.w[j * 3 + c][p] = m.om[c * m.npad + v];
+        }
+    }
+    int sig = 0;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        constexpr int ea[6] = {0, 0, 0, 1, 1, 2}, eb[6] = {1, 2, 3, 2, 3, 3};
+        const int j = ea[e], k = eb[e];
+        float N[3];
+        if (id[j] < id[k]) cross_canon(a[j], a[k], N);
+        else {
+            cross_canon(a[k], a[j], N);
+            sig |= 1 << e;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) L.nrm[e * 3 + c][p] = N[c];
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const int pp = f == 0 ? 1 : 0, qq = f <= 1 ? 2 : 1, rr = f <= 2 ? 3 : 2; // ascending, without f
+        float N[3];
+        cross_canon(a[qq], a[rr], N);
+        L.vol[f][p] = fmaf(a[pp][0], N[0], fmaf(a[pp][1], N[1], a[pp][2] * N[2]));
+    }
+    L.meta[p] = inc | (sig << 3);
+
+    // bounding cone of the directions reaching the tet
+    float u[4][3], U[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float r2 = fmaf(a[j][0], a[j][0], fmaf(a[j][1], a[j][1], a[j][2] * a[j][2]));
+        const float s = (j == inc) ? 0.f : __builtin_amdgcn_rsqf(r2);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            u[j][c] = a[j][c] * s;
+            U[c] += u[j][c];
+        }
+    }
+    const float uu = fmaf(U[0], U[0], fmaf(U[1], U[1], U[2] * U[2]));
+    float cosa = 2.f;
+    if (uu > 0.f) {
+        const float s = __builtin_amdgcn_rsqf(uu);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) U[c] *= s;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j != inc) cosa = fminf(cosa, fmaf(U[0], u[j][0], fmaf(U[1], u[j][1], U[2] * u[j][2])));
+    }
+    cosa -= 1e-5f; // margin covering the rounding of the cone itself
+    const bool cull = uu > 0.f && cosa > 0.02f;
+    L.cone[0][p] = U[0];
+    L.cone[1][p] = U[1];
+    L.cone[2][p] = U[2];
+    L.cone[3][p] = cull ? cosa : -2.f;
+
+    // rectangle of ray indices covering the cone
+    int r0 = 0, nr = ang.N, c0 = 0, nc = ang.M2;
+    if (cull) {
+        const float sina = sqrtf(fmaxf(0.f, 1.f - cosa * cosa));
+        const float rxy = sqrtf(fmaxf(0.f, 1.f - U[2] * U[2]));
+        const bool north = U[2] >= cosa, south = -U[2] >= cosa;
+        const float chi = north ? 2.f : fmaf(U[2], cosa, rxy * sina) + 1e-5f;
+        const float clo = south ? -2.f : fmaf(U[2], cosa, -rxy * sina) - 1e-5f;
+        // rows: cphi descending; rows n with clo <= cphi[n] <= chi
+        int lo = 0, hi = ang.N;
+        while (lo < hi) { // first n with cphi[n] <= chi
+            const int mid = (lo + hi) >> 1;
+            if (ang.cphi[mid] > chi) lo = mid + 1;
+            else hi = mid;
+        }
+        r0 = lo;
+        lo = r0;
+        hi = ang.N;
+        while (lo < hi) { // first n with cphi[n] < clo
+            const int mid = (lo + hi) >> 1;
+            if (ang.cphi[mid] >= clo) lo = mid + 1;
+            else hi = mid;
+        }
+        nr = lo - r0;
+        if (!(north || south) && rxy > 0.f && sina < rxy) {
+            const float sb = sina / rxy;
+            const float cb = sqrtf(fmaxf(0.f, 1.f - sb * sb));
+            const float ct = U[0] / rxy, st = U[1] / rxy;
+            // endpoints at azimuth theta_U -+ beta
+            const float dlo0 = diamond(fmaf(ct, cb, st * sb), fmaf(st, cb, -ct * sb)) - 2e-4f;
+            const float dhi0 = diamond(fmaf(ct, cb, -st * sb), fmaf(st, cb, ct * sb)) + 2e-4f;
+            const float dlo = dlo0 < 0.f ? dlo0 + 4.f : dlo0;
+            const float dhi = dhi0 >= 4.f ? dhi0 - 4.f : dhi0;
+            const int jlo = lower_bound_f(ang.dia, ang.M2, dlo); // first column with dia >= dlo
+            const int jhi = upper_bound_f(ang.dia, ang.M2, dhi) - 1; // last column with dia <= dhi
+            c0 = jlo;
+            if (dlo <= dhi) nc = max(0, jhi - jlo + 1);
+            else nc = min(ang.M2, (ang.M2 - jlo) + (jhi + 1));
+            if (c0 >= ang.M2) c0 -= ang.M2;
+        }
+    }
+    L.rows[p] = r0;
+    L.cols[p] = c0;
+    L.ncol[p] = nc;
+    return nr > 0 && nc > 0 ? nr * nc : 0;
+}
+
+// Faces of a tetrahedron: face F is opposite vertex F; its vertices p < q < r
+// in local order; edge indices of (p,q), (q,r), (p,r) with the numbering
+// 01->0 02->1 03->2 12->3 13->4 23->5.
+template <int F> struct Face;
+template <> struct Face<0> { static constexpr int p = 1, q = 2, r = 3, epq = 3, eqr = 5, epr = 4; };
+template <> struct Face<1> { static constexpr int p = 0, q = 2, r = 3, epq = 1, eqr = 5, epr = 2; };
+template <> struct Face<2> { static constexpr int p = 0, q = 1, r = 3, epq = 0, eqr = 4, epr = 2; };
+template <> struct Face<3> { static constexpr int p = 0, q = 1, r = 2, epq = 0, eqr = 3, epr = 1; };
+
+struct Chord {
+    float rho_n, rho_f, wn[3], wf[3];
+    int nh;
+};
+
+// Crossing of face F by the ray d: ce[e] = [d, a_j, a_k] (j < k local),
+// se[e] its sign (+1 for zero, decided on the canonical value).
+template <int F>
+__device__ __forceinline__ void face_cross(const RtLds &L, int p, const float (&ce)[6], const int (&se)[6],
+                                           Chord &ch)
+{
+    using FF = Face<F>;
+    const int s1 = se[FF::epq], s2 = se[FF::eqr], s3 = -se[FF::epr];
+    if (s1 != s2 || s2 != s3) return;
+    const float E1 = ce[FF::epq], E2 = ce[FF::eqr], E3 = -ce[FF::epr];
+    const float S = (E1 + E2) + E3;
+    const float rho = L.vol[F][p] / S;
+    if (!(rho > 0.f) || !(rho < 3.0e38f)) return;
+    const float lp = E2 / S, lq = E3 / S, lr = E1 / S;
+    float w[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        w[c] = fmaf(lp, L.w[FF::p * 3 + c][p], fmaf(lq, L.w[FF::q * 3 + c][p], lr * L.w[FF::r * 3 + c][p]));
+    const bool first = ch.nh == 0;
+    const bool un = first || rho < ch.rho_n;
+    const bool uf = first || rho > ch.rho_f;
+    ch.rho_n = un ? rho : ch.rho_n;
+    ch.rho_f = uf ? rho : ch.rho_f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        ch.wn[c] = un ? w[c] : ch.wn[c];
+        ch.wf[c] = uf ? w[c] : ch.wf[c];
+    }
+    ++ch.nh;
+}
+
+// Sign of [d, a_j, a_k] recomputed in FP64 (positions from the hi/lo split,
+// FP64 ray direction); canonical operand order (smaller node id first).
+__device__ __forceinline__ int edge_sign_f64(const DevMesh &m, const double *d64, int v0, int v1, const float *xhv,
+                                          const float *xlv)
+{
+    double A[3], B[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double xn = (double)xhv[c] + (double)xlv[c];
+        A[c] = ((double)m.xh[c * m.npad + v0] + (double)m.xl[c * m.npad + v0]) - xn;
+        B[c] = ((double)m.xh[c * m.npad + v1] + (double)m.xl[c * m.npad + v1]) - xn;
+    }
+    const double N0 = A[1] * B[2] - A[2] * B[1];
+    const double N1 = A[2] * B[0] - A[0] * B[2];
+    const double N2 = A[0] * B[1] - A[1] * B[0];
+    const double c64 = d64[0] * N0 + d64[1] * N1 + d64[2] * N2;
+    return c64 >= 0.0 ? 1 : -1;
+}
+
+// One (pair, ray) item; adds to (ax, ay, az).  Returns 1 if the ray hits.
+__device__ __forceinline__ int rt_item(const DevMesh &m, const AngTab &ang, const RtLds &L, int p, int l,
+                                       const float *omx, const float *xhv, const float *xlv, float &ax,
+                                       float &ay, float &az, int &retests)
+{
+    const float4 d = ang.dir[l];
+    const float cosa = L.cone[3][p];
+    if (cosa > -1.5f) {
+        const float dc = fmaf(d.x, L.cone[0][p], fmaf(d.y, L.cone[1][p], d.z * L.cone[2][p]));
+        if (dc < cosa) return 0;
+    }
+    const int meta = L.meta[p];
+    const int inc = meta & 7;
+    const int sig = meta >> 3;
+    float ce[6];
+    int se[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        constexpr int ea[6] = {0, 0, 0, 1, 1, 2}, eb[6] = {1, 2, 3, 2, 3, 3};
+        ce[e] = 0.f;
+        se[e] = 1;
+        if (inc == ea[e] || inc == eb[e]) continue; // edge through the node: its faces are skipped
+        const float nx = L.nrm[e * 3][p], ny = L.nrm[e * 3 + 1][p], nz = L.nrm[e * 3 + 2][p];
+        const float c = fmaf(d.x, nx, fmaf(d.y, ny, d.z * nz));
+        int sg = c >= 0.f ? 1 : -1;
+        if (fabsf(c) <= 1e-5f * (fabsf(nx) + fabsf(ny) + fabsf(nz))) {
+            const int vj = L.ids[ea[e]][p], vk = L.ids[eb[e]][p];
+            const bool flip = (sig >> e) & 1;
+            sg = edge_sign_f64(m, ang.dir64 + 3 * (size_t)l, flip ? vk : vj, flip ? vj : vk, xhv, xlv);
+            ++retests;
+        }
+        const bool flip = (sig >> e) & 1;
+        se[e] = flip ? -sg : sg;
+        ce[e] = flip ? -c : c;
+    }
+    Chord ch;
+    ch.nh = 0;
+    ch.rho_n = ch.rho_f = 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ch.wn[c] = ch.wf[c] = 0.f;
+    if (inc == 4 || inc == 0) face_cross<0>(L, p, ce, se, ch);
+    if (inc == 4 || inc == 1) face_cross<1>(L, p, ce, se, ch);
+    if (inc == 4 || inc == 2) face_cross<2>(L, p, ce, se, ch);
+    if (inc == 4 || inc == 3) face_cross<3>(L, p, ce, se, ch);
+    float len;
+    if (ch.nh == 0) return 0;
+    if (inc != 4) {
+        if (ch.nh < 1) return 0;
+        // chord from the node (rho = 0, omega_x) to the opposite face
+        len = ch.rho_f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ch.wn[c] = omx[c];
+    } else if (ch.nh == 1) {
+        // one crossing ahead: the point lies inside the tet (a target that is
+        // not a vertex of it); the chord starts at the point itself, where the
+        // vorticity is the tet's linear field at the point: barycentric
+        // weights from the face volumes [a_p, a_q, a_r] (alternating signs)
+        const float v0 = L.vol[0][p], v1 = -L.vol[1][p], v2 = L.vol[2][p], v3 = -L.vol[3][p];
+        const float D = (v0 + v1) + (v2 + v3);
+        if (!(fabsf(D) > 0.f)) return 0;
+        const float iD = 1.0f / D;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            ch.wn[c] = (fmaf(v0, L.w[c][p], v1 * L.w[3 + c][p]) + fmaf(v2, L.w[6 + c][p], v3 * L.w[9 + c][p])) * iD;
+        len = ch.rho_f;
+    } else {
+        len = ch.rho_f - ch.rho_n;
+    }
+    const float h = 0.5f * d.w * len;
+    const float sx = ch.wn[0] + ch.wf[0], sy = ch.wn[1] + ch.wf[1], sz = ch.wn[2] + ch.wf[2];
+    ax = fmaf(h, fmaf(d.y, sz, -(d.z * sy)), ax);
+    ay = fmaf(h, fmaf(d.z, sx, -(d.x * sz)), ay);
+    az = fmaf(h, fmaf(d.x, sy, -(d.y * sx)), az);
+    return 1;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane)
+{
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+struct RtAcc {
+    float ax, ay, az, sx, sy, sz, cx, cy, cz;
+    double dx, dy, dz;
+    unsigned long long pairs, hits;
+    int retests;
+};
+
+// One batch of mcount (<= 64) listed tets: setup, then all candidate rays.
+template <int PREC>
+__device__ __forceinline__ void rt_batch(const DevMesh &m, const AngTab &ang, RtLds &L, int mcount, int lane,
+                                         int self, const float *xhv, const float *xlv, const float *omx,
+                                         RtAcc &A)
+{
+    int cntp = 0;
+    if (lane < mcount) cntp = rt_setup(m, ang, L, lane, L.list[lane], self, xhv, xlv);
+    const int incl = wave_incl_scan(cntp, lane);
+    L.pref[lane] = incl;
+    __syncthreads();
+    const int total = __shfl(incl, 63, 64);
+    for (int k0 = 0; k0 < total; k0 += 64) {
+        const int k = k0 + lane;
+        if (k < total) {
+            int lo = 0, hi = mcount - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (L.pref[mid] > k) hi = mid;
+                else lo = mid + 1;
+            }
+            const int p = lo;
+            const int r = k - (p ? L.pref[p - 1] : 0);
+            const int nc = L.ncol[p];
+            int row = (int)(((float)r + 0.5f) * (1.0f / (float)nc));
+            if (row * nc > r) --row;
+            if ((row + 1) * nc <= r) ++row;
+            int col = L.cols[p] + (r - row * nc);
+            if (col >= ang.M2) col -= ang.M2;
+            const int l = (L.rows[p] + row) * ang.M2 + col;
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+            A.hits += rt_item(m, ang, L, p, l, omx, xhv, xlv, a0, a1, a2, A.retests);
+            if (PREC == 0) {
+                A.ax += a0;
+                A.ay += a1;
+                A.az += a2;
+            } else if (PREC == 1) {
+                two_sum(A.sx, A.cx, a0);
+                two_sum(A.sy, A.cy, a1);
+                two_sum(A.sz, A.cz, a2);
+            } else {
+                A.dx += (double)a0;
+                A.dy += (double)a1;
+                A.dz += (double)a2;
+            }
+        }
+    }
+    A.pairs += mcount;
+    __syncthreads();
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang, int all_pairs,
+                                           double *__restrict__ rtv, unsigned long long *__restrict__ cnt)
+{
+    __shared__ RtLds L;
+    const int lane = threadIdx.x;
+    const int self = blockIdx.x;
+    float xhv[3], xlv[3], omx[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        xhv[c] = m.xh[c * m.npad + self];
+        xlv[c] = m.xl[c * m.npad + self];
+        omx[c] = m.om[c * m.npad + self];
+    }
+    RtAcc A;
+    A.ax = A.ay = A.az = A.sx = A.sy = A.sz = A.cx = A.cy = A.cz = 0.f;
+    A.dx = A.dy = A.dz = 0.0;
+    A.pairs = A.hits = 0;
+    A.retests = 0;
+    int nlist = 0; // uniform
+
+    RowIter rows(m, xhv[0], xhv[1], xhv[2], th.r_rt);
+    int t0 = 0, t1 = all_pairs ? m.T : 0;
+    bool have = all_pairs ? (m.T > 0) : rows.next(t0, t1);
+    while (have) {
+        for (int b0 = t0; b0 < t1; b0 += 64) {
+            const int t = b0 + lane;
+            bool is_rt = false;
+            if (t < t1) {
+                if (all_pairs) is_rt = true;
+                else {
+                    const float *g = m.g1 + (size_t)t * kRecG;
+                    is_rt = fixed_rule(xhv[0], xhv[1], xhv[2], g[0], g[1], g[2], m.tid[t], self, th) == RULE_RT;
+                }
+            }
+            const unsigned long long mask = __ballot(is_rt);
+            const int pos = nlist + __popcll(mask & ((1ull << lane) - 1ull));
+            if (is_rt) L.list[pos] = t;
+            nlist += __popcll(mask);
+            __syncthreads();
+            if (nlist >= 64) {
+                rt_batch<PREC>(m, ang, L, 64, lane, self, xhv, xlv, omx, A);
+                const int rest = nlist - 64;
+                const int keep = lane < rest ? L.list[64 + lane] : 0;
+                __syncthreads();
+                if (lane < rest) L.list[lane] = keep;
+                __syncthreads();
+                nlist = rest;
+            }
+        }
+        have = all_pairs ? false : rows.next(t0, t1);
+    }
+    if (nlist > 0) rt_batch<PREC>(m, ang, L, nlist, lane, self, xhv, xlv, omx, A);
+
+    double vx, vy, vz;
+    if (PREC == 0) {
+        vx = A.ax;
+        vy = A.ay;
+        vz = A.az;
+    } else if (PREC == 1) {
+        vx = (double)A.sx + (double)A.cx;
+        vy = (double)A.sy + (double)A.cy;
+        vz = (double)A.sz + (double)A.cz;
+    } else {
+        vx = A.dx;
+        vy = A.dy;
+        vz = A.dz;
+    }
+    vx = wave_sum_f64(vx);
+    vy = wave_sum_f64(vy);
+    vz = wave_sum_f64(vz);
+    const unsigned long long hits = wave_sum_u64(A.hits);
+    const unsigned long long rts = wave_sum_u64((unsigned long long)A.retests);
+    if (lane == 0) {
+        rtv[self] = vx;
+        rtv[m.npad + self] = vy;
+        rtv[2 * m.npad + self] = vz;
+        if (cnt) {
+            atomicAdd(&cnt[2], A.pairs);
+            atomicAdd(&cnt[3], hits);
+            atomicAdd(&cnt[4], rts);
+        }
+    }
+}
+
+hipError_t launch_rt(const DevMesh &m, const Thresholds &th, const AngTab &ang, int all_pairs, int precision,
+                     double *rtv, unsigned long long *cnt, hipStream_t s)
+{
+    if (m.n == 0) return hipSuccess;
+    if (precision == 0)
+        hipLaunchKernelGGL(k_rt<0>, dim3(m.n), dim3(64), 0, s, m, th, ang, all_pairs, rtv, cnt);
+    else if (precision == 1)
+        hipLaunchKernelGGL(k_rt<1>, dim3(m.n), dim3(64), 0, s, m, th, ang, all_pairs, rtv, cnt);
+    else
+        hipLaunchKernelGGL(k_rt<2>, dim3(m.n), dim3(64), 0, s, m, th, ang, all_pairs, rtv, cnt);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_combine(int n, int npad, const int *__restrict__ node_orig,
+                                                 const double *__restrict__ part, int splits,
+                                                 const double *__restrict__ band, const double *__restrict__ rtv,
+                                                 double *__restrict__ vel, int *__restrict__ nonfinite)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int o = node_orig[i];
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double v = 0.0;
+        for (int s = 0; s < splits; ++s) v += part[((size_t)s * 3 + c) * npad + i];
+        if (band) v += band[(size_t)c * npad + i];
+        if (rtv) v += rtv[(size_t)c * npad + i];
+        vel[3 * (size_t)o + c] = v;
+        bad |= !isfinite(v);
+    }
+    if (bad) atomicOr(nonfinite, 1);
+}
+
+hipError_t launch_combine(const DevMesh &m, const int *node_orig, const double *part, int splits,
+                          const double *band, const double *rtv, double *vel, int *nonfinite, hipStream_t s)
+{
+    if (m.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_combine, dim3((m.n + 255) / 256), dim3(256), 0, s, m.n, m.npad, node_orig, part, splits,
+                       band, rtv, vel, nonfinite);
+    return hipGetLastError();
+}
+
+} // namespace bsk

@@ -1,0 +1,229 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle
+on the same seeded inputs.
+
+Tolerance: relative L2 error <= 1e-6 over all nodes and components for the
+FP32 path (the stated target), per policy.  Rule decisions (binary32 on both
+sides) must match exactly, pair counts included."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_0712_1695_amd as bs
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    torch.cuda.set_device(0)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu_eval(mesh_or_arrays, **pol):
+    if isinstance(mesh_or_arrays, W.Mesh):
+        xyz, om, tets = mesh_or_arrays.xyz, mesh_or_arrays.omega, mesh_or_arrays.tets
+    else:
+        xyz, om, tets = mesh_or_arrays
+    h = bs.bs_mesh_upload(xyz, om, tets)
+    bs.bs_set_policy(h, **pol)
+    v, st = bs.bs_eval_velocity(h, stats=True)
+    bs.bs_mesh_free(h)
+    return v, st
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("rule,pts", [(0, 1), (1, 4), (2, 11)])
+def test_gauss_only_c1(rule, pts):
+    m = W.make_config("C1")
+    _say(f"gauss-only G{pts} on C1")
+    v, st = gpu_eval(m, kind=bs.BS_POLICY_GAUSS_ONLY, gauss_rule=rule)
+    ref = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("gauss_only", gauss_rule=rule))
+    assert rel_l2(v, ref) <= TOL
+    assert st["pairs_by_rule"][rule] == m.n_nodes * m.n_tets
+
+
+@pytest.mark.parametrize("prec", [bs.BS_PREC_FP32_NAIVE, bs.BS_PREC_FP32_COMP, bs.BS_PREC_FP64])
+def test_fixed_policy_c1(prec):
+    m = W.make_config("C1")
+    _say(f"fixed policy on C1, precision {prec}")
+    v, st = gpu_eval(m, kind=bs.BS_POLICY_FIXED, precision=prec)
+    ref, cnt = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("fixed"), return_counters=True)
+    assert st["hbar"] == cnt["hbar"]
+    assert st["pairs_by_rule"] == cnt["pairs_by_rule"]
+    assert st["rt_hit_lines"] > 0
+    assert st["nonfinite_out"] == 0
+    assert rel_l2(v, ref) <= TOL
+
+
+@pytest.mark.parametrize("nm", [(16, 16), (8, 12), (5, 7)])
+def test_pure_ray_tracing_c1(nm):
+    """Odd orders put a Gauss node at t = 0: lines with phi = pi/2 or
+    theta = pi/2 are tangent to the box faces, and from an (unjittered)
+    boundary node such a line runs along boundary faces, where the chord has
+    no unique value (the line integral jumps between the two sides).  For
+    odd orders only interior nodes are compared here; the general-position
+    case is covered by the next test."""
+    m = W.make_config("C1")
+    _say(f"pure ray tracing on C1, N x M = {nm}")
+    v, st = gpu_eval(m, kind=bs.BS_POLICY_PURE_RT, n_phi=nm[0], n_theta=nm[1])
+    ref, cnt = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("pure_rt", n_phi=nm[0], n_theta=nm[1]),
+                               return_counters=True)
+    if nm[0] % 2 or nm[1] % 2:
+        keep = ~m.boundary
+        assert np.all(np.isfinite(v))
+        assert rel_l2(v[keep], ref[keep]) <= TOL
+    else:
+        assert rel_l2(v, ref) <= TOL
+        # every (line, tet) hit of the oracle is one ray hit on the GPU (exact
+        # decisions away from edges and vertices; allow a few near-edge flips)
+        assert abs(st["rt_hit_lines"] - cnt["rt_hit_lines"]) <= 1e-5 * cnt["rt_hit_lines"] + 8
+
+
+@pytest.mark.parametrize("nm", [(5, 7), (3, 3), (16, 16)])
+def test_pure_ray_tracing_general_position(nm):
+    """Every node jittered (boundary included): no line lies in a face plane,
+    so the result is unique for any order and all nodes are compared."""
+    xyz, tets, h, b = W.kuhn_grid((-1, -1, -1), (1, 1, 1), (7, 6, 5))
+    xyz = xyz + np.random.default_rng(9).uniform(-0.1, 0.1, size=xyz.shape) * h[None, :]
+    tets = W.orient_positive(xyz, tets)
+    om = W.field_gaussian_swirl(xyz)
+    _say(f"pure ray tracing, general position, N x M = {nm}")
+    v, _ = gpu_eval((xyz, om, tets), kind=bs.BS_POLICY_PURE_RT, n_phi=nm[0], n_theta=nm[1])
+    ref = oracle.evaluate(xyz, om, tets, oracle.make_policy("pure_rt", n_phi=nm[0], n_theta=nm[1]))
+    assert rel_l2(v, ref) <= TOL
+
+
+def test_ring_reduced_full_oracle():
+    m = W.make_config("C2", scale=(24, 24, 8))
+    _say(f"ring at 24x24x8 cells ({m.n_nodes} nodes), fixed policy")
+    v, st = gpu_eval(m)
+    ref, cnt = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("fixed"), return_counters=True)
+    assert st["pairs_by_rule"] == cnt["pairs_by_rule"]
+    assert rel_l2(v, ref) <= TOL
+
+
+def _sample_nodes(m, k, seed):
+    rng = np.random.default_rng(seed)
+    corners = [0, m.n_nodes - 1]
+    inner = rng.choice(m.n_nodes, size=k - 2, replace=False)
+    return np.unique(np.concatenate([corners, inner]))
+
+
+@pytest.mark.parametrize("name", ["C2", "C3"])
+def test_full_size_sampled(name):
+    """Full workload on the GPU in the configuration the benchmark times;
+    the oracle evaluates a seeded sample of nodes one by one."""
+    m = W.make_config(name)
+    _say(f"{name} full size ({m.n_nodes} nodes, {m.n_tets} tets), fixed policy")
+    v, st = gpu_eval(m)
+    tg = _sample_nodes(m, 40, seed=11)
+    ref = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("fixed"), targets=tg)
+    err = rel_l2(v[tg], ref)
+    _say(f"{name}: sampled rel-L2 {err:.3e}; rules {st['pairs_by_rule']}; t_eval {st['t_eval_s']*1e3:.2f} ms")
+    assert err <= TOL
+    assert sum(st["pairs_by_rule"]) == m.n_nodes * m.n_tets
+
+
+def test_precision_modes_c3_sampled():
+    """Precision sweep on the 48^3 Fourier-curl workload: naive FP32
+    accumulation over ~6.6e5 terms per node drifts past 1e-6; the TwoSum
+    tiles and FP64 accumulation stay within it.  Errors are reported per
+    result (whole-sample rel-L2 and worst node)."""
+    m = W.make_config("C3")
+    tg = _sample_nodes(m, 24, seed=3)
+    ref = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("fixed"), targets=tg)
+    errs = {}
+    for prec in (bs.BS_PREC_FP32_NAIVE, bs.BS_PREC_FP32_COMP, bs.BS_PREC_FP64):
+        v, st = gpu_eval(m, precision=prec)
+        err = rel_l2(v[tg], ref)
+        per = np.linalg.norm(v[tg] - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-300)
+        _say(f"C3 precision {prec}: rel-L2 {err:.3e}, max per-node {per.max():.3e}, "
+             f"t_eval {st['t_eval_s']*1e3:.1f} ms")
+        errs[prec] = err
+    assert errs[bs.BS_PREC_FP32_COMP] <= TOL and errs[bs.BS_PREC_FP64] <= TOL
+    assert errs[bs.BS_PREC_FP32_NAIVE] <= 1e-4
+    assert errs[bs.BS_PREC_FP32_NAIVE] > errs[bs.BS_PREC_FP32_COMP]
+
+
+# ------------------------------------------------------------------ edges
+
+def test_single_tet_and_tiny_meshes():
+    t = W.single_tet(5)
+    for kind in (bs.BS_POLICY_FIXED, bs.BS_POLICY_PURE_RT):
+        v, _ = gpu_eval(t, kind=kind)
+        ref = oracle.evaluate(t.xyz, t.omega, t.tets,
+                              oracle.make_policy("fixed" if kind == bs.BS_POLICY_FIXED else "pure_rt"))
+        assert rel_l2(v, ref) <= TOL
+    m = W.make_config("C1", scale=(1, 1, 1))
+    v, _ = gpu_eval(m)
+    assert rel_l2(v, oracle.evaluate(m.xyz, m.omega, m.tets)) <= TOL
+
+
+def test_no_tets_gives_zero_velocity():
+    xyz = np.random.default_rng(0).standard_normal((37, 3))
+    v, st = gpu_eval((xyz, np.ones((37, 3)), np.zeros((0, 4), dtype=np.int32)))
+    assert np.all(v == 0.0) and st["pairs"] == 0
+
+
+def test_ragged_counts_and_unreferenced_nodes():
+    """Node count not a multiple of any block size; extra nodes used by no
+    tetrahedron (their velocity is still evaluated), some of them inside
+    tetrahedra (off-node targets: rays start inside the element)."""
+    m = W.make_config("C1", scale=(3, 5, 4))
+    rng = np.random.default_rng(2)
+    extra = rng.uniform(-1.5, 1.5, size=(7, 3))
+    xyz = np.vstack([m.xyz, extra])
+    om = np.vstack([m.omega, rng.standard_normal((7, 3))])
+    v, st = gpu_eval((xyz, om, m.tets))
+    ref, cnt = oracle.evaluate(xyz, om, m.tets, return_counters=True)
+    assert st["pairs_by_rule"] == cnt["pairs_by_rule"]
+    assert rel_l2(v, ref) <= TOL
+
+
+def test_reoriented_tets():
+    m = W.make_config("C1", scale=(4, 4, 4))
+    tets = m.tets.copy()
+    flip = np.arange(0, m.n_tets, 3)
+    tets[flip, 1], tets[flip, 2] = m.tets[flip, 2], m.tets[flip, 1]
+    v, st = gpu_eval((m.xyz, m.omega, tets))
+    assert st["reoriented"] == flip.size
+    assert rel_l2(v, oracle.evaluate(m.xyz, m.omega, tets)) <= TOL
+
+
+def test_device_pointers_update_stream_and_determinism():
+    import torch
+
+    m = W.make_config("C1", scale=(6, 6, 6))
+    dev = torch.device("cuda", 0)
+    xyz_t = torch.tensor(m.xyz, device=dev)
+    om_t = torch.tensor(m.omega, device=dev)
+    tets_t = torch.tensor(m.tets, device=dev)
+    h_host = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
+    h_dev = bs.bs_mesh_upload(xyz_t, om_t, tets_t)
+    a = bs.bs_eval_velocity(h_host)
+    out = torch.empty((m.n_nodes, 3), dtype=torch.float64, device=dev)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        bs.bs_eval_velocity(h_dev, out=out)
+    s.synchronize()
+    assert np.array_equal(a, out.cpu().numpy())
+    assert np.array_equal(a, bs.bs_eval_velocity(h_host))  # deterministic
+    # update to other coordinates == fresh upload of those coordinates
+    m2 = W.make_config("C1", scale=(6, 6, 6), seed=77)
+    bs.bs_mesh_update(h_host, xyz=m2.xyz, omega=m2.omega)
+    h2 = bs.bs_mesh_upload(m2.xyz, m2.omega, m2.tets)
+    assert np.array_equal(bs.bs_eval_velocity(h_host), bs.bs_eval_velocity(h2))
+    for h in (h_host, h_dev, h2):
+        bs.bs_mesh_free(h)
