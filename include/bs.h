@@ -153,6 +153,23 @@ typedef struct {
  * mesh), BS_E_ARG (NULL vel), BS_E_DEVICE (launch or runtime failure). */
 int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, bs_stats *st);
 
+/* Lagrangian motion of the nodes (the paper's setting, Sections 1 and 3:
+ * control points move with the flow and the velocity is re-evaluated every
+ * step): `steps` Heun (RK2) steps of size dt,
+ *     v1 = v(x); x* = x + dt v1; v2 = v(x*); x <- x + dt/2 (v1 + v2),
+ * with the current policy, connectivity and nodal vorticity kept.  The
+ * position updates are FP64 on the host; each stage re-runs the per-element
+ * precompute and one evaluation.  The mesh ends at the new positions;
+ * xyz_out ([n_nodes][3], host or device per flags; may be NULL) receives
+ * them; step_seconds (host, `steps` doubles; may be NULL) the wall time of
+ * every step; st (may be NULL) the counters of the last evaluation, with
+ * t_eval_s the summed device time of all evaluations.  Errors: BS_E_STATE
+ * (NULL mesh), BS_E_ARG (steps < 0, non-finite dt), BS_E_DEGENERATE (a
+ * tetrahedron flattens or inverts relative to its uploaded orientation;
+ * the mesh is left at the start of that step), BS_E_DEVICE. */
+int bs_advect_heun(bs_mesh *m, double dt, int steps, double *xyz_out, uint32_t flags, void *stream,
+                   double *step_seconds, bs_stats *st);
+
 /* Static description of a status code. */
 const char *bs_status_string(int status);
 

@@ -93,7 +93,7 @@ class Stats(ctypes.Structure):
 
 # every symbol include/bs.h declares
 EXPORTS = ["bs_mesh_upload", "bs_mesh_update", "bs_mesh_free", "bs_policy_default", "bs_set_policy",
-           "bs_eval_velocity", "bs_status_string", "bs_last_error"]
+           "bs_eval_velocity", "bs_advect_heun", "bs_status_string", "bs_last_error"]
 
 
 class BsError(RuntimeError):
@@ -127,6 +127,9 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     L.bs_set_policy.restype = ctypes.c_int
     L.bs_eval_velocity.argtypes = [vp, vp, ctypes.c_uint32, vp, ctypes.POINTER(Stats)]
     L.bs_eval_velocity.restype = ctypes.c_int
+    L.bs_advect_heun.argtypes = [vp, ctypes.c_double, ctypes.c_int, vp, ctypes.c_uint32, vp, vp,
+                                 ctypes.POINTER(Stats)]
+    L.bs_advect_heun.restype = ctypes.c_int
     L.bs_status_string.argtypes = [ctypes.c_int]
     L.bs_status_string.restype = ctypes.c_char_p
     L.bs_last_error.argtypes = []
@@ -267,6 +270,27 @@ def bs_eval_velocity(mesh: BsMesh, out=None, stream=None, stats: bool = False):
                                 ctypes.byref(st) if st is not None else None)
     _check(rc, "bs_eval_velocity")
     return (vel, st.as_dict()) if stats else vel
+
+
+def bs_advect_heun(mesh: BsMesh, dt: float, steps: int, out=None, stream=None, stats: bool = False):
+    """Advance the mesh nodes `steps` Heun steps of size dt (positions kept in
+    the mesh).  Returns (positions [n,3] numpy or the device tensor `out`,
+    per-step seconds [steps] numpy[, stats dict])."""
+    L = load_library()
+    st = Stats() if stats else None
+    secs = np.zeros(max(int(steps), 1), dtype=np.float64)
+    if out is None:
+        pos = np.empty((mesh.n_nodes, 3), dtype=np.float64)
+        ptr, flags = ctypes.c_void_p(pos.ctypes.data), BS_PTR_HOST
+    else:
+        if not (_is_torch(out) and out.is_cuda and str(out.dtype) == "torch.float64" and out.is_contiguous()):
+            raise ValueError("out must be a contiguous float64 device tensor")
+        pos, ptr, flags = out, ctypes.c_void_p(out.data_ptr()), BS_PTR_DEVICE
+    _check(L.bs_advect_heun(mesh.handle, float(dt), int(steps), ptr, flags, _stream_handle(stream),
+                            ctypes.c_void_p(secs.ctypes.data), ctypes.byref(st) if st is not None else None),
+           "bs_advect_heun")
+    secs = secs[: int(steps)]
+    return (pos, secs, st.as_dict()) if stats else (pos, secs)
 
 
 def status_string(status: int) -> str:

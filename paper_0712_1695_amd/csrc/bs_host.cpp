@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -216,6 +217,7 @@ struct bs_mesh {
     std::vector<double> xyz, omega; // current FP64 inputs
     double hbar = 0.0, max_vc = 0.0;
     int64_t reoriented = 0;
+    std::vector<int8_t> orient; // sign of det per tet at upload (inversion check on updates)
     bsk::Bins bins{};
     // device buffers
     DBuf xh, xl, om, blk, node_orig, g1, g4, g11, tid, cell_start;
@@ -298,6 +300,24 @@ int validate_geometry(bs_mesh *m)
         if (!(std::fabs(det) > 1e-12 * h2 * std::sqrt(h2)))
             return fail(BS_E_DEGENERATE, "tetrahedron %lld has zero volume", (long long)t);
         if (det < 0) ++neg;
+        const int8_t sg = det < 0 ? -1 : 1;
+        if (!m->orient.empty() && m->orient[(size_t)t] != sg)
+            return fail(BS_E_DEGENERATE, "tetrahedron %lld inverted relative to its uploaded orientation",
+                        (long long)t);
+    }
+    if (m->orient.empty()) {
+        m->orient.resize((size_t)T);
+        for (int64_t t = 0; t < T; ++t) {
+            const int32_t *id = &m->tets[4 * t];
+            double e[3][3];
+            for (int j = 0; j < 3; ++j)
+                for (int c = 0; c < 3; ++c)
+                    e[j][c] = m->xyz[3 * (int64_t)id[j + 1] + c] - m->xyz[3 * (int64_t)id[0] + c];
+            const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                               e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                               e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+            m->orient[(size_t)t] = det < 0 ? -1 : 1;
+        }
     }
     m->reoriented = neg;
     return BS_OK;
@@ -772,13 +792,13 @@ int bs_set_policy(bs_mesh *m, const bs_policy *p)
     return BS_OK;
 }
 
-int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, bs_stats *st)
+} // extern "C"
+
+namespace {
+
+// One evaluation into m->vel (device, input node order), on stream s.
+int eval_device(bs_mesh *m, hipStream_t s)
 {
-    g_err.clear();
-    if (!m) return fail(BS_E_STATE, "null mesh");
-    if (!vel) return fail(BS_E_ARG, "null output");
-    if (vel_flags & ~BS_PTR_DEVICE) return fail(BS_E_ARG, "unknown flags 0x%x", vel_flags);
-    hipStream_t s = (hipStream_t)stream;
     int rc = install_angular(m);
     if (rc) return rc;
     const bs_policy &P = m->pol;
@@ -845,6 +865,60 @@ int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, 
                                  (double *)m->vel.p, (int *)m->nonfinite.p, s)))
         return hip_fail(e, "combine kernel");
     (void)hipEventRecord(m->ev[4], s);
+    return BS_OK;
+}
+
+int read_stats(bs_mesh *m, bs_stats *st)
+{
+    unsigned long long c[bsk::kNumCounters];
+    int nf = 0;
+    hipError_t e;
+    if ((e = hipMemcpy(c, m->cnt.p, sizeof c, hipMemcpyDeviceToHost)) ||
+        (e = hipMemcpy(&nf, m->nonfinite.p, 4, hipMemcpyDeviceToHost)))
+        return hip_fail(e, "read counters");
+    const bs_policy &P = m->pol;
+    std::memset(st, 0, sizeof *st);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, m->ev[0], m->ev[4]);
+    st->t_eval_s = ms * 1e-3;
+    for (int k = 0; k < 4; ++k) {
+        float mk = 0.f;
+        (void)hipEventElapsedTime(&mk, m->ev[k], m->ev[k + 1]);
+        st->t_kernel_s[k] = mk * 1e-3;
+    }
+    st->pairs = m->n * m->T;
+    if (P.kind == BS_POLICY_FIXED) {
+        st->pairs_by_rule[BS_RULE_G4] = (int64_t)c[0];
+        st->pairs_by_rule[BS_RULE_G11] = (int64_t)c[1];
+        st->pairs_by_rule[BS_RULE_RT] = (int64_t)c[2];
+        st->pairs_by_rule[BS_RULE_G1] = st->pairs - (int64_t)(c[0] + c[1] + c[2]);
+    } else if (P.kind == BS_POLICY_PURE_RT) {
+        st->pairs_by_rule[BS_RULE_RT] = st->pairs;
+    } else {
+        st->pairs_by_rule[P.gauss_rule] = st->pairs;
+    }
+    st->rt_hit_lines = (int64_t)c[3];
+    st->fp64_retests = (int64_t)c[4];
+    st->reoriented = m->reoriented;
+    st->nonfinite_out = nf;
+    st->hbar = m->hbar;
+    return BS_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, bs_stats *st)
+{
+    g_err.clear();
+    if (!m) return fail(BS_E_STATE, "null mesh");
+    if (!vel) return fail(BS_E_ARG, "null output");
+    if (vel_flags & ~BS_PTR_DEVICE) return fail(BS_E_ARG, "unknown flags 0x%x", vel_flags);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = eval_device(m, s);
+    if (rc) return rc;
+    hipError_t e;
     const size_t vbytes = 8 * 3 * (size_t)m->n;
     e = hipMemcpyAsync(vel, m->vel.p, vbytes, (vel_flags & BS_PTR_DEVICE) ? hipMemcpyDeviceToDevice
                                                                           : hipMemcpyDeviceToHost, s);
@@ -852,37 +926,72 @@ int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, 
     if (!(vel_flags & BS_PTR_DEVICE) || st) {
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "evaluation");
     }
-    if (st) {
-        unsigned long long c[bsk::kNumCounters];
-        int nf = 0;
-        if ((e = hipMemcpy(c, m->cnt.p, sizeof c, hipMemcpyDeviceToHost)) ||
-            (e = hipMemcpy(&nf, m->nonfinite.p, 4, hipMemcpyDeviceToHost)))
-            return hip_fail(e, "read counters");
-        std::memset(st, 0, sizeof *st);
+    if (st && (rc = read_stats(m, st))) return rc;
+    return BS_OK;
+}
+
+int bs_advect_heun(bs_mesh *m, double dt, int steps, double *xyz_out, uint32_t flags, void *stream,
+                   double *step_seconds, bs_stats *st)
+{
+    g_err.clear();
+    if (!m) return fail(BS_E_STATE, "null mesh");
+    if (steps < 0 || !std::isfinite(dt)) return fail(BS_E_ARG, "steps must be >= 0 and dt finite");
+    if (flags & ~BS_PTR_DEVICE) return fail(BS_E_ARG, "unknown flags 0x%x", flags);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n3 = 3 * (size_t)m->n;
+    std::vector<double> x = m->xyz, v1(n3), v2(n3), xs(n3);
+    double t_dev = 0.0;
+    int rc = BS_OK;
+    hipError_t e;
+    auto eval_to = [&](std::vector<double> &v) -> int {
+        int r = eval_device(m, s);
+        if (r) return r;
+        if ((e = hipMemcpyAsync(v.data(), m->vel.p, 8 * n3, hipMemcpyDeviceToHost, s)) ||
+            (e = hipStreamSynchronize(s)))
+            return hip_fail(e, "read velocity");
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, m->ev[0], m->ev[4]);
-        st->t_eval_s = ms * 1e-3;
-        for (int k = 0; k < 4; ++k) {
-            float mk = 0.f;
-            (void)hipEventElapsedTime(&mk, m->ev[k], m->ev[k + 1]);
-            st->t_kernel_s[k] = mk * 1e-3;
+        t_dev += ms * 1e-3;
+        return BS_OK;
+    };
+    auto move_to = [&](const std::vector<double> &pos) -> int {
+        m->xyz = pos;
+        int r = validate_geometry(m);
+        if (r) return r;
+        return build_device_mesh(m, s);
+    };
+    for (int k = 0; k < steps && rc == BS_OK; ++k) {
+        const auto t0 = std::chrono::steady_clock::now();
+        const std::vector<double> x0 = x;
+        if ((rc = eval_to(v1))) break;
+        for (size_t i = 0; i < n3; ++i) xs[i] = x[i] + dt * v1[i];
+        if ((rc = move_to(xs)) == BS_OK && (rc = eval_to(v2)) == BS_OK) {
+            for (size_t i = 0; i < n3; ++i) x[i] = x[i] + 0.5 * dt * (v1[i] + v2[i]);
+            rc = move_to(x);
         }
-        st->pairs = m->n * m->T;
-        if (P.kind == BS_POLICY_FIXED) {
-            st->pairs_by_rule[BS_RULE_G4] = (int64_t)c[0];
-            st->pairs_by_rule[BS_RULE_G11] = (int64_t)c[1];
-            st->pairs_by_rule[BS_RULE_RT] = (int64_t)c[2];
-            st->pairs_by_rule[BS_RULE_G1] = st->pairs - (int64_t)(c[0] + c[1] + c[2]);
-        } else if (P.kind == BS_POLICY_PURE_RT) {
-            st->pairs_by_rule[BS_RULE_RT] = st->pairs;
+        if (rc) {
+            // leave the mesh at the start of the failing step
+            const std::string why = g_err;
+            m->xyz = x0;
+            if (validate_geometry(m) == BS_OK) build_device_mesh(m, s);
+            g_err = why;
+            return rc;
+        }
+        if (step_seconds)
+            step_seconds[k] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (xyz_out) {
+        if (flags & BS_PTR_DEVICE) {
+            if ((e = hipMemcpyAsync(xyz_out, x.data(), 8 * n3, hipMemcpyHostToDevice, s)) ||
+                (e = hipStreamSynchronize(s)))
+                return hip_fail(e, "write positions");
         } else {
-            st->pairs_by_rule[P.gauss_rule] = st->pairs;
+            std::memcpy(xyz_out, x.data(), 8 * n3);
         }
-        st->rt_hit_lines = (int64_t)c[3];
-        st->fp64_retests = (int64_t)c[4];
-        st->reoriented = m->reoriented;
-        st->nonfinite_out = nf;
-        st->hbar = m->hbar;
+    }
+    if (st) {
+        if ((rc = read_stats(m, st))) return rc;
+        st->t_eval_s = t_dev;
     }
     return BS_OK;
 }

@@ -56,14 +56,13 @@ __device__ __forceinline__ void two_sum(float &s, float &c, float a)
 __device__ __forceinline__ int fixed_rule(float x, float y, float z, float cx, float cy, float cz, int4 id,
                                           int self, const Thresholds &th)
 {
-    if (id.x == self || id.y == self || id.z == self || id.w == self) return RULE_RT;
+    const bool inc = (id.x == self) | (id.y == self) | (id.z == self) | (id.w == self);
     const float dx = x - cx, dy = y - cy, dz = z - cz;
     const float sx = dx * dx, sy = dy * dy, sz = dz * dz;
     const float d2 = (sx + sy) + sz;
-    if (d2 < th.rt2) return RULE_RT;
-    if (d2 < th.g11_2) return RULE_G11;
-    if (d2 < th.g4_2) return RULE_G4;
-    return RULE_G1;
+    int rule = d2 < th.g4_2 ? RULE_G4 : RULE_G1;
+    rule = d2 < th.g11_2 ? RULE_G11 : rule;
+    return (inc || d2 < th.rt2) ? RULE_RT : rule;
 }
 
 // One Gauss point: acc += (W x r) / |r|^3, r = x - p.
@@ -313,16 +312,22 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 }
 
 // ---------------------------------------------------------------------------
-// Band corrections.  One wave per 64 consecutive (Morton-ordered) nodes.
-// For every tet whose centroid lies within r_band of the block's bounding
-// sphere: lanes whose pair rule is not G1 subtract the G1 term added by
-// k_gauss_all, then lanes with G4 / G11 add that rule (ray-traced pairs are
-// added by k_rt).
+// Band corrections.  One workgroup of kBandWaves waves per 64 consecutive
+// (Morton-ordered) nodes; lane = node, the waves take the bin rows of the
+// block's neighbourhood in turn.  For every tet whose centroid lies within
+// r_band of the block's bounding sphere: lanes whose pair rule is not G1
+// subtract the G1 term added by k_gauss_all, then lanes with G4 / G11 add
+// that rule (ray-traced pairs are added by k_rt).  The waves' partial sums
+// are combined in FP64 through LDS.
+constexpr int kBandWaves = 4;
+
 template <int PREC>
-__global__ void __launch_bounds__(64) k_band(DevMesh m, Thresholds th, double *__restrict__ band,
-                                             unsigned long long *__restrict__ cnt)
+__global__ void __launch_bounds__(64 * kBandWaves) k_band(DevMesh m, Thresholds th, double *__restrict__ band,
+                                                          unsigned long long *__restrict__ cnt)
 {
-    const int lane = threadIdx.x;
+    __shared__ double red[kBandWaves][3][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); // uniform within the wave
     const int i = blockIdx.x * kBlockNodes + lane;
     const bool valid = i < m.n;
     const float x = m.xh[i], y = m.xh[m.npad + i], z = m.xh[2 * m.npad + i];
@@ -331,13 +336,15 @@ __global__ void __launch_bounds__(64) k_band(DevMesh m, Thresholds th, double *_
     double dx = 0.0, dy = 0.0, dz = 0.0;
     unsigned long long n4 = 0, n11 = 0;
     RowIter rows(m, bc.x, bc.y, bc.z, th.r_band + bc.w);
-    int t0, t1;
+    int t0, t1, row = 0;
     while (rows.next(t0, t1)) {
+        if ((row++ % kBandWaves) != wave) continue;
         float ax = 0.f, ay = 0.f, az = 0.f;
         for (int t = t0; t < t1; ++t) {
             const float *g = m.g1 + (size_t)t * kRecG;
             const int4 id = m.tid[t];
-            const int rule = valid ? fixed_rule(x, y, z, g[0], g[1], g[2], id, i, th) : RULE_G1;
+            const float gx = g[0], gy = g[1], gz = g[2];
+            const int rule = valid ? fixed_rule(x, y, z, gx, gy, gz, id, i, th) : RULE_G1;
             if (rule != RULE_G1) {
                 float a = 0.f, b = 0.f, c = 0.f;
                 gauss_point(x, y, z, g, a, b, c);
@@ -372,32 +379,42 @@ __global__ void __launch_bounds__(64) k_band(DevMesh m, Thresholds th, double *_
             sz += az;
         }
     }
-    if (PREC == 2) {
-        band[i] = dx;
-        band[m.npad + i] = dy;
-        band[2 * m.npad + i] = dz;
-    } else {
-        band[i] = (double)sx + (double)ccx;
-        band[m.npad + i] = (double)sy + (double)ccy;
-        band[2 * m.npad + i] = (double)sz + (double)ccz;
+    if (PREC != 2) {
+        dx = (double)sx + (double)ccx;
+        dy = (double)sy + (double)ccy;
+        dz = (double)sz + (double)ccz;
     }
+    red[wave][0][lane] = dx;
+    red[wave][1][lane] = dy;
+    red[wave][2][lane] = dz;
     n4 = wave_sum_u64(n4);
     n11 = wave_sum_u64(n11);
     if (lane == 0 && cnt) {
         atomicAdd(&cnt[0], n4);
         atomicAdd(&cnt[1], n11);
     }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double v = red[0][c][lane];
+#pragma unroll
+            for (int w = 1; w < kBandWaves; ++w) v += red[w][c][lane];
+            band[(size_t)c * m.npad + i] = v;
+        }
+    }
 }
 
 hipError_t launch_band(const DevMesh &m, const Thresholds &th, int precision, double *band,
                        unsigned long long *cnt, hipStream_t s)
 {
+    const dim3 blk(64 * kBandWaves);
     if (precision == 0)
-        hipLaunchKernelGGL(k_band<0>, dim3(m.nblk), dim3(64), 0, s, m, th, band, cnt);
+        hipLaunchKernelGGL(k_band<0>, dim3(m.nblk), blk, 0, s, m, th, band, cnt);
     else if (precision == 1)
-        hipLaunchKernelGGL(k_band<1>, dim3(m.nblk), dim3(64), 0, s, m, th, band, cnt);
+        hipLaunchKernelGGL(k_band<1>, dim3(m.nblk), blk, 0, s, m, th, band, cnt);
     else
-        hipLaunchKernelGGL(k_band<2>, dim3(m.nblk), dim3(64), 0, s, m, th, band, cnt);
+        hipLaunchKernelGGL(k_band<2>, dim3(m.nblk), blk, 0, s, m, th, band, cnt);
     return hipGetLastError();
 }
 
