@@ -170,6 +170,70 @@ int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, 
 int bs_advect_heun(bs_mesh *m, double dt, int steps, double *xyz_out, uint32_t flags, void *stream,
                    double *step_seconds, bs_stats *st);
 
+/* ------------------------------------------------------------ rule selector
+ * A 16-64-64-4 network (ReLU, BF16 weights and activations, FP32
+ * accumulation on the matrix cores) picks, for pairs the fixed rule sends
+ * to ray tracing and whose tet does not contain the node, the cheapest
+ * rule (BS_RULE_*) expected to meet an error budget; the fixed rule is the
+ * fallback below a softmax confidence and the judge of the labels.  The
+ * training pairs are labelled by the method itself (bs_learn_pairs).
+ *
+ * Packed blob (BS_MLP_BLOB_LEN uint16 BF16 values, in this order):
+ *   mu[16], inv_sigma[16]   feature standardisation xs = (x - mu) * inv_sigma
+ *   W1[16][64], b1[64], W2[64][64], b2[64], W3[64][4], b3[4]   (row = input)
+ * Features of a pair (x, tet with vertices v_j): c = centroid - x, d = |c|,
+ * h_T / h_min longest / shortest edge, lambda_j barycentric coordinates of
+ * x, n_f outward unit face normals, 6V the volume triple product:
+ *   d/h_T, d/hbar, h_T/h_min, hbar/d, sort_desc(lambda_j h_T/d) [4],
+ *   sort_desc(n_f . (-c/d)) [4], incident (0/1), 6V/h_T^3,
+ *   min_f dist(x, plane f)/h_T, 1. */
+#define BS_MLP_BLOB_LEN 5540
+
+/* Sample up to max_pairs (node, tet) pairs from the band the fixed rule
+ * (current policy's cut distances) ray-traces, skipping tets that contain
+ * the node: nodes are drawn without replacement (splitmix64 seeded by
+ * `seed`) and all their band pairs taken.  pairs: host [max_pairs][2]
+ * int32 (input node index, input tet index); *n_out: pairs written.
+ * Errors: BS_E_STATE (NULL mesh), BS_E_ARG. */
+int bs_learn_sample_pairs(bs_mesh *m, int64_t max_pairs, uint64_t seed, int32_t *pairs, int64_t *n_out);
+
+/* Label given pairs (host [n][2] int32, input numbering): features
+ * (device [n][16] float), relative errors of the 1-, 4- and 11-point rules
+ * against a high-accuracy value of the pair's integral (device [n][3]
+ * float; FP64 signed-cone integral with a 24 x 24 collapsed Gauss rule per
+ * face), and label = the cheapest rule with error <= tau, else BS_RULE_RT
+ * (device [n] int8).  Errors: BS_E_STATE, BS_E_ARG, BS_E_INDEX, BS_E_DEVICE. */
+int bs_learn_pairs(bs_mesh *m, const int32_t *pairs, int64_t n, double tau, float *feats, int8_t *labels,
+                   float *errs, void *stream);
+
+typedef struct {
+    int epochs;       /* passes over the data                                */
+    int batch;        /* rows per Adam step, a positive multiple of 64       */
+    float lr, beta1, beta2, eps; /* Adam                                     */
+    float class_w[4]; /* cross-entropy weight of each true class             */
+    uint64_t seed;    /* initialisation and shuffling                        */
+} bs_train_cfg;
+
+/* Train the network on n rows (feats device [n][16] float, labels device
+ * [n] int8 in 0..3): standardisation from the data, He initialisation,
+ * class-weighted softmax cross-entropy, forward and backward on the matrix
+ * cores, Adam on FP32 master weights.  blob: host output (BS_MLP_BLOB_LEN);
+ * epoch_loss: host [epochs] (may be NULL), mean weighted loss of sampled
+ * steps.  Errors: BS_E_ARG, BS_E_NOMEM, BS_E_DEVICE. */
+int bs_mlp_train(const float *feats, const int8_t *labels, int64_t n, const bs_train_cfg *cfg, uint16_t *blob,
+                 float *epoch_loss, void *stream);
+
+/* One forward and backward pass (gradient check): blob host BF16, feats /
+ * labels device, class_w host [4]; loss (host, may be NULL) = weighted mean
+ * cross-entropy; grads host [BS_MLP_BLOB_LEN - 32] FP32 gradients of
+ * W1, b1, W2, b2, W3, b3 in blob order.  Errors: BS_E_ARG, BS_E_DEVICE. */
+int bs_mlp_grad(const uint16_t *blob, const float *feats, const int8_t *labels, int64_t n, const float *class_w,
+                float *loss, float *grads, void *stream);
+
+/* Logits of the network for n rows: blob host, feats device [n][16],
+ * logits device [n][4].  Errors: BS_E_ARG, BS_E_DEVICE. */
+int bs_mlp_logits(const uint16_t *blob, const float *feats, int64_t n, float *logits, void *stream);
+
 /* Static description of a status code. */
 const char *bs_status_string(int status);
 

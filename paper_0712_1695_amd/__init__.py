@@ -93,7 +93,23 @@ class Stats(ctypes.Structure):
 
 # every symbol include/bs.h declares
 EXPORTS = ["bs_mesh_upload", "bs_mesh_update", "bs_mesh_free", "bs_policy_default", "bs_set_policy",
-           "bs_eval_velocity", "bs_advect_heun", "bs_status_string", "bs_last_error"]
+           "bs_eval_velocity", "bs_advect_heun", "bs_learn_sample_pairs", "bs_learn_pairs", "bs_mlp_train",
+           "bs_mlp_grad", "bs_mlp_logits", "bs_status_string", "bs_last_error"]
+
+BS_MLP_BLOB_LEN = 5540
+
+
+class TrainCfg(ctypes.Structure):
+    _fields_ = [
+        ("epochs", ctypes.c_int),
+        ("batch", ctypes.c_int),
+        ("lr", ctypes.c_float),
+        ("beta1", ctypes.c_float),
+        ("beta2", ctypes.c_float),
+        ("eps", ctypes.c_float),
+        ("class_w", ctypes.c_float * 4),
+        ("seed", ctypes.c_uint64),
+    ]
 
 
 class BsError(RuntimeError):
@@ -130,6 +146,16 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     L.bs_advect_heun.argtypes = [vp, ctypes.c_double, ctypes.c_int, vp, ctypes.c_uint32, vp, vp,
                                  ctypes.POINTER(Stats)]
     L.bs_advect_heun.restype = ctypes.c_int
+    L.bs_learn_sample_pairs.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64, vp, ctypes.POINTER(ctypes.c_int64)]
+    L.bs_learn_sample_pairs.restype = ctypes.c_int
+    L.bs_learn_pairs.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, vp, vp, vp, vp]
+    L.bs_learn_pairs.restype = ctypes.c_int
+    L.bs_mlp_train.argtypes = [vp, vp, ctypes.c_int64, ctypes.POINTER(TrainCfg), vp, vp, vp]
+    L.bs_mlp_train.restype = ctypes.c_int
+    L.bs_mlp_grad.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, vp, vp]
+    L.bs_mlp_grad.restype = ctypes.c_int
+    L.bs_mlp_logits.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
+    L.bs_mlp_logits.restype = ctypes.c_int
     L.bs_status_string.argtypes = [ctypes.c_int]
     L.bs_status_string.restype = ctypes.c_char_p
     L.bs_last_error.argtypes = []
@@ -291,6 +317,77 @@ def bs_advect_heun(mesh: BsMesh, dt: float, steps: int, out=None, stream=None, s
            "bs_advect_heun")
     secs = secs[: int(steps)]
     return (pos, secs, st.as_dict()) if stats else (pos, secs)
+
+
+def _dev(t, dtype_name):
+    if not (_is_torch(t) and t.is_cuda and str(t.dtype) == dtype_name and t.is_contiguous()):
+        raise ValueError(f"expected a contiguous {dtype_name} device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def bs_learn_sample_pairs(mesh: BsMesh, max_pairs: int, seed: int = 0) -> np.ndarray:
+    """Pairs (input node, input tet) of the ray-traced band, non-incident."""
+    L = load_library()
+    out = np.zeros((max(int(max_pairs), 1), 2), dtype=np.int32)
+    n = ctypes.c_int64()
+    _check(L.bs_learn_sample_pairs(mesh.handle, int(max_pairs), int(seed), ctypes.c_void_p(out.ctypes.data),
+                                   ctypes.byref(n)), "bs_learn_sample_pairs")
+    return out[: n.value]
+
+
+def bs_learn_pairs(mesh: BsMesh, pairs, tau: float, stream=None):
+    """Features, labels and Gauss-rule errors of the given pairs (device
+    tensors: float32 [n,16], int8 [n], float32 [n,3])."""
+    import torch
+
+    L = load_library()
+    pr = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    n = pr.shape[0]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    feats = torch.empty((n, 16), dtype=torch.float32, device=dev)
+    labels = torch.empty((n,), dtype=torch.int8, device=dev)
+    errs = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    _check(L.bs_learn_pairs(mesh.handle, ctypes.c_void_p(pr.ctypes.data), n, float(tau),
+                            ctypes.c_void_p(feats.data_ptr()), ctypes.c_void_p(labels.data_ptr()),
+                            ctypes.c_void_p(errs.data_ptr()), _stream_handle(stream)), "bs_learn_pairs")
+    return feats, labels, errs
+
+
+def bs_mlp_train(feats, labels, epochs=4, batch=4096, lr=2e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                 class_w=(1.0, 1.0, 1.0, 1.0), seed=0, stream=None):
+    """Train on device tensors; returns (blob uint16 [5540], epoch losses)."""
+    L = load_library()
+    cfg = TrainCfg(int(epochs), int(batch), lr, beta1, beta2, eps, (ctypes.c_float * 4)(*class_w), int(seed))
+    blob = np.zeros(BS_MLP_BLOB_LEN, dtype=np.uint16)
+    losses = np.zeros(max(int(epochs), 1), dtype=np.float32)
+    _check(L.bs_mlp_train(_dev(feats, "torch.float32"), _dev(labels, "torch.int8"), int(feats.shape[0]),
+                          ctypes.byref(cfg), ctypes.c_void_p(blob.ctypes.data), ctypes.c_void_p(losses.ctypes.data),
+                          _stream_handle(stream)), "bs_mlp_train")
+    return blob, losses[: int(epochs)]
+
+
+def bs_mlp_grad(blob, feats, labels, class_w=(1.0, 1.0, 1.0, 1.0), stream=None):
+    """(loss, gradients [5508] float32) of one forward/backward pass."""
+    L = load_library()
+    b = np.ascontiguousarray(blob, dtype=np.uint16)
+    cw = np.ascontiguousarray(class_w, dtype=np.float32)
+    grads = np.zeros(BS_MLP_BLOB_LEN - 32, dtype=np.float32)
+    loss = ctypes.c_float()
+    _check(L.bs_mlp_grad(ctypes.c_void_p(b.ctypes.data), _dev(feats, "torch.float32"), _dev(labels, "torch.int8"),
+                         int(feats.shape[0]), ctypes.c_void_p(cw.ctypes.data), ctypes.byref(loss),
+                         ctypes.c_void_p(grads.ctypes.data), _stream_handle(stream)), "bs_mlp_grad")
+    return float(loss.value), grads
+
+
+def bs_mlp_logits(blob, feats, stream=None):
+    import torch
+
+    L = load_library()
+    b = np.ascontiguousarray(blob, dtype=np.uint16)
+    out = torch.empty((feats.shape[0], 4), dtype=torch.float32, device=feats.device)
+    _check(L.bs_mlp_logits(ctypes.c_void_p(b.ctypes.data), _dev(feats, "torch.float32"), int(feats.shape[0]),
+                           ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)), "bs_mlp_logits")
+    return out
 
 
 def status_string(status: int) -> str:

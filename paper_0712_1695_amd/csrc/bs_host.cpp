@@ -14,6 +14,7 @@
 //   integrate the half sphere to 1/2).  Each line gives two rays, +s and -s,
 //   both with weight k_nm.
 #include "bs_internal.h"
+#include "bs_learn.h"
 
 #include "../../include/bs.h"
 
@@ -218,6 +219,9 @@ struct bs_mesh {
     double hbar = 0.0, max_vc = 0.0;
     int64_t reoriented = 0;
     std::vector<int8_t> orient; // sign of det per tet at upload (inversion check on updates)
+    std::vector<int32_t> h_rank, h_order, h_cell_start; // node rank, tet order, bins (host copies)
+    std::vector<float> h_cen32;                         // binary32 centroids, input tet order
+    std::vector<float> h_xh;                            // binary32 node coordinates, input node order
     bsk::Bins bins{};
     // device buffers
     DBuf xh, xl, om, blk, node_orig, g1, g4, g11, tid, cell_start;
@@ -227,6 +231,7 @@ struct bs_mesh {
     // policy
     bs_policy pol{};
     int ang_N = 0, ang_M = 0;
+    DBuf mlp; // BF16 network blob of the learned policy
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
@@ -455,6 +460,13 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
         for (int64_t t = 0; t < T; ++t) order[(size_t)fill[(size_t)cell_of[(size_t)t]]++] = (int32_t)t;
     }
 
+    m->h_rank = rank;
+    m->h_order = order;
+    m->h_cell_start = cell_start;
+    m->h_cen32 = cen32;
+    m->h_xh.resize((size_t)(3 * n));
+    for (int64_t i = 0; i < 3 * n; ++i) m->h_xh[(size_t)i] = (float)X[i];
+
     // ---- per-tet records in bin order
     std::vector<float> g1((size_t)T * 8), g4((size_t)T * 32), g11((size_t)T * 88);
     std::vector<int4> tid((size_t)T);
@@ -635,8 +647,12 @@ int check_policy(const bs_policy *p)
         return fail(BS_E_POLICY, "gauss_rule must be BS_RULE_G1, _G4 or _G11");
     if (p->precision < BS_PREC_FP32_NAIVE || p->precision > BS_PREC_FP64)
         return fail(BS_E_POLICY, "unknown precision %d", p->precision);
-    if (p->kind == BS_POLICY_LEARNED)
-        return fail(BS_E_POLICY, "the learned policy needs the network entry points");
+    if (p->kind == BS_POLICY_LEARNED) {
+        if (!p->mlp_bf16 || p->mlp_len != bsk::kMlpBlobLen)
+            return fail(BS_E_POLICY, "learned policy needs a weight blob of %d values (got %lld)", bsk::kMlpBlobLen,
+                        (long long)p->mlp_len);
+        if (!(p->conf_min >= 0.f && p->conf_min <= 1.f)) return fail(BS_E_POLICY, "conf_min must lie in [0, 1]");
+    }
     return BS_OK;
 }
 
@@ -773,7 +789,7 @@ void bs_mesh_free(bs_mesh *m)
     if (!m) return;
     DBuf *bufs[] = {&m->xh, &m->xl, &m->om, &m->blk, &m->node_orig, &m->g1, &m->g4, &m->g11, &m->tid,
                     &m->cell_start, &m->part, &m->band, &m->rtv, &m->vel, &m->cnt, &m->nonfinite, &m->dir,
-                    &m->dir64, &m->cphi, &m->dia};
+                    &m->dir64, &m->cphi, &m->dia, &m->mlp};
     for (DBuf *b : bufs) dfree(*b);
     for (auto &e : m->ev)
         if (e) (void)hipEventDestroy(e);
@@ -787,6 +803,11 @@ int bs_set_policy(bs_mesh *m, const bs_policy *p)
     if (!p) return fail(BS_E_ARG, "null policy");
     int rc = check_policy(p);
     if (rc) return rc;
+    if (p->kind == BS_POLICY_LEARNED) {
+        if ((rc = dalloc(m->mlp, 2 * bsk::kMlpBlobLen))) return rc;
+        hipError_t e = hipMemcpy(m->mlp.p, p->mlp_bf16, 2 * bsk::kMlpBlobLen, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "upload network");
+    }
     m->pol = *p;
     m->pol.mlp_bf16 = nullptr;
     return BS_OK;
@@ -807,7 +828,8 @@ int eval_device(bs_mesh *m, hipStream_t s)
     // tet splits of the all-pairs Gauss kernel: enough waves to fill 256 CUs
     const int node_blocks = m->npad / 1024;
     int splits = 0;
-    const bool gauss_all = P.kind == BS_POLICY_FIXED || P.kind == BS_POLICY_GAUSS_ONLY;
+    const bool fixed_like = P.kind == BS_POLICY_FIXED || P.kind == BS_POLICY_LEARNED;
+    const bool gauss_all = fixed_like || P.kind == BS_POLICY_GAUSS_ONLY;
     if (gauss_all && m->T > 0) {
         splits = std::max(1, std::min<int>((int)((4096 + 4 * node_blocks - 1) / (4 * node_blocks)),
                                            (int)((m->T + 255) / 256)));
@@ -842,21 +864,26 @@ int eval_device(bs_mesh *m, hipStream_t s)
             if ((e = bsk::launch_gauss_all(dm, pts, P.precision, splits, (double *)m->part.p, s)))
                 return hip_fail(e, "gauss kernel");
             part = (const double *)m->part.p;
-        } else if (P.kind == BS_POLICY_FIXED) {
+        } else if (fixed_like) {
             if ((e = bsk::launch_gauss_all(dm, 1, P.precision, splits, (double *)m->part.p, s)))
                 return hip_fail(e, "far-field kernel");
             part = (const double *)m->part.p;
         }
     }
     (void)hipEventRecord(m->ev[1], s);
-    if (m->T > 0 && P.kind == BS_POLICY_FIXED) {
+    if (m->T > 0 && fixed_like) {
         if ((e = bsk::launch_band(dm, th, P.precision, (double *)m->band.p, cnt, s)))
             return hip_fail(e, "band kernel");
         band = (const double *)m->band.p;
     }
     (void)hipEventRecord(m->ev[2], s);
-    if (m->T > 0 && (P.kind == BS_POLICY_FIXED || P.kind == BS_POLICY_PURE_RT)) {
-        if ((e = bsk::launch_rt(dm, th, ang, P.kind == BS_POLICY_PURE_RT, P.precision, (double *)m->rtv.p, cnt, s)))
+    bsk::LearnParams lp{};
+    lp.w = P.kind == BS_POLICY_LEARNED ? (const __bf16 *)m->mlp.p : nullptr;
+    lp.conf_min = P.conf_min;
+    lp.hbar = (float)m->hbar;
+    if (m->T > 0 && (fixed_like || P.kind == BS_POLICY_PURE_RT)) {
+        if ((e = bsk::launch_rt(dm, th, ang, lp, P.kind == BS_POLICY_PURE_RT, P.precision, (double *)m->rtv.p, cnt,
+                                s)))
             return hip_fail(e, "ray-tracing kernel");
         rtv = (const double *)m->rtv.p;
     }
@@ -887,11 +914,14 @@ int read_stats(bs_mesh *m, bs_stats *st)
         st->t_kernel_s[k] = mk * 1e-3;
     }
     st->pairs = m->n * m->T;
-    if (P.kind == BS_POLICY_FIXED) {
-        st->pairs_by_rule[BS_RULE_G4] = (int64_t)c[0];
-        st->pairs_by_rule[BS_RULE_G11] = (int64_t)c[1];
+    if (P.kind == BS_POLICY_FIXED || P.kind == BS_POLICY_LEARNED) {
+        // c[2] counts the pairs actually ray traced; the learned selector's
+        // moves out of the ray-traced band are c[5..7]
+        st->pairs_by_rule[BS_RULE_G4] = (int64_t)(c[0] + c[6]);
+        st->pairs_by_rule[BS_RULE_G11] = (int64_t)(c[1] + c[7]);
         st->pairs_by_rule[BS_RULE_RT] = (int64_t)c[2];
-        st->pairs_by_rule[BS_RULE_G1] = st->pairs - (int64_t)(c[0] + c[1] + c[2]);
+        st->pairs_by_rule[BS_RULE_G1] = st->pairs - st->pairs_by_rule[BS_RULE_G4] - st->pairs_by_rule[BS_RULE_G11] -
+                                        st->pairs_by_rule[BS_RULE_RT];
     } else if (P.kind == BS_POLICY_PURE_RT) {
         st->pairs_by_rule[BS_RULE_RT] = st->pairs;
     } else {
@@ -993,6 +1023,331 @@ int bs_advect_heun(bs_mesh *m, double dt, int steps, double *xyz_out, uint32_t f
         if ((rc = read_stats(m, st))) return rc;
         st->t_eval_s = t_dev;
     }
+    return BS_OK;
+}
+
+} // extern "C"
+
+// =============================================================== rule selector
+namespace {
+
+// binary32 rule decision on the host, identical to the kernels' (no FMA:
+// this file is built without contraction)
+int host_rule(const float *x, const float *c, bool inc, float rt2, float g11_2, float g4_2)
+{
+    const float dx = x[0] - c[0], dy = x[1] - c[1], dz = x[2] - c[2];
+    const float sx = dx * dx, sy = dy * dy, sz = dz * dz;
+    const float d2 = (sx + sy) + sz;
+    int rule = d2 < g4_2 ? BS_RULE_G4 : BS_RULE_G1;
+    rule = d2 < g11_2 ? BS_RULE_G11 : rule;
+    return (inc || d2 < rt2) ? BS_RULE_RT : rule;
+}
+
+void thresholds(const bs_mesh *m, float *rt2, float *g11_2, float *g4_2)
+{
+    const double hb = m->hbar;
+    const double c_rt = m->pol.near_cut * hb, c_11 = m->pol.d_g11 * hb, c_4 = m->pol.d_g4 * hb;
+    *rt2 = (float)(c_rt * c_rt);
+    *g11_2 = (float)(c_11 * c_11);
+    *g4_2 = (float)(c_4 * c_4);
+}
+
+uint64_t splitmix(uint64_t &s)
+{
+    uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+double uniform01(uint64_t &s) { return (double)(splitmix(s) >> 11) * (1.0 / 9007199254740992.0); }
+
+// collapsed Gauss rule on the reference triangle: (u, v, weight), q x q points
+std::vector<double> triangle_rule(int q)
+{
+    std::vector<double> t, w;
+    gauss_legendre(q, t, w);
+    std::vector<double> out;
+    for (int i = 0; i < q; ++i)
+        for (int j = 0; j < q; ++j) {
+            const double a = 0.5 * (t[(size_t)i] + 1.0), b = 0.5 * (t[(size_t)j] + 1.0);
+            out.push_back(a * (1.0 - b));
+            out.push_back(a * b);
+            out.push_back(0.25 * w[(size_t)i] * w[(size_t)j] * a);
+        }
+    return out;
+}
+
+} // namespace
+
+extern "C" {
+
+int bs_learn_sample_pairs(bs_mesh *m, int64_t max_pairs, uint64_t seed, int32_t *pairs, int64_t *n_out)
+{
+    g_err.clear();
+    if (!m) return fail(BS_E_STATE, "null mesh");
+    if (!pairs || !n_out || max_pairs < 0) return fail(BS_E_ARG, "null output or negative count");
+    float rt2, g11_2, g4_2;
+    thresholds(m, &rt2, &g11_2, &g4_2);
+    const double R = std::max(std::sqrt((double)rt2), m->max_vc) * (1.0 + 1e-4) + 1e-6;
+    std::vector<int32_t> nodes((size_t)m->n);
+    for (int64_t i = 0; i < m->n; ++i) nodes[(size_t)i] = (int32_t)i;
+    uint64_t st = seed;
+    int64_t k = 0;
+    const bsk::Bins &b = m->bins;
+    for (int64_t a = 0; a < m->n && k < max_pairs; ++a) {
+        // draw the next node without replacement
+        const int64_t j = a + (int64_t)(uniform01(st) * (double)(m->n - a));
+        std::swap(nodes[(size_t)a], nodes[(size_t)std::min(j, m->n - 1)]);
+        const int32_t i = nodes[(size_t)a];
+        const float *x = &m->h_xh[3 * (size_t)i];
+        int lo[3], hi[3];
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = std::max(0, (int)std::floor((x[c] - R - b.lo[c]) / b.cs));
+            hi[c] = std::min(b.dim[c] - 1, (int)std::floor((x[c] + R - b.lo[c]) / b.cs));
+        }
+        for (int iz = lo[2]; iz <= hi[2]; ++iz)
+            for (int iy = lo[1]; iy <= hi[1]; ++iy) {
+                const int row = (iz * b.dim[1] + iy) * b.dim[0];
+                for (int32_t s = m->h_cell_start[(size_t)(row + lo[0])];
+                     s < m->h_cell_start[(size_t)(row + hi[0] + 1)] && k < max_pairs; ++s) {
+                    const int32_t t = m->h_order[(size_t)s];
+                    const int32_t *id = &m->tets[4 * (size_t)t];
+                    const bool inc = id[0] == i || id[1] == i || id[2] == i || id[3] == i;
+                    if (inc) continue;
+                    if (host_rule(x, &m->h_cen32[3 * (size_t)t], false, rt2, g11_2, g4_2) != BS_RULE_RT) continue;
+                    pairs[2 * k] = i;
+                    pairs[2 * k + 1] = t;
+                    ++k;
+                }
+            }
+    }
+    *n_out = k;
+    return BS_OK;
+}
+
+int bs_learn_pairs(bs_mesh *m, const int32_t *pairs, int64_t n, double tau, float *feats, int8_t *labels,
+                   float *errs, void *stream)
+{
+    g_err.clear();
+    if (!m) return fail(BS_E_STATE, "null mesh");
+    if (n < 0 || (n > 0 && (!pairs || !feats || !labels || !errs))) return fail(BS_E_ARG, "null array");
+    if (n > (int64_t)1 << 30) return fail(BS_E_ARG, "too many pairs");
+    if (!(tau >= 0)) return fail(BS_E_ARG, "tau must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int2> pr((size_t)n);
+    // input numbering -> sorted node rank and sorted tet slot
+    std::vector<int32_t> slot((size_t)m->T);
+    for (int64_t k = 0; k < m->T; ++k) slot[(size_t)m->h_order[(size_t)k]] = (int32_t)k;
+    for (int64_t k = 0; k < n; ++k) {
+        const int32_t i = pairs[2 * k], t = pairs[2 * k + 1];
+        if (i < 0 || i >= m->n || t < 0 || t >= m->T) return fail(BS_E_INDEX, "pair %lld out of range", (long long)k);
+        pr[(size_t)k] = make_int2(m->h_rank[(size_t)i], slot[(size_t)t]);
+    }
+    const std::vector<double> tri = triangle_rule(24);
+    std::vector<float> rules(80, 0.f);
+    {
+        int q = 0;
+        for (int k : {1, 4, 11}) {
+            const TetRule r = tet_rule(k);
+            for (int p = 0; p < r.n; ++p, ++q) {
+                for (int j = 0; j < 4; ++j) rules[(size_t)(4 * q + j)] = (float)r.lam[p][j];
+                rules[(size_t)(64 + q)] = (float)r.w[p];
+            }
+        }
+    }
+    DBuf dpr, dtri, drules;
+    int rc;
+    if ((rc = dalloc(dpr, sizeof(int2) * (size_t)std::max<int64_t>(n, 1))) ||
+        (rc = dalloc(dtri, 8 * tri.size())) || (rc = dalloc(drules, 4 * rules.size())))
+        return rc;
+    hipError_t e;
+    if ((n > 0 && (e = hipMemcpyAsync(dpr.p, pr.data(), sizeof(int2) * (size_t)n, hipMemcpyHostToDevice, s))) ||
+        (e = hipMemcpyAsync(dtri.p, tri.data(), 8 * tri.size(), hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(drules.p, rules.data(), 4 * rules.size(), hipMemcpyHostToDevice, s)) ||
+        (e = bsk::launch_label(dev_view(m), (const int2 *)dpr.p, (int)n, (float)m->hbar, (const double *)dtri.p,
+                               (int)(tri.size() / 3), (const float *)drules.p, tau, feats, labels, errs, s)) ||
+        (e = hipStreamSynchronize(s))) {
+        dfree(dpr);
+        dfree(dtri);
+        dfree(drules);
+        return hip_fail(e, "label kernel");
+    }
+    dfree(dpr);
+    dfree(dtri);
+    dfree(drules);
+    return BS_OK;
+}
+
+static uint16_t f32_to_bf16(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+static float bf16_to_f32(uint16_t h)
+{
+    const uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// shared scratch of the training entry points
+struct TrainBufs {
+    DBuf wb, master, m1, m2, gpart, wpart, lpart, cw, index, gout, lsum;
+    ~TrainBufs()
+    {
+        for (DBuf *b : {&wb, &master, &m1, &m2, &gpart, &wpart, &lpart, &cw, &index, &gout, &lsum}) dfree(*b);
+    }
+};
+
+int bs_mlp_grad(const uint16_t *blob, const float *feats, const int8_t *labels, int64_t n, const float *class_w,
+                float *loss, float *grads, void *stream)
+{
+    g_err.clear();
+    if (!blob || !feats || !labels || !class_w || !grads || n <= 0 || n > (1 << 26))
+        return fail(BS_E_ARG, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    const int nb = (int)((n + 63) / 64);
+    TrainBufs B;
+    int rc;
+    if ((rc = dalloc(B.wb, 2 * bsk::kMlpBlobLen)) || (rc = dalloc(B.gpart, 4 * (size_t)nb * bsk::kMlpGradLen)) ||
+        (rc = dalloc(B.wpart, 4 * (size_t)nb)) || (rc = dalloc(B.lpart, 4 * (size_t)nb)) ||
+        (rc = dalloc(B.cw, 16)) || (rc = dalloc(B.gout, 4 * bsk::kMlpGradLen)) || (rc = dalloc(B.lsum, 16)) ||
+        (rc = dalloc(B.master, 4 * bsk::kMlpGradLen)) || (rc = dalloc(B.m1, 4 * bsk::kMlpGradLen)) ||
+        (rc = dalloc(B.m2, 4 * bsk::kMlpGradLen)))
+        return rc;
+    hipError_t e;
+    double sums[2] = {0, 0};
+    if ((e = hipMemcpyAsync(B.wb.p, blob, 2 * bsk::kMlpBlobLen, hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(B.cw.p, class_w, 16, hipMemcpyHostToDevice, s)) ||
+        (e = bsk::launch_mlp_grad_step(feats, labels, nullptr, (int)n, (__bf16 *)B.wb.p, (const float *)B.cw.p,
+                                       (float *)B.gpart.p, (float *)B.wpart.p, (float *)B.lpart.p,
+                                       (float *)B.master.p, (float *)B.m1.p, (float *)B.m2.p, 0.f, 0.9f, 0.999f,
+                                       1e-8f, 1, (float *)B.gout.p, s)) ||
+        (e = bsk::launch_sum_f((const float *)B.lpart.p, nb, (double *)B.lsum.p, s)) ||
+        (e = bsk::launch_sum_f((const float *)B.wpart.p, nb, (double *)B.lsum.p + 1, s)) ||
+        (e = hipMemcpyAsync(grads, B.gout.p, 4 * bsk::kMlpGradLen, hipMemcpyDeviceToHost, s)) ||
+        (e = hipMemcpyAsync(sums, B.lsum.p, 16, hipMemcpyDeviceToHost, s)) || (e = hipStreamSynchronize(s)))
+        return hip_fail(e, "gradient kernels");
+    if (loss) *loss = (float)(sums[1] > 0 ? sums[0] / sums[1] : 0.0);
+    return BS_OK;
+}
+
+int bs_mlp_train(const float *feats, const int8_t *labels, int64_t n, const bs_train_cfg *cfg, uint16_t *blob,
+                 float *epoch_loss, void *stream)
+{
+    g_err.clear();
+    if (!feats || !labels || !cfg || !blob || n <= 0 || n > (1 << 28) || cfg->epochs < 0 || cfg->batch < 64 ||
+        cfg->batch % 64)
+        return fail(BS_E_ARG, "bad arguments (batch must be a positive multiple of 64)");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    // feature standardisation from the training set (FP64 on the host)
+    std::vector<float> hf((size_t)n * 16);
+    if ((e = hipMemcpy(hf.data(), feats, 4 * hf.size(), hipMemcpyDeviceToHost)))
+        return hip_fail(e, "read features");
+    double mu[16] = {0}, var[16] = {0};
+    for (int64_t i = 0; i < n; ++i)
+        for (int q = 0; q < 16; ++q) mu[q] += hf[(size_t)i * 16 + q];
+    for (int q = 0; q < 16; ++q) mu[q] /= (double)n;
+    for (int64_t i = 0; i < n; ++i)
+        for (int q = 0; q < 16; ++q) {
+            const double d = hf[(size_t)i * 16 + q] - mu[q];
+            var[q] += d * d;
+        }
+    std::vector<uint16_t> wb(bsk::kMlpBlobLen);
+    for (int q = 0; q < 16; ++q) {
+        const double sd = std::sqrt(var[q] / (double)n);
+        wb[(size_t)q] = f32_to_bf16((float)mu[q]);
+        wb[(size_t)(16 + q)] = f32_to_bf16(sd > 1e-6 ? (float)(1.0 / sd) : 0.f);
+    }
+    // He initialisation (Box-Muller on splitmix64), zero biases
+    std::vector<float> master(bsk::kMlpGradLen, 0.f);
+    uint64_t st = cfg->seed;
+    auto gauss = [&]() {
+        const double u1 = std::max(uniform01(st), 1e-300), u2 = uniform01(st);
+        return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+    };
+    const int offs[3] = {0, 1024 + 64, 1024 + 64 + 4096 + 64};
+    const int fan[3] = {16, 64, 64}, cnt[3] = {1024, 4096, 256};
+    for (int L = 0; L < 3; ++L)
+        for (int k = 0; k < cnt[L]; ++k) master[(size_t)(offs[L] + k)] = (float)(gauss() * std::sqrt(2.0 / fan[L]));
+    for (int j = 0; j < bsk::kMlpGradLen; ++j) wb[(size_t)(32 + j)] = f32_to_bf16(master[(size_t)j]);
+    const int bsz = cfg->batch, nb = bsz / 64;
+    TrainBufs B;
+    int rc;
+    if ((rc = dalloc(B.wb, 2 * bsk::kMlpBlobLen)) || (rc = dalloc(B.master, 4 * bsk::kMlpGradLen)) ||
+        (rc = dalloc(B.m1, 4 * bsk::kMlpGradLen)) || (rc = dalloc(B.m2, 4 * bsk::kMlpGradLen)) ||
+        (rc = dalloc(B.gpart, 4 * (size_t)nb * bsk::kMlpGradLen)) || (rc = dalloc(B.wpart, 4 * (size_t)nb)) ||
+        (rc = dalloc(B.lpart, 4 * (size_t)nb)) || (rc = dalloc(B.cw, 16)) || (rc = dalloc(B.index, 4 * (size_t)n)) ||
+        (rc = dalloc(B.lsum, 16)))
+        return rc;
+    if ((e = hipMemcpyAsync(B.wb.p, wb.data(), 2 * wb.size(), hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(B.master.p, master.data(), 4 * master.size(), hipMemcpyHostToDevice, s)) ||
+        (e = hipMemsetAsync(B.m1.p, 0, 4 * bsk::kMlpGradLen, s)) ||
+        (e = hipMemsetAsync(B.m2.p, 0, 4 * bsk::kMlpGradLen, s)) ||
+        (e = hipMemcpyAsync(B.cw.p, cfg->class_w, 16, hipMemcpyHostToDevice, s)))
+        return hip_fail(e, "training setup");
+    std::vector<int32_t> perm((size_t)n);
+    for (int64_t i = 0; i < n; ++i) perm[(size_t)i] = (int32_t)i;
+    int step = 0;
+    for (int ep = 0; ep < cfg->epochs; ++ep) {
+        for (int64_t i = n - 1; i > 0; --i) {
+            const int64_t j = (int64_t)(uniform01(st) * (double)(i + 1));
+            std::swap(perm[(size_t)i], perm[(size_t)std::min(j, i)]);
+        }
+        if ((e = hipMemcpyAsync(B.index.p, perm.data(), 4 * (size_t)n, hipMemcpyHostToDevice, s)))
+            return hip_fail(e, "upload permutation");
+        double lsum = 0.0, wsum = 0.0;
+        for (int64_t b0 = 0; b0 + bsz <= n; b0 += bsz) {
+            ++step;
+            if ((e = bsk::launch_mlp_grad_step(feats, labels, (const int *)B.index.p + b0, bsz, (__bf16 *)B.wb.p,
+                                               (const float *)B.cw.p, (float *)B.gpart.p, (float *)B.wpart.p,
+                                               (float *)B.lpart.p, (float *)B.master.p, (float *)B.m1.p,
+                                               (float *)B.m2.p, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, step,
+                                               nullptr, s)))
+                return hip_fail(e, "training step");
+            if (epoch_loss && (b0 / bsz) % 64 == 0) {
+                double sums[2];
+                if ((e = bsk::launch_sum_f((const float *)B.lpart.p, nb, (double *)B.lsum.p, s)) ||
+                    (e = bsk::launch_sum_f((const float *)B.wpart.p, nb, (double *)B.lsum.p + 1, s)) ||
+                    (e = hipMemcpyAsync(sums, B.lsum.p, 16, hipMemcpyDeviceToHost, s)) ||
+                    (e = hipStreamSynchronize(s)))
+                    return hip_fail(e, "training loss");
+                lsum += sums[0];
+                wsum += sums[1];
+            }
+        }
+        if (epoch_loss) epoch_loss[ep] = (float)(wsum > 0 ? lsum / wsum : 0.0);
+    }
+    if ((e = hipMemcpyAsync(wb.data(), B.wb.p, 2 * wb.size(), hipMemcpyDeviceToHost, s)) ||
+        (e = hipStreamSynchronize(s)))
+        return hip_fail(e, "read weights");
+    std::memcpy(blob, wb.data(), 2 * wb.size());
+    return BS_OK;
+}
+
+int bs_mlp_logits(const uint16_t *blob, const float *feats, int64_t n, float *logits, void *stream)
+{
+    g_err.clear();
+    if (!blob || !feats || !logits || n < 0 || n > (1 << 28)) return fail(BS_E_ARG, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    DBuf wb;
+    int rc = dalloc(wb, 2 * bsk::kMlpBlobLen);
+    if (rc) return rc;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(wb.p, blob, 2 * bsk::kMlpBlobLen, hipMemcpyHostToDevice, s)) ||
+        (e = bsk::launch_mlp_logits(feats, (int)n, (const __bf16 *)wb.p, logits, s)) ||
+        (e = hipStreamSynchronize(s))) {
+        dfree(wb);
+        return hip_fail(e, "logits kernel");
+    }
+    dfree(wb);
     return BS_OK;
 }
 

@@ -51,6 +51,14 @@ struct AngTab {
     int N, M2;            // rows, columns (2M)
 };
 
+// Learned rule selector: BF16 weight blob (device), softmax confidence
+// threshold, mean edge length (feature scale).  w == nullptr: fixed rule.
+struct LearnParams {
+    const __bf16 *w;
+    float conf_min;
+    float hbar;
+};
+
 struct DevMesh {
     int n, npad, T, nblk;
     const float *xh, *xl, *om;
@@ -62,7 +70,8 @@ struct DevMesh {
 };
 
 // Counters accumulated by the kernels (device, 64-bit):
-// [0] G4 pairs, [1] G11 pairs, [2] RT pairs, [3] RT hit lines, [4] FP64 retests
+// [0] G4 pairs, [1] G11 pairs, [2] RT pairs, [3] RT hit lines, [4] FP64 retests,
+// [5..7] pairs the learned selector moved from RT to G1 / G4 / G11
 constexpr int kNumCounters = 8;
 
 // Launchers (return hipSuccess or the launch error).
@@ -70,8 +79,8 @@ hipError_t launch_gauss_all(const DevMesh &m, int rule_pts, int precision, int s
                             hipStream_t s);
 hipError_t launch_band(const DevMesh &m, const Thresholds &th, int precision, double *band,
                        unsigned long long *cnt, hipStream_t s);
-hipError_t launch_rt(const DevMesh &m, const Thresholds &th, const AngTab &ang, int all_pairs, int precision,
-                     double *rtv, unsigned long long *cnt, hipStream_t s);
+hipError_t launch_rt(const DevMesh &m, const Thresholds &th, const AngTab &ang, const LearnParams &lp,
+                     int all_pairs, int precision, double *rtv, unsigned long long *cnt, hipStream_t s);
 hipError_t launch_combine(const DevMesh &m, const int *node_orig, const double *part, int splits,
                           const double *band, const double *rtv, double *vel, int *nonfinite, hipStream_t s);
 

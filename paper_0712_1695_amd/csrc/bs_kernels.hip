@@ -30,6 +30,7 @@
 //   k_rt         one wave per node: ray tracing of its near tetrahedra;
 //   k_combine    FP64 sum of the partials, back to input node order.
 #include "bs_internal.h"
+#include "bs_mlp_dev.h"
 
 #include <hip/hip_runtime.h>
 
@@ -450,7 +451,16 @@ struct RtLds {
     int ncol[64];      // columns per row
     int pref[64];      // inclusive prefix sum of the item counts
     int ids[4][64];    // vertex node ids (for the FP64 retest)
-    int list[128];     // pending ray-traced tets
+};
+
+// LDS of k_rt: the pending list, and either one batch's pair data or the
+// network's scratch (never live together).
+struct RtShared {
+    union {
+        RtLds b;
+        InferLds n;
+    } u;
+    int list[128]; // pending ray-traced tets
 };
 
 __device__ __forceinline__ float diamond(float c, float s)
@@ -776,12 +786,30 @@ struct RtAcc {
 
 // One batch of mcount (<= 64) listed tets: setup, then all candidate rays.
 template <int PREC>
-__device__ __forceinline__ void rt_batch(const DevMesh &m, const AngTab &ang, RtLds &L, int mcount, int lane,
-                                         int self, const float *xhv, const float *xlv, const float *omx,
+__device__ __forceinline__ void acc_add(RtAcc &A, float a0, float a1, float a2)
+{
+    if (PREC == 0) {
+        A.ax += a0;
+        A.ay += a1;
+        A.az += a2;
+    } else if (PREC == 1) {
+        two_sum(A.sx, A.cx, a0);
+        two_sum(A.sy, A.cy, a1);
+        two_sum(A.sz, A.cz, a2);
+    } else {
+        A.dx += (double)a0;
+        A.dy += (double)a1;
+        A.dz += (double)a2;
+    }
+}
+
+template <int PREC>
+__device__ __forceinline__ void rt_batch(const DevMesh &m, const AngTab &ang, RtLds &L, const int *list, int mcount,
+                                         int lane, int self, const float *xhv, const float *xlv, const float *omx,
                                          RtAcc &A)
 {
     int cntp = 0;
-    if (lane < mcount) cntp = rt_setup(m, ang, L, lane, L.list[lane], self, xhv, xlv);
+    if (lane < mcount) cntp = rt_setup(m, ang, L, lane, list[lane], self, xhv, xlv);
     const int incl = wave_incl_scan(cntp, lane);
     L.pref[lane] = incl;
     __syncthreads();
@@ -806,30 +834,76 @@ __device__ __forceinline__ void rt_batch(const DevMesh &m, const AngTab &ang, Rt
             const int l = (L.rows[p] + row) * ang.M2 + col;
             float a0 = 0.f, a1 = 0.f, a2 = 0.f;
             A.hits += rt_item(m, ang, L, p, l, omx, xhv, xlv, a0, a1, a2, A.retests);
-            if (PREC == 0) {
-                A.ax += a0;
-                A.ay += a1;
-                A.az += a2;
-            } else if (PREC == 1) {
-                two_sum(A.sx, A.cx, a0);
-                two_sum(A.sy, A.cy, a1);
-                two_sum(A.sz, A.cz, a2);
-            } else {
-                A.dx += (double)a0;
-                A.dy += (double)a1;
-                A.dz += (double)a2;
-            }
+            acc_add<PREC>(A, a0, a1, a2);
         }
     }
     A.pairs += mcount;
     __syncthreads();
 }
 
+// Learned rule choice for the pairs of one scan step (lane = tet t): the
+// network picks a rule for pairs the fixed rule ray-traces whose tet does
+// not contain the node; below conf_min softmax confidence the pair stays
+// ray traced.  Pairs given a Gauss rule are evaluated here (the band kernel
+// removed their 1-point term, as for any ray-traced pair).  Returns the
+// pair's final rule.
 template <int PREC>
-__global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang, int all_pairs,
+__device__ __forceinline__ int learned_rule(const DevMesh &m, const LearnParams &lp, InferLds &L, int lane, int t,
+                                            bool cand, int self, const float *xhv, const float *xlv, RtAcc &A,
+                                            unsigned long long *n_by_rule)
+{
+    const __bf16 *W = lp.w;
+    const __bf16 *mu = W, *isg = W + 16, *W1 = W + 32, *b1 = W1 + 1024, *W2 = b1 + 64, *b2 = W2 + 4096,
+                 *W3 = b2 + 64, *b3 = W3 + 256;
+    const int4 id4 = m.tid[t];
+    const int id[4] = {id4.x, id4.y, id4.z, id4.w};
+    float a[4][3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            a[j][c] = (m.xh[c * m.npad + id[j]] - xhv[c]) + (m.xl[c * m.npad + id[j]] - xlv[c]);
+    float f[16];
+    pair_features(a, lp.hbar, false, f);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) L.x[lane][q] = (__bf16)(cand ? (f[q] - (float)mu[q]) * (float)isg[q] : 0.f);
+    __syncthreads();
+    mlp_forward_tile(L, W1, b1, W2, b2, W3, b3, lane);
+    int rule = RULE_RT;
+    if (cand) {
+        float z[4], zm = -3e38f;
+        int arg = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            z[c] = L.z3[lane][c];
+            if (z[c] >= zm) { // ties go to the more expensive rule
+                zm = z[c];
+                arg = c;
+            }
+        }
+        float se = 0.f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) se += __expf(z[c] - zm);
+        if (1.0f / se >= lp.conf_min) rule = arg;
+        if (rule != RULE_RT) {
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+            const int np = rule == RULE_G1 ? 1 : rule == RULE_G4 ? 4 : 11;
+            const float *g = rule == RULE_G1 ? m.g1 + (size_t)t * kRecG
+                             : rule == RULE_G4 ? m.g4 + (size_t)t * 4 * kRecG : m.g11 + (size_t)t * 11 * kRecG;
+            for (int q = 0; q < np; ++q) gauss_point(xhv[0], xhv[1], xhv[2], g + q * kRecG, a0, a1, a2);
+            acc_add<PREC>(A, a0, a1, a2);
+            ++n_by_rule[rule];
+        }
+    }
+    __syncthreads();
+    return rule;
+}
+
+template <int PREC, bool LEARNED>
+__global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang, LearnParams lp, int all_pairs,
                                            double *__restrict__ rtv, unsigned long long *__restrict__ cnt)
 {
-    __shared__ RtLds L;
+    __shared__ RtShared S;
     const int lane = threadIdx.x;
     const int self = blockIdx.x;
     float xhv[3], xlv[3], omx[3];
@@ -844,6 +918,7 @@ __global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang,
     A.dx = A.dy = A.dz = 0.0;
     A.pairs = A.hits = 0;
     A.retests = 0;
+    unsigned long long n_by_rule[3] = {0, 0, 0};
     int nlist = 0; // uniform
 
     RowIter rows(m, xhv[0], xhv[1], xhv[2], th.r_rt);
@@ -852,32 +927,40 @@ __global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang,
     while (have) {
         for (int b0 = t0; b0 < t1; b0 += 64) {
             const int t = b0 + lane;
-            bool is_rt = false;
+            bool is_rt = false, inc = false;
             if (t < t1) {
+                const int4 id = m.tid[t];
+                inc = (id.x == self) | (id.y == self) | (id.z == self) | (id.w == self);
                 if (all_pairs) is_rt = true;
                 else {
                     const float *g = m.g1 + (size_t)t * kRecG;
-                    is_rt = fixed_rule(xhv[0], xhv[1], xhv[2], g[0], g[1], g[2], m.tid[t], self, th) == RULE_RT;
+                    is_rt = fixed_rule(xhv[0], xhv[1], xhv[2], g[0], g[1], g[2], id, self, th) == RULE_RT;
                 }
+            }
+            if (LEARNED) {
+                const bool cand = is_rt && !inc;
+                if (__ballot(cand))
+                    is_rt = learned_rule<PREC>(m, lp, S.u.n, lane, t < t1 ? t : t0, cand, self, xhv, xlv, A,
+                                               n_by_rule) == RULE_RT && is_rt;
             }
             const unsigned long long mask = __ballot(is_rt);
             const int pos = nlist + __popcll(mask & ((1ull << lane) - 1ull));
-            if (is_rt) L.list[pos] = t;
+            if (is_rt) S.list[pos] = t;
             nlist += __popcll(mask);
             __syncthreads();
             if (nlist >= 64) {
-                rt_batch<PREC>(m, ang, L, 64, lane, self, xhv, xlv, omx, A);
+                rt_batch<PREC>(m, ang, S.u.b, S.list, 64, lane, self, xhv, xlv, omx, A);
                 const int rest = nlist - 64;
-                const int keep = lane < rest ? L.list[64 + lane] : 0;
+                const int keep = lane < rest ? S.list[64 + lane] : 0;
                 __syncthreads();
-                if (lane < rest) L.list[lane] = keep;
+                if (lane < rest) S.list[lane] = keep;
                 __syncthreads();
                 nlist = rest;
             }
         }
         have = all_pairs ? false : rows.next(t0, t1);
     }
-    if (nlist > 0) rt_batch<PREC>(m, ang, L, nlist, lane, self, xhv, xlv, omx, A);
+    if (nlist > 0) rt_batch<PREC>(m, ang, S.u.b, S.list, nlist, lane, self, xhv, xlv, omx, A);
 
     double vx, vy, vz;
     if (PREC == 0) {
@@ -898,6 +981,9 @@ __global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang,
     vz = wave_sum_f64(vz);
     const unsigned long long hits = wave_sum_u64(A.hits);
     const unsigned long long rts = wave_sum_u64((unsigned long long)A.retests);
+    unsigned long long lr[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) lr[k] = LEARNED ? wave_sum_u64(n_by_rule[k]) : 0;
     if (lane == 0) {
         rtv[self] = vx;
         rtv[m.npad + self] = vy;
@@ -906,20 +992,26 @@ __global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang,
             atomicAdd(&cnt[2], A.pairs);
             atomicAdd(&cnt[3], hits);
             atomicAdd(&cnt[4], rts);
+            if (LEARNED)
+                for (int k = 0; k < 3; ++k) atomicAdd(&cnt[5 + k], lr[k]);
         }
     }
 }
 
-hipError_t launch_rt(const DevMesh &m, const Thresholds &th, const AngTab &ang, int all_pairs, int precision,
-                     double *rtv, unsigned long long *cnt, hipStream_t s)
+hipError_t launch_rt(const DevMesh &m, const Thresholds &th, const AngTab &ang, const LearnParams &lp,
+                     int all_pairs, int precision, double *rtv, unsigned long long *cnt, hipStream_t s)
 {
     if (m.n == 0) return hipSuccess;
-    if (precision == 0)
-        hipLaunchKernelGGL(k_rt<0>, dim3(m.n), dim3(64), 0, s, m, th, ang, all_pairs, rtv, cnt);
-    else if (precision == 1)
-        hipLaunchKernelGGL(k_rt<1>, dim3(m.n), dim3(64), 0, s, m, th, ang, all_pairs, rtv, cnt);
-    else
-        hipLaunchKernelGGL(k_rt<2>, dim3(m.n), dim3(64), 0, s, m, th, ang, all_pairs, rtv, cnt);
+    const bool L = lp.w != nullptr;
+#define BS_RT(P, LL) hipLaunchKernelGGL((k_rt<P, LL>), dim3(m.n), dim3(64), 0, s, m, th, ang, lp, all_pairs, rtv, cnt)
+    if (precision == 0) {
+        if (L) BS_RT(0, true); else BS_RT(0, false);
+    } else if (precision == 1) {
+        if (L) BS_RT(1, true); else BS_RT(1, false);
+    } else {
+        if (L) BS_RT(2, true); else BS_RT(2, false);
+    }
+#undef BS_RT
     return hipGetLastError();
 }
 
