@@ -167,17 +167,6 @@ void parallel_for(int64_t n, F &&f)
     for (auto &t : th) t.join();
 }
 
-uint64_t spread3(uint64_t v)
-{
-    v &= 0x1fffff;
-    v = (v | v << 32) & 0x1f00000000ffffull;
-    v = (v | v << 16) & 0x1f0000ff0000ffull;
-    v = (v | v << 8) & 0x100f00f00f00f00full;
-    v = (v | v << 4) & 0x10c30c30c30c30c3ull;
-    v = (v | v << 2) & 0x1249249249249249ull;
-    return v;
-}
-
 struct DBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -222,10 +211,14 @@ struct bs_mesh {
     std::vector<int32_t> h_rank, h_order, h_cell_start; // node rank, tet order, bins (host copies)
     std::vector<float> h_cen32;                         // binary32 centroids, input tet order
     std::vector<float> h_xh;                            // binary32 node coordinates, input node order
+    std::vector<int32_t> nbr_in;  // [T][4] face neighbours (input tet numbering, -1 boundary)
+    bool manifold = true;         // every face shared by at most two tets
+    bool convex = false;          // boundary is one closed, locally convex surface (rays never re-enter)
     bsk::Bins bins{};
     // device buffers
-    DBuf xh, xl, om, blk, node_orig, g1, g4, g11, tid, cell_start;
-    DBuf part, band, rtv, vel, cnt, nonfinite;
+    DBuf xh, xl, om, blk, node_orig, g1, g4, g11, tid, cell_start, nbr, inc_start, inc_list;
+    DBuf part, band, rtv, vel, cnt, nonfinite, fallback;
+    int rt_mode = 0; // 0: walk where the boundary is convex, 1: always the candidate kernel
     DBuf dir, dir64, cphi, dia;
     int part_splits = 0;
     // policy
@@ -328,6 +321,121 @@ int validate_geometry(bs_mesh *m)
     return BS_OK;
 }
 
+// Face neighbours of every tet (input numbering): the face opposite local
+// vertex f of tet t is keyed by its sorted node triple.
+void build_neighbours(bs_mesh *m)
+{
+    const int64_t T = m->T;
+    m->nbr_in.assign((size_t)(4 * T), -1);
+    m->manifold = true;
+    struct FK {
+        int32_t a, b, c;
+        int64_t tf;
+    };
+    std::vector<FK> fk((size_t)(4 * T));
+    for (int64_t t = 0; t < T; ++t)
+        for (int f = 0; f < 4; ++f) {
+            int32_t v[3], k = 0;
+            for (int j = 0; j < 4; ++j)
+                if (j != f) v[k++] = m->tets[(size_t)(4 * t + j)];
+            std::sort(v, v + 3);
+            fk[(size_t)(4 * t + f)] = {v[0], v[1], v[2], 4 * t + f};
+        }
+    std::sort(fk.begin(), fk.end(), [](const FK &x, const FK &y) {
+        return x.a != y.a ? x.a < y.a : x.b != y.b ? x.b < y.b : x.c != y.c ? x.c < y.c : x.tf < y.tf;
+    });
+    for (size_t i = 0; i < fk.size();) {
+        size_t j = i + 1;
+        while (j < fk.size() && fk[j].a == fk[i].a && fk[j].b == fk[i].b && fk[j].c == fk[i].c) ++j;
+        if (j - i == 2) {
+            m->nbr_in[(size_t)fk[i].tf] = (int32_t)(fk[i + 1].tf / 4);
+            m->nbr_in[(size_t)fk[i + 1].tf] = (int32_t)(fk[i].tf / 4);
+        } else if (j - i > 2) {
+            m->manifold = false;
+        }
+        i = j;
+    }
+}
+
+// The boundary is one connected, closed surface whose every edge is convex
+// (a locally convex closed surface bounds a convex body): a ray leaving the
+// mesh never re-enters it.
+bool boundary_convex(const bs_mesh *m)
+{
+    if (!m->manifold) return false;
+    const int64_t T = m->T;
+    const double *X = m->xyz.data();
+    struct BF {
+        int32_t v[3]; // oriented outward
+    };
+    std::vector<BF> bf;
+    for (int64_t t = 0; t < T; ++t)
+        for (int f = 0; f < 4; ++f) {
+            if (m->nbr_in[(size_t)(4 * t + f)] >= 0) continue;
+            int32_t v[3], k = 0;
+            for (int j = 0; j < 4; ++j)
+                if (j != f) v[k++] = m->tets[(size_t)(4 * t + j)];
+            const int32_t o = m->tets[(size_t)(4 * t + f)];
+            double e1[3], e2[3], d[3];
+            for (int c = 0; c < 3; ++c) {
+                e1[c] = X[3 * (int64_t)v[1] + c] - X[3 * (int64_t)v[0] + c];
+                e2[c] = X[3 * (int64_t)v[2] + c] - X[3 * (int64_t)v[0] + c];
+                d[c] = X[3 * (int64_t)o + c] - X[3 * (int64_t)v[0] + c];
+            }
+            const double nx = e1[1] * e2[2] - e1[2] * e2[1], ny = e1[2] * e2[0] - e1[0] * e2[2],
+                         nz = e1[0] * e2[1] - e1[1] * e2[0];
+            if (nx * d[0] + ny * d[1] + nz * d[2] > 0) std::swap(v[1], v[2]);
+            bf.push_back({{v[0], v[1], v[2]}});
+        }
+    if (bf.empty()) return false;
+    // edges of boundary faces: (min, max) -> faces
+    struct EK {
+        int64_t key;
+        int32_t face, other; // the face's third vertex
+    };
+    std::vector<EK> ek;
+    ek.reserve(3 * bf.size());
+    const int64_t n1 = m->n + 1;
+    for (size_t i = 0; i < bf.size(); ++i)
+        for (int e = 0; e < 3; ++e) {
+            const int32_t a = bf[i].v[e], b = bf[i].v[(e + 1) % 3], c = bf[i].v[(e + 2) % 3];
+            ek.push_back({(int64_t)std::min(a, b) * n1 + std::max(a, b), (int32_t)i, c});
+        }
+    std::sort(ek.begin(), ek.end(), [](const EK &x, const EK &y) { return x.key < y.key || (x.key == y.key && x.face < y.face); });
+    std::vector<int32_t> parent(bf.size());
+    for (size_t i = 0; i < bf.size(); ++i) parent[i] = (int32_t)i;
+    auto find = [&](int32_t x) {
+        while (parent[(size_t)x] != x) x = parent[(size_t)x] = parent[(size_t)parent[(size_t)x]];
+        return x;
+    };
+    for (size_t i = 0; i < ek.size();) {
+        size_t j = i + 1;
+        while (j < ek.size() && ek[j].key == ek[i].key) ++j;
+        if (j - i != 2) return false; // open or non-manifold boundary
+        const BF &F = bf[(size_t)ek[i].face];
+        const int32_t g = ek[i + 1].other; // vertex of the neighbouring face off the shared edge
+        double e1[3], e2[3], d[3], l2 = 0;
+        for (int c = 0; c < 3; ++c) {
+            e1[c] = X[3 * (int64_t)F.v[1] + c] - X[3 * (int64_t)F.v[0] + c];
+            e2[c] = X[3 * (int64_t)F.v[2] + c] - X[3 * (int64_t)F.v[0] + c];
+            d[c] = X[3 * (int64_t)g + c] - X[3 * (int64_t)F.v[0] + c];
+            l2 += d[c] * d[c] + e1[c] * e1[c];
+        }
+        const double nx = e1[1] * e2[2] - e1[2] * e2[1], ny = e1[2] * e2[0] - e1[0] * e2[2],
+                     nz = e1[0] * e2[1] - e1[1] * e2[0];
+        const double nn = std::sqrt(nx * nx + ny * ny + nz * nz);
+        // outward normal: g must not lie outside the plane of F
+        if (nx * d[0] + ny * d[1] + nz * d[2] > 1e-9 * nn * std::sqrt(l2)) return false;
+        const int32_t ra = find(ek[i].face), rb = find(ek[i + 1].face);
+        if (ra != rb) parent[(size_t)ra] = rb;
+        i = j;
+    }
+    const int32_t r0 = find(0);
+    for (size_t i = 1; i < bf.size(); ++i)
+        if (find((int32_t)i) != r0) return false;
+    return true;
+}
+
 // Everything that depends on coordinates and vorticity: node order, bins,
 // per-tet records.  Connectivity is already validated.
 int build_device_mesh(bs_mesh *m, hipStream_t s)
@@ -336,29 +444,43 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
     const double *X = m->xyz.data(), *W = m->omega.data();
     m->hbar = T > 0 ? mean_edge(n, X, T, m->tets.data()) : 0.0;
 
-    // ---- nodes in Morton order
-    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-    for (int64_t i = 0; i < n; ++i)
-        for (int c = 0; c < 3; ++c) {
-            lo[c] = std::min(lo[c], X[3 * i + c]);
-            hi[c] = std::max(hi[c], X[3 * i + c]);
-        }
-    double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
-    std::vector<std::pair<uint64_t, int32_t>> key((size_t)n);
-    for (int64_t i = 0; i < n; ++i) {
-        uint64_t code = 0;
-        for (int c = 0; c < 3; ++c) {
-            const double u = (X[3 * i + c] - lo[c]) / ext * 2097151.0;
-            code |= spread3((uint64_t)std::min(2097151.0, std::max(0.0, u))) << c;
-        }
-        key[(size_t)i] = {code, (int32_t)i};
-    }
-    std::sort(key.begin(), key.end());
+    // ---- nodes ordered by a k-d split into leaves of 64 (one band-kernel
+    // block per leaf): recursive median splits across the longest axis, at
+    // multiples of the leaf size, give compact blocks
     std::vector<int32_t> orig((size_t)n), rank((size_t)n);
-    for (int64_t i = 0; i < n; ++i) {
-        orig[(size_t)i] = key[(size_t)i].second;
-        rank[(size_t)key[(size_t)i].second] = (int32_t)i;
+    for (int64_t i = 0; i < n; ++i) orig[(size_t)i] = (int32_t)i;
+    {
+        struct Range {
+            int64_t a, b;
+        };
+        std::vector<Range> stack{{0, n}};
+        while (!stack.empty()) {
+            const Range r = stack.back();
+            stack.pop_back();
+            const int64_t len = r.b - r.a;
+            if (len <= bsk::kBlockNodes) continue;
+            double lo3[3] = {1e300, 1e300, 1e300}, hi3[3] = {-1e300, -1e300, -1e300};
+            for (int64_t k = r.a; k < r.b; ++k)
+                for (int c = 0; c < 3; ++c) {
+                    const double v = X[3 * (int64_t)orig[(size_t)k] + c];
+                    lo3[c] = std::min(lo3[c], v);
+                    hi3[c] = std::max(hi3[c], v);
+                }
+            int ax = 0;
+            for (int c = 1; c < 3; ++c)
+                if (hi3[c] - lo3[c] > hi3[ax] - lo3[ax]) ax = c;
+            int64_t k = ((len / 2 + bsk::kBlockNodes / 2) / bsk::kBlockNodes) * bsk::kBlockNodes;
+            k = std::min(std::max<int64_t>(k, bsk::kBlockNodes), len - 1);
+            std::nth_element(orig.begin() + r.a, orig.begin() + r.a + k, orig.begin() + r.b,
+                             [&](int32_t u, int32_t v) {
+                                 const double xu = X[3 * (int64_t)u + ax], xv = X[3 * (int64_t)v + ax];
+                                 return xu < xv || (xu == xv && u < v);
+                             });
+            stack.push_back({r.a + k, r.b});
+            stack.push_back({r.a, r.a + k});
+        }
     }
+    for (int64_t i = 0; i < n; ++i) rank[(size_t)orig[(size_t)i]] = (int32_t)i;
     const int npad = (int)(((n + 1023) / 1024) * 1024);
     const int nblk = (int)((n + bsk::kBlockNodes - 1) / bsk::kBlockNodes);
     m->npad = npad;
@@ -515,6 +637,32 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
         }
     });
 
+    // ---- face neighbours (sorted numbering) and incident tets per node
+    std::vector<int32_t> slot((size_t)T);
+    for (int64_t k = 0; k < T; ++k) slot[(size_t)order[(size_t)k]] = (int32_t)k;
+    std::vector<int4> nbr((size_t)T);
+    std::vector<int32_t> inc_start((size_t)n + 1, 0), inc_list((size_t)(4 * T));
+    for (int64_t k = 0; k < T; ++k) {
+        const int64_t t = order[(size_t)k];
+        int32_t q[4];
+        for (int f = 0; f < 4; ++f) {
+            const int32_t u = m->nbr_in[(size_t)(4 * t + f)];
+            q[f] = u >= 0 ? slot[(size_t)u] : -1;
+        }
+        nbr[(size_t)k] = make_int4(q[0], q[1], q[2], q[3]);
+        for (int j = 0; j < 4; ++j) inc_start[(size_t)rank[(size_t)m->tets[(size_t)(4 * t + j)]] + 1]++;
+    }
+    for (int64_t i = 0; i < n; ++i) inc_start[(size_t)i + 1] += inc_start[(size_t)i];
+    {
+        std::vector<int32_t> fill(inc_start.begin(), inc_start.end() - 1);
+        for (int64_t k = 0; k < T; ++k) {
+            const int64_t t = order[(size_t)k];
+            for (int j = 0; j < 4; ++j) inc_list[(size_t)fill[(size_t)rank[(size_t)m->tets[(size_t)(4 * t + j)]]]++] =
+                (int32_t)k;
+        }
+    }
+    m->convex = T > 0 && boundary_convex(m);
+
     // ---- upload
     int rc;
     const size_t nb = sizeof(float) * 3 * (size_t)npad;
@@ -524,7 +672,9 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
         (rc = dalloc(m->g11, 4 * g11.size())) || (rc = dalloc(m->tid, sizeof(int4) * (size_t)T)) ||
         (rc = dalloc(m->cell_start, 4 * cell_start.size())) || (rc = dalloc(m->band, 8 * 3 * (size_t)npad)) ||
         (rc = dalloc(m->rtv, 8 * 3 * (size_t)npad)) || (rc = dalloc(m->vel, 8 * 3 * (size_t)n)) ||
-        (rc = dalloc(m->cnt, 8 * bsk::kNumCounters)) || (rc = dalloc(m->nonfinite, 4)))
+        (rc = dalloc(m->cnt, 8 * bsk::kNumCounters)) || (rc = dalloc(m->nonfinite, 4)) ||
+        (rc = dalloc(m->nbr, sizeof(int4) * (size_t)T)) || (rc = dalloc(m->inc_start, 4 * inc_start.size())) ||
+        (rc = dalloc(m->inc_list, 4 * inc_list.size())))
         return rc;
     hipError_t e;
 #define BS_UP(buf, vec)                                                                                            \
@@ -542,6 +692,9 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
     BS_UP(g11, g11)
     BS_UP(tid, tid)
     BS_UP(cell_start, cell_start)
+    BS_UP(nbr, nbr)
+    BS_UP(inc_start, inc_start)
+    BS_UP(inc_list, inc_list)
 #undef BS_UP
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "upload");
@@ -631,6 +784,9 @@ bsk::DevMesh dev_view(const bs_mesh *m)
     d.g11 = (const float *)m->g11.p;
     d.tid = (const int4 *)m->tid.p;
     d.cell_start = (const int *)m->cell_start.p;
+    d.nbr = (const int4 *)m->nbr.p;
+    d.inc_start = (const int *)m->inc_start.p;
+    d.inc_list = (const int *)m->inc_list.p;
     d.bins = m->bins;
     return d;
 }
@@ -749,6 +905,7 @@ int bs_mesh_upload(const bs_mesh_desc *d, bs_mesh **out)
         delete m;
         return rc;
     }
+    build_neighbours(m);
     if (dev < 0 && (rc = check_device(&dev))) {
         delete m;
         return rc;
@@ -788,6 +945,7 @@ void bs_mesh_free(bs_mesh *m)
 {
     if (!m) return;
     DBuf *bufs[] = {&m->xh, &m->xl, &m->om, &m->blk, &m->node_orig, &m->g1, &m->g4, &m->g11, &m->tid,
+                    &m->nbr, &m->inc_start, &m->inc_list, &m->fallback,
                     &m->cell_start, &m->part, &m->band, &m->rtv, &m->vel, &m->cnt, &m->nonfinite, &m->dir,
                     &m->dir64, &m->cphi, &m->dia, &m->mlp};
     for (DBuf *b : bufs) dfree(*b);
@@ -882,9 +1040,21 @@ int eval_device(bs_mesh *m, hipStream_t s)
     lp.conf_min = P.conf_min;
     lp.hbar = (float)m->hbar;
     if (m->T > 0 && (fixed_like || P.kind == BS_POLICY_PURE_RT)) {
-        if ((e = bsk::launch_rt(dm, th, ang, lp, P.kind == BS_POLICY_PURE_RT, P.precision, (double *)m->rtv.p, cnt,
-                                s)))
+        const int all = P.kind == BS_POLICY_PURE_RT;
+        if (m->convex && m->rt_mode == 0) {
+            if ((rc = dalloc(m->fallback, 4 * ((size_t)m->n + 1)))) return rc;
+            int *nfb = (int *)m->fallback.p + m->n;
+            const float r_stop = all ? 3.0e38f : (float)((std::max(c_rt, m->max_vc) + m->max_vc) * (1.0 + 1e-4) + 1e-6);
+            if ((e = hipMemsetAsync(nfb, 0, 4, s)) ||
+                (e = bsk::launch_rt_walk(dm, th, ang, lp, all, r_stop, P.precision, (double *)m->rtv.p, cnt,
+                                         (int *)m->fallback.p, nfb, s)) ||
+                (e = bsk::launch_rt(dm, th, ang, lp, all, P.precision, (double *)m->rtv.p, cnt,
+                                    (const int *)m->fallback.p, nfb, s)))
+                return hip_fail(e, "ray-tracing walk");
+        } else if ((e = bsk::launch_rt(dm, th, ang, lp, all, P.precision, (double *)m->rtv.p, cnt, nullptr, nullptr,
+                                       s))) {
             return hip_fail(e, "ray-tracing kernel");
+        }
         rtv = (const double *)m->rtv.p;
     }
     (void)hipEventRecord(m->ev[3], s);

@@ -13,6 +13,8 @@
 //     g4[T][4][8] 4-point rule: p_q, W_q = w_q |T| omega(p_q) / 4pi, pad
 //     g11[T][11][8] 11-point rule, same record
 //     tid[T]      the four vertex indices (sorted-node numbering), input order
+//     nbr[T]      the tet across each face (sorted numbering), -1 on the boundary
+//     inc_start[n+1], inc_list: the tets incident to every node
 //     cell_start[ncell + 1] first tet of every bin (bins in x-fastest order)
 //   angular tables (per policy): one entry per ray of the full sphere,
 //     index l = n * 2M + j (polar row n, azimuth column j in [0, 2M)):
@@ -66,6 +68,9 @@ struct DevMesh {
     const float *g1, *g4, *g11;
     const int4 *tid;
     const int *cell_start;
+    const int4 *nbr;       // [T] face neighbours (sorted numbering; face f opposite vertex f; -1 boundary)
+    const int *inc_start;  // [n+1] CSR of the tets incident to each node
+    const int *inc_list;
     Bins bins;
 };
 
@@ -80,7 +85,13 @@ hipError_t launch_gauss_all(const DevMesh &m, int rule_pts, int precision, int s
 hipError_t launch_band(const DevMesh &m, const Thresholds &th, int precision, double *band,
                        unsigned long long *cnt, hipStream_t s);
 hipError_t launch_rt(const DevMesh &m, const Thresholds &th, const AngTab &ang, const LearnParams &lp,
-                     int all_pairs, int precision, double *rtv, unsigned long long *cnt, hipStream_t s);
+                     int all_pairs, int precision, double *rtv, unsigned long long *cnt, const int *node_list,
+                     const int *node_count, hipStream_t s);
+// Walk variant (convex meshes); nodes it cannot hold are appended to
+// fallback[*n_fallback] for launch_rt in node-list mode.
+hipError_t launch_rt_walk(const DevMesh &m, const Thresholds &th, const AngTab &ang, const LearnParams &lp,
+                          int all_pairs, float r_stop, int precision, double *rtv, unsigned long long *cnt,
+                          int *fallback, int *n_fallback, hipStream_t s);
 hipError_t launch_combine(const DevMesh &m, const int *node_orig, const double *part, int splits,
                           const double *band, const double *rtv, double *vel, int *nonfinite, hipStream_t s);
 

@@ -453,14 +453,20 @@ struct RtLds {
     int ids[4][64];    // vertex node ids (for the FP64 retest)
 };
 
-// LDS of k_rt: the pending list, and either one batch's pair data or the
-// network's scratch (never live together).
-struct RtShared {
+// LDS of k_rt: the pending list, and either one batch's pair data or (for
+// the learned policy) the network's scratch, never live together.
+template <bool LEARNED> struct RtShared {
     union {
         RtLds b;
         InferLds n;
     } u;
     int list[128]; // pending ray-traced tets
+};
+template <> struct RtShared<false> {
+    union {
+        RtLds b;
+    } u;
+    int list[128];
 };
 
 __device__ __forceinline__ float diamond(float c, float s)
@@ -901,11 +907,13 @@ __device__ __forceinline__ int learned_rule(const DevMesh &m, const LearnParams 
 
 template <int PREC, bool LEARNED>
 __global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang, LearnParams lp, int all_pairs,
-                                           double *__restrict__ rtv, unsigned long long *__restrict__ cnt)
+                                           double *__restrict__ rtv, unsigned long long *__restrict__ cnt,
+                                           const int *__restrict__ node_list, const int *__restrict__ node_count)
 {
-    __shared__ RtShared S;
+    __shared__ RtShared<LEARNED> S;
     const int lane = threadIdx.x;
-    const int self = blockIdx.x;
+    if (node_list && (int)blockIdx.x >= *node_count) return;
+    const int self = node_list ? node_list[blockIdx.x] : (int)blockIdx.x;
     float xhv[3], xlv[3], omx[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -937,7 +945,7 @@ __global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang,
                     is_rt = fixed_rule(xhv[0], xhv[1], xhv[2], g[0], g[1], g[2], id, self, th) == RULE_RT;
                 }
             }
-            if (LEARNED) {
+            if constexpr (LEARNED) {
                 const bool cand = is_rt && !inc;
                 if (__ballot(cand))
                     is_rt = learned_rule<PREC>(m, lp, S.u.n, lane, t < t1 ? t : t0, cand, self, xhv, xlv, A,
@@ -998,12 +1006,380 @@ __global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Ray tracing by walking the mesh (for meshes whose boundary is convex).
+// One wave per node; lane = ray.  Every ray leaves the node through the one
+// incident tet whose opposite face it crosses, then crosses face neighbours
+// outward: the exit face of one tet is the entry face of the next, decided
+// by the same shared edge values, so chords join exactly.  A tet adds its
+// chord when its pair with the node is ray traced (a sorted LDS list built
+// by the scan; every tet for the pure ray-tracing policy).  The walk stops
+// at the boundary or once the ray is farther than r_stop (no ray-traced tet
+// lies beyond: r_rt plus the largest vertex-centroid distance).  Nodes whose
+// lists exceed the LDS capacity are handed to k_rt.
+constexpr int kWalkCap = 1024; // ray-traced tets per node
+constexpr int kIncCap = 64;    // incident tets per node
+constexpr int kMaxSteps = 1 << 13; // tets per ray: bounds a walk that stalls on a degenerate crossing
+
+struct WalkLds {
+    int list[kWalkCap];
+    // incident tets: the three vertices of the face opposite the node
+    float ia[kIncCap][9];  // relative positions (p, q, r)
+    float iw[kIncCap][9];  // vorticity
+    float in[kIncCap][9];  // canonical normals of the edges pq, qr, pr
+    int iid[kIncCap][3];   // node ids of p, q, r
+    int imeta[kIncCap];    // bits 0-2: flip of pq, qr, pr
+    int inb[kIncCap];      // tet across the face (-1: boundary)
+    float ivol[kIncCap];   // [a_p, a_q, a_r]
+    int nlist, ninc, overflow;
+};
+
+template <bool LEARNED> struct WalkShared {
+    WalkLds w;
+    InferLds n;
+};
+template <> struct WalkShared<false> {
+    WalkLds w;
+};
+
+// value [d, A, B] for the canonical ordering (smaller node id first); FP64
+// sign when tiny.  Returns the value for (A, B) in the given order.
+__device__ __forceinline__ float edge_val(const float4 &d, const float *A, int ia, const float *B, int ib,
+                                          const DevMesh &m, const double *d64, const float *xhv, const float *xlv,
+                                          int &sgn, int &retests)
+{
+    float N[3];
+    const bool flip = ia > ib;
+    if (!flip) cross_canon(A, B, N);
+    else cross_canon(B, A, N);
+    const float c = fmaf(d.x, N[0], fmaf(d.y, N[1], d.z * N[2]));
+    int sg = c >= 0.f ? 1 : -1;
+    if (fabsf(c) <= 1e-5f * (fabsf(N[0]) + fabsf(N[1]) + fabsf(N[2]))) {
+        sg = edge_sign_f64(m, d64, flip ? ib : ia, flip ? ia : ib, xhv, xlv);
+        ++retests;
+    }
+    sgn = flip ? -sg : sg;
+    return flip ? -c : c;
+}
+
+__device__ __forceinline__ bool in_sorted(const int *a, int n, int v)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < n && a[lo] == v;
+}
+
+template <int PREC, bool LEARNED>
+__global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab ang, LearnParams lp,
+                                                int all_pairs, float r_stop, double *__restrict__ rtv,
+                                                unsigned long long *__restrict__ cnt, int *__restrict__ fallback,
+                                                int *__restrict__ n_fallback)
+{
+    __shared__ WalkShared<LEARNED> S;
+    WalkLds &W = S.w;
+    const int lane = threadIdx.x;
+    const int self = blockIdx.x;
+    float xhv[3], xlv[3], omx[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        xhv[c] = m.xh[c * m.npad + self];
+        xlv[c] = m.xl[c * m.npad + self];
+        omx[c] = m.om[c * m.npad + self];
+    }
+    RtAcc A;
+    A.ax = A.ay = A.az = A.sx = A.sy = A.sz = A.cx = A.cy = A.cz = 0.f;
+    A.dx = A.dy = A.dz = 0.0;
+    A.pairs = A.hits = 0;
+    A.retests = 0;
+    unsigned long long n_by_rule[3] = {0, 0, 0};
+    if (lane == 0) {
+        W.nlist = 0;
+        W.overflow = 0;
+    }
+    __syncthreads();
+
+    // ---- A. ray-traced tets of the node (not needed when every pair is)
+    int nlist = 0;
+    if (!all_pairs) {
+        RowIter rows(m, xhv[0], xhv[1], xhv[2], th.r_rt);
+        int t0, t1;
+        while (rows.next(t0, t1)) {
+            for (int b0 = t0; b0 < t1; b0 += 64) {
+                const int t = b0 + lane;
+                bool is_rt = false, inc = false;
+                if (t < t1) {
+                    const int4 id = m.tid[t];
+                    inc = (id.x == self) | (id.y == self) | (id.z == self) | (id.w == self);
+                    const float *g = m.g1 + (size_t)t * kRecG;
+                    is_rt = fixed_rule(xhv[0], xhv[1], xhv[2], g[0], g[1], g[2], id, self, th) == RULE_RT;
+                }
+                if constexpr (LEARNED) {
+                    const bool cand = is_rt && !inc;
+                    if (__ballot(cand))
+                        is_rt = learned_rule<PREC>(m, lp, S.n, lane, t < t1 ? t : t0, cand, self, xhv, xlv, A,
+                                                   n_by_rule) == RULE_RT && is_rt;
+                }
+                const unsigned long long mask = __ballot(is_rt);
+                const int pos = nlist + __popcll(mask & ((1ull << lane) - 1ull));
+                if (is_rt && pos < kWalkCap) W.list[pos] = t;
+                nlist += __popcll(mask);
+            }
+        }
+        if (nlist > kWalkCap) {
+            if (lane == 0) fallback[atomicAdd(n_fallback, 1)] = self;
+            return;
+        }
+        // sort the list (bitonic, padded with INT_MAX)
+        int np2 = 1;
+        while (np2 < nlist) np2 <<= 1;
+        for (int k = nlist + lane; k < np2; k += 64) W.list[k] = 0x7fffffff;
+        __syncthreads();
+        for (int size = 2; size <= np2; size <<= 1)
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int k = lane; k < np2 / 2; k += 64) {
+                    const int i = 2 * k - (k & (stride - 1));
+                    const int j = i + stride;
+                    const bool up = (i & size) == 0;
+                    const int a = W.list[i], b = W.list[j];
+                    if ((a > b) == up) {
+                        W.list[i] = b;
+                        W.list[j] = a;
+                    }
+                }
+                __syncthreads();
+            }
+    }
+
+    // ---- B. incident tets: the face opposite the node, its neighbour
+    const int i0 = m.inc_start[self], i1 = m.inc_start[self + 1];
+    const int ninc = i1 - i0;
+    // a point that is no vertex of the mesh (inside a tet, or outside the
+    // mesh) has no incident tet to start from: the candidate kernel takes it
+    if (ninc > kIncCap || ninc == 0) {
+        if (lane == 0) fallback[atomicAdd(n_fallback, 1)] = self;
+        return;
+    }
+    if (lane < ninc) {
+        const int t = m.inc_list[i0 + lane];
+        const int4 id4 = m.tid[t];
+        const int id[4] = {id4.x, id4.y, id4.z, id4.w};
+        const int4 nb4 = m.nbr[t];
+        const int nb[4] = {nb4.x, nb4.y, nb4.z, nb4.w};
+        int f = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (id[j] == self) f = j;
+        int v[3], k = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j != f) v[k++] = j;
+        float a[3][3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int nid = id[v[q]];
+            W.iid[lane][q] = nid;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                a[q][c] = (m.xh[c * m.npad + nid] - xhv[c]) + (m.xl[c * m.npad + nid] - xlv[c]);
+                W.ia[lane][3 * q + c] = a[q][c];
+                W.iw[lane][3 * q + c] = m.om[c * m.npad + nid];
+            }
+        }
+        // edges pq (0,1), qr (1,2), pr (0,2) in canonical order
+        const int ep[3][2] = {{0, 1}, {1, 2}, {0, 2}};
+        int flips = 0;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            const int x0 = ep[e][0], x1 = ep[e][1];
+            float N[3];
+            if (id[v[x0]] < id[v[x1]]) cross_canon(a[x0], a[x1], N);
+            else {
+                cross_canon(a[x1], a[x0], N);
+                flips |= 1 << e;
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) W.in[lane][3 * e + c] = N[c];
+        }
+        float N[3];
+        cross_canon(a[1], a[2], N);
+        W.ivol[lane] = fmaf(a[0][0], N[0], fmaf(a[0][1], N[1], a[0][2] * N[2]));
+        W.imeta[lane] = flips;
+        W.inb[lane] = nb[f];
+    }
+    __syncthreads();
+
+    // ---- C. rays
+    const int nrays = ang.N * ang.M2;
+    for (int l = lane; l < nrays; l += 64) {
+        const float4 d = ang.dir[l];
+        const double *d64 = ang.dir64 + 3 * (size_t)l;
+        // start: the incident tet whose opposite face the ray crosses
+        int start = -1;
+        float rho = 0.f, w_in[3] = {0.f, 0.f, 0.f};
+        for (int i = 0; i < ninc && start < 0; ++i) {
+            const int meta = W.imeta[i];
+            float ce[3];
+            int se[3];
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                const float nx = W.in[i][3 * e], ny = W.in[i][3 * e + 1], nz = W.in[i][3 * e + 2];
+                const float c = fmaf(d.x, nx, fmaf(d.y, ny, d.z * nz));
+                int sg = c >= 0.f ? 1 : -1;
+                if (fabsf(c) <= 1e-5f * (fabsf(nx) + fabsf(ny) + fabsf(nz))) {
+                    const int ep0[3] = {0, 1, 0}, ep1[3] = {1, 2, 2};
+                    const int u0 = W.iid[i][ep0[e]], u1 = W.iid[i][ep1[e]];
+                    const bool fl = (meta >> e) & 1;
+                    sg = edge_sign_f64(m, d64, fl ? u1 : u0, fl ? u0 : u1, xhv, xlv);
+                    ++A.retests;
+                }
+                const bool fl = (meta >> e) & 1;
+                se[e] = fl ? -sg : sg;
+                ce[e] = fl ? -c : c;
+            }
+            // face (p, q, r): [d,p,q] = ce0, [d,q,r] = ce1, [d,r,p] = -ce2
+            if (se[0] != se[1] || se[1] != -se[2]) continue;
+            const float E1 = ce[0], E2 = ce[1], E3 = -ce[2];
+            const float Sm = (E1 + E2) + E3;
+            const float r = W.ivol[i] / Sm;
+            if (!(r > 0.f) || !(r < 3.0e38f)) continue;
+            const float lp_ = E2 / Sm, lq = E3 / Sm, lr = E1 / Sm;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                w_in[c] = fmaf(lp_, W.iw[i][c], fmaf(lq, W.iw[i][3 + c], lr * W.iw[i][6 + c]));
+            rho = r;
+            start = i;
+        }
+        if (start < 0) continue;
+        {
+            const float h = 0.5f * d.w * rho;
+            const float sx = omx[0] + w_in[0], sy = omx[1] + w_in[1], sz = omx[2] + w_in[2];
+            acc_add<PREC>(A, h * fmaf(d.y, sz, -(d.z * sy)), h * fmaf(d.z, sx, -(d.x * sz)),
+                          h * fmaf(d.x, sy, -(d.y * sx)));
+            ++A.hits;
+        }
+        int T = W.inb[start];
+        int ent[3] = {W.iid[start][0], W.iid[start][1], W.iid[start][2]};
+        int steps = 0;
+        while (T >= 0 && rho < r_stop && steps < kMaxSteps) {
+            ++steps;
+            const int4 id4 = m.tid[T];
+            const int id[4] = {id4.x, id4.y, id4.z, id4.w};
+            int fin = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (id[j] != ent[0] && id[j] != ent[1] && id[j] != ent[2]) fin = j;
+            float a[4][3], w[4][3];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    a[j][c] = (m.xh[c * m.npad + id[j]] - xhv[c]) + (m.xl[c * m.npad + id[j]] - xlv[c]);
+                    w[j][c] = m.om[c * m.npad + id[j]];
+                }
+            float ce[6];
+            int se[6];
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                constexpr int ea[6] = {0, 0, 0, 1, 1, 2}, eb[6] = {1, 2, 3, 2, 3, 3};
+                ce[e] = edge_val(d, a[ea[e]], id[ea[e]], a[eb[e]], id[eb[e]], m, d64, xhv, xlv, se[e], A.retests);
+            }
+            // exit: the crossed face other than the entry face, farthest along the ray
+            int fout = -1;
+            float rout = 0.f, wout[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                if (f == fin) continue;
+                const int pp = f == 0 ? 1 : 0, qq = f <= 1 ? 2 : 1, rr = f <= 2 ? 3 : 2;
+                const int epq = pp == 0 ? qq - 1 : (pp == 1 ? qq + 1 : 5);
+                const int eqr = qq == 1 ? rr + 1 : 5;
+                const int epr = pp == 0 ? rr - 1 : (pp == 1 ? rr + 1 : 5);
+                const int s1 = se[epq], s2 = se[eqr], s3 = -se[epr];
+                if (s1 != s2 || s2 != s3) continue;
+                const float E1 = ce[epq], E2 = ce[eqr], E3 = -ce[epr];
+                const float Sm = (E1 + E2) + E3;
+                float N[3];
+                cross_canon(a[qq], a[rr], N);
+                const float vol = fmaf(a[pp][0], N[0], fmaf(a[pp][1], N[1], a[pp][2] * N[2]));
+                const float r = vol / Sm;
+                if (!(r < 3.0e38f) || !(r > -3.0e38f) || (fout >= 0 && r <= rout)) continue;
+                const float lp_ = E2 / Sm, lq = E3 / Sm, lr = E1 / Sm;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) wout[c] = fmaf(lp_, w[pp][c], fmaf(lq, w[qq][c], lr * w[rr][c]));
+                rout = r;
+                fout = f;
+            }
+            if (fout < 0) break; // no exit found (degenerate): end the ray here
+            const float r_out = fmaxf(rout, rho);
+            if (all_pairs || in_sorted(W.list, nlist, T)) {
+                const float h = 0.5f * d.w * (r_out - rho);
+                const float sx = w_in[0] + wout[0], sy = w_in[1] + wout[1], sz = w_in[2] + wout[2];
+                acc_add<PREC>(A, h * fmaf(d.y, sz, -(d.z * sy)), h * fmaf(d.z, sx, -(d.x * sz)),
+                              h * fmaf(d.x, sy, -(d.y * sx)));
+                ++A.hits;
+            }
+            const int4 nb4 = m.nbr[T];
+            const int nb[4] = {nb4.x, nb4.y, nb4.z, nb4.w};
+            int k = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (j != fout) ent[k++] = id[j];
+            T = nb[fout];
+            rho = r_out;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) w_in[c] = wout[c];
+        }
+    }
+    A.pairs = all_pairs ? (unsigned long long)m.T : (unsigned long long)nlist;
+
+    double vx, vy, vz;
+    if (PREC == 0) {
+        vx = A.ax;
+        vy = A.ay;
+        vz = A.az;
+    } else if (PREC == 1) {
+        vx = (double)A.sx + (double)A.cx;
+        vy = (double)A.sy + (double)A.cy;
+        vz = (double)A.sz + (double)A.cz;
+    } else {
+        vx = A.dx;
+        vy = A.dy;
+        vz = A.dz;
+    }
+    vx = wave_sum_f64(vx);
+    vy = wave_sum_f64(vy);
+    vz = wave_sum_f64(vz);
+    const unsigned long long hits = wave_sum_u64(A.hits);
+    const unsigned long long rts = wave_sum_u64((unsigned long long)A.retests);
+    unsigned long long lr[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) lr[k] = LEARNED ? wave_sum_u64(n_by_rule[k]) : 0;
+    if (lane == 0) {
+        rtv[self] = vx;
+        rtv[m.npad + self] = vy;
+        rtv[2 * m.npad + self] = vz;
+        if (cnt) {
+            atomicAdd(&cnt[2], A.pairs);
+            atomicAdd(&cnt[3], hits);
+            atomicAdd(&cnt[4], rts);
+            if (LEARNED)
+                for (int k = 0; k < 3; ++k) atomicAdd(&cnt[5 + k], lr[k]);
+        }
+    }
+}
+
 hipError_t launch_rt(const DevMesh &m, const Thresholds &th, const AngTab &ang, const LearnParams &lp,
-                     int all_pairs, int precision, double *rtv, unsigned long long *cnt, hipStream_t s)
+                     int all_pairs, int precision, double *rtv, unsigned long long *cnt, const int *node_list,
+                     const int *node_count, hipStream_t s)
 {
     if (m.n == 0) return hipSuccess;
     const bool L = lp.w != nullptr;
-#define BS_RT(P, LL) hipLaunchKernelGGL((k_rt<P, LL>), dim3(m.n), dim3(64), 0, s, m, th, ang, lp, all_pairs, rtv, cnt)
+#define BS_RT(P, LL)                                                                                               \
+    hipLaunchKernelGGL((k_rt<P, LL>), dim3(m.n), dim3(64), 0, s, m, th, ang, lp, all_pairs, rtv, cnt, node_list,  \
+                       node_count)
     if (precision == 0) {
         if (L) BS_RT(0, true); else BS_RT(0, false);
     } else if (precision == 1) {
@@ -1012,6 +1388,26 @@ hipError_t launch_rt(const DevMesh &m, const Thresholds &th, const AngTab &ang, 
         if (L) BS_RT(2, true); else BS_RT(2, false);
     }
 #undef BS_RT
+    return hipGetLastError();
+}
+
+hipError_t launch_rt_walk(const DevMesh &m, const Thresholds &th, const AngTab &ang, const LearnParams &lp,
+                          int all_pairs, float r_stop, int precision, double *rtv, unsigned long long *cnt,
+                          int *fallback, int *n_fallback, hipStream_t s)
+{
+    if (m.n == 0) return hipSuccess;
+    const bool L = lp.w != nullptr;
+#define BS_RW(P, LL)                                                                                               \
+    hipLaunchKernelGGL((k_rt_walk<P, LL>), dim3(m.n), dim3(64), 0, s, m, th, ang, lp, all_pairs, r_stop, rtv, cnt, \
+                       fallback, n_fallback)
+    if (precision == 0) {
+        if (L) BS_RW(0, true); else BS_RW(0, false);
+    } else if (precision == 1) {
+        if (L) BS_RW(1, true); else BS_RW(1, false);
+    } else {
+        if (L) BS_RW(2, true); else BS_RW(2, false);
+    }
+#undef BS_RW
     return hipGetLastError();
 }
 

@@ -263,3 +263,17 @@ def test_lagrangian_reports_inversion():
     assert ei.value.status == bs.BS_E_DEGENERATE
     assert np.array_equal(bs.bs_eval_velocity(h), v0)
     bs.bs_mesh_free(h)
+
+
+def test_walk_and_candidate_kernels_agree():
+    """Ray tracing by walking face neighbours (convex meshes) and by testing
+    candidate rays per pair compute the same chords; both match the oracle.
+    A non-convex mesh (ball-clipped) takes the candidate kernel."""
+    m = W.make_config("C1")
+    ref = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("pure_rt"))
+    v, st = gpu_eval(m, kind=bs.BS_POLICY_PURE_RT)
+    assert rel_l2(v, ref) <= TOL
+    b = W.ball_mesh(cells=8)
+    b.omega = W.field_gaussian_swirl(b.xyz)
+    vb, _ = gpu_eval(b)
+    assert rel_l2(vb, oracle.evaluate(b.xyz, b.omega, b.tets)) <= TOL
