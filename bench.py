@@ -38,7 +38,52 @@ def algorithmic_flops(st, nm):
     return (FLOPS_PER_POINT * (g1 + 4 * g4 + 11 * g11) + rt * (9.0 + 7.0 * nm) + 156.0 * st["rt_hit_lines"])
 
 
-def cpu_baseline(mesh, target_seconds=12.0):
+WORKLOAD_TEXT = {
+    "C1": "Gaussian swirl, [-1,1]^3, 10^3 Kuhn cells",
+    "C2": "vortex ring, [-1.5,1.5]^2 x [-0.5,0.5], 64x64x22 Kuhn cells",
+    "C3": "random Fourier curl field, [-1,1]^3, 48^3 Kuhn cells",
+    "C5": "two coaxial rings, [-1.5,1.5]^3, 80^3 Kuhn cells",
+}
+
+
+def measured_traffic(kernel, workload, precision):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the kernel source has changed since the counters were
+    taken (the summary records the sha256 of that source) or the run is not
+    the profiled configuration."""
+    import hashlib
+
+    if workload != "C2" or precision != 1:
+        return None
+    path = os.path.join(ROOT, "profiles", "bs_eval_velocity_C2_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_0712_1695_amd", "csrc", "bs_kernels.hip")
+    try:
+        lines = open(path).read().split("\n")
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    for ln in lines:
+        f = ln.split()
+        if len(f) == 4 and f[0] == "traffic" and f[1] == kernel and f[3] == sha:
+            return float(f[2])
+    return None
+
+
+def copy_calibration(mib):
+    """A plain device-to-device copy of a known size, so that the HBM byte
+    counters of a profiler can be scaled: it reads and writes mib MiB."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}), flush=True)
+
+
+def cpu_baseline(mesh, target_seconds=15.0):
     import oracle
 
     pol = oracle.make_policy("fixed")
@@ -49,9 +94,9 @@ def cpu_baseline(mesh, target_seconds=12.0):
         t0 = time.perf_counter()
         oracle.evaluate(mesh.xyz, mesh.omega, mesh.tets, pol, targets=tg)
         dt = time.perf_counter() - t0
-        if dt >= target_seconds / 4 or k >= mesh.n_nodes // 2:
+        if dt >= target_seconds / 2 or k >= mesh.n_nodes // 2:
             break
-        k = min(mesh.n_nodes // 2, int(k * max(2.0, target_seconds / 3 / max(dt, 1e-3))))
+        k = min(mesh.n_nodes // 2, int(k * max(2.0, target_seconds / max(dt, 1e-3))))
     pairs = k * mesh.n_tets
     return {"value": pairs / dt, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"{k} random nodes x all {mesh.n_tets} tets of the same workload (FP64, fixed rule), "
@@ -66,11 +111,17 @@ def main():
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", type=int, default=1)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain copy of MIB MiB (profiler byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); multi-GPU sharding is not built",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     import torch
 
@@ -117,7 +168,8 @@ def main():
         "peak": FP32_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": far_flops / far_t / 1e12 / FP32_PEAK_TFLOPS,
-        "traffic": None,
+        "traffic": measured_traffic("k_gauss_all", args.workload, args.precision),
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "avg_duration_ms": far_t * 1e3,
     }
     line = {
@@ -134,7 +186,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: vortex ring, 64x64x22 Kuhn cells, {mesh.n_nodes} nodes x "
+            "workload": f"{args.workload}: {WORKLOAD_TEXT.get(args.workload, mesh.name)}, {mesh.n_nodes} nodes x "
                         f"{mesh.n_tets} tets, fixed rule (RT < 2 hbar, G11 < 4, G4 < 8, else G1), 16x16 lines, "
                         f"{['fp32 naive', 'fp32 compensated', 'fp64 accumulation'][args.precision]}",
             "pairs_per_step": pairs,
