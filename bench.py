@@ -111,6 +111,8 @@ def main():
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", type=int, default=1)
+    ap.add_argument("--valu-far", action="store_true",
+                    help="far field on the vector ALUs instead of the matrix cores (comparison)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (profiler byte-counter calibration)")
     args = ap.parse_args()
@@ -141,14 +143,14 @@ def main():
     stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):
-        bs.bs_eval_velocity(h, out=out)
+        bs.bs_eval_velocity(h, out=out, valu_far=args.valu_far)
     torch.cuda.synchronize()
 
     kern = np.zeros(4)
     stats = None
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        _, stats = bs.bs_eval_velocity(h, out=out, stats=True)
+        _, stats = bs.bs_eval_velocity(h, out=out, stats=True, valu_far=args.valu_far)
         kern += np.array(stats["t_kernel_s"])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -159,16 +161,18 @@ def main():
     value = pairs / (wall / args.steps)
     flops = algorithmic_flops(stats, nm)
     g1_pairs = stats["pairs_by_rule"][0]
-    far_flops = FLOPS_PER_POINT * g1_pairs  # G1 pairs of the rule; the kernel evaluates all pairs
+    far_flops = FLOPS_PER_POINT * g1_pairs  # the method's flops of the G1 pairs
     far_t = kern[0]
+    far_name = "k_gauss_all" if (args.valu_far or args.precision == 2) else "k_far_mfma"
     roof = {
-        "kernel": "k_gauss_all (far field, 1-point rule, every pair)",
-        "bound": "alu",
+        "kernel": far_name + (" (far field, 1-point rule on every pair, vector ALUs)" if far_name == "k_gauss_all"
+                              else " (far field, the G1 pairs, FP32 matrix-core contractions)"),
+        "bound": "alu" if far_name == "k_gauss_all" else "mfma",
         "achieved": far_flops / far_t / 1e12,
         "peak": FP32_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": far_flops / far_t / 1e12 / FP32_PEAK_TFLOPS,
-        "traffic": measured_traffic("k_gauss_all", args.workload, args.precision),
+        "traffic": measured_traffic(far_name, args.workload, args.precision),
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "avg_duration_ms": far_t * 1e3,
     }

@@ -53,6 +53,11 @@ extern "C" {
 
 #define BS_PTR_HOST 0u
 #define BS_PTR_DEVICE 1u
+/* bs_eval_velocity only: take the far field of the fixed-rule policies on
+ * the vector ALUs (every pair by the 1-point rule, then the G1 term of the
+ * other pairs removed) instead of the matrix cores (G1 pairs only, FP32
+ * MFMA contractions).  Both compute the same sum; for comparison. */
+#define BS_EVAL_VALU_FAR 0x10u
 
 /* Rules a (node, tetrahedron) pair can be evaluated with. */
 #define BS_RULE_G1 0  /* 1-point Gauss rule (centroid), degree 1              */
@@ -68,7 +73,8 @@ extern "C" {
 
 /* Accumulation precision of the pair sums (the final per-node sum is FP64). */
 #define BS_PREC_FP32_NAIVE 0 /* one FP32 accumulator per component            */
-#define BS_PREC_FP32_COMP 1  /* FP32 tile sums folded by TwoSum (default)      */
+#define BS_PREC_FP32_COMP 1  /* FP32 sums over short tiles, folded by TwoSum
+                              * or in FP64 (default)                          */
 #define BS_PREC_FP64 2       /* FP32 pair terms accumulated in FP64            */
 
 typedef struct bs_mesh bs_mesh; /* opaque; owns all device memory */
@@ -148,9 +154,10 @@ typedef struct {
 } bs_stats;
 
 /* Velocity at every node, written to vel ([n_nodes][3] FP64, input node
- * order; host memory unless vel_flags has BS_PTR_DEVICE).  Uses the policy
- * last set (defaults if none).  st may be NULL.  Errors: BS_E_STATE (NULL
- * mesh), BS_E_ARG (NULL vel), BS_E_DEVICE (launch or runtime failure). */
+ * order; host memory unless vel_flags has BS_PTR_DEVICE; BS_EVAL_VALU_FAR
+ * selects the vector-ALU far field).  Uses the policy last set (defaults if
+ * none).  st may be NULL.  Errors: BS_E_STATE (NULL mesh), BS_E_ARG (NULL
+ * vel, unknown flag), BS_E_DEVICE (launch or runtime failure). */
 int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, bs_stats *st);
 
 /* Lagrangian motion of the nodes (the paper's setting, Sections 1 and 3:

@@ -37,6 +37,7 @@ BS_E_POLICY = -8
 
 BS_PTR_HOST = 0
 BS_PTR_DEVICE = 1
+BS_EVAL_VALU_FAR = 0x10
 
 BS_RULE_G1, BS_RULE_G4, BS_RULE_G11, BS_RULE_RT = 0, 1, 2, 3
 BS_POLICY_FIXED, BS_POLICY_PURE_RT, BS_POLICY_GAUSS_ONLY, BS_POLICY_LEARNED = 0, 1, 2, 3
@@ -277,14 +278,17 @@ def bs_set_policy(mesh: BsMesh, policy: Optional[Policy] = None, **kw):
     return p
 
 
-def bs_eval_velocity(mesh: BsMesh, out=None, stream=None, stats: bool = False):
+def bs_eval_velocity(mesh: BsMesh, out=None, stream=None, stats: bool = False, valu_far: bool = False):
     """Velocity at every node ([n,3] float64, input node order).  out: a
-    device torch tensor to fill (returned), else a new numpy array."""
+    device torch tensor to fill (returned), else a new numpy array.
+    valu_far: far field on the vector ALUs instead of the matrix cores."""
     L = load_library()
     st = Stats() if stats else None
+    extra = BS_EVAL_VALU_FAR if valu_far else 0
     if out is None:
         vel = np.empty((mesh.n_nodes, 3), dtype=np.float64)
-        rc = L.bs_eval_velocity(mesh.handle, ctypes.c_void_p(vel.ctypes.data), BS_PTR_HOST, _stream_handle(stream),
+        rc = L.bs_eval_velocity(mesh.handle, ctypes.c_void_p(vel.ctypes.data), BS_PTR_HOST | extra,
+                                _stream_handle(stream),
                                 ctypes.byref(st) if st is not None else None)
     else:
         if not (_is_torch(out) and out.is_cuda and out.dtype.__str__() == "torch.float64" and out.is_contiguous()):
@@ -292,8 +296,8 @@ def bs_eval_velocity(mesh: BsMesh, out=None, stream=None, stats: bool = False):
         if tuple(out.shape) != (mesh.n_nodes, 3):
             raise ValueError("out must have shape [n_nodes, 3]")
         vel = out
-        rc = L.bs_eval_velocity(mesh.handle, ctypes.c_void_p(out.data_ptr()), BS_PTR_DEVICE, _stream_handle(stream),
-                                ctypes.byref(st) if st is not None else None)
+        rc = L.bs_eval_velocity(mesh.handle, ctypes.c_void_p(out.data_ptr()), BS_PTR_DEVICE | extra,
+                                _stream_handle(stream), ctypes.byref(st) if st is not None else None)
     _check(rc, "bs_eval_velocity")
     return (vel, st.as_dict()) if stats else vel
 

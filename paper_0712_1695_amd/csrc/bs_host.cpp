@@ -219,6 +219,7 @@ struct bs_mesh {
     DBuf xh, xl, om, blk, node_orig, g1, g4, g11, tid, cell_start, nbr, inc_start, inc_list;
     DBuf part, band, rtv, vel, cnt, nonfinite, fallback;
     int rt_mode = 0; // 0: walk where the boundary is convex, 1: always the candidate kernel
+    int far_mode = 0; // 0: matrix-core far field (fixed-rule policies, FP32 modes), 1: vector-ALU kernel
     DBuf dir, dir64, cphi, dia;
     int part_splits = 0;
     // policy
@@ -988,9 +989,14 @@ int eval_device(bs_mesh *m, hipStream_t s)
     int splits = 0;
     const bool fixed_like = P.kind == BS_POLICY_FIXED || P.kind == BS_POLICY_LEARNED;
     const bool gauss_all = fixed_like || P.kind == BS_POLICY_GAUSS_ONLY;
+    // the fixed-rule far field runs on the matrix cores except in FP64 mode
+    const bool far_mfma = fixed_like && P.precision != BS_PREC_FP64 && m->far_mode == 0;
     if (gauss_all && m->T > 0) {
-        splits = std::max(1, std::min<int>((int)((4096 + 4 * node_blocks - 1) / (4 * node_blocks)),
-                                           (int)((m->T + 255) / 256)));
+        if (far_mfma)
+            splits = std::max(1, std::min<int>((4096 + m->nblk - 1) / m->nblk, (int)((m->T + 2047) / 2048)));
+        else
+            splits = std::max(1, std::min<int>((int)((4096 + 4 * node_blocks - 1) / (4 * node_blocks)),
+                                               (int)((m->T + 255) / 256)));
         if ((rc = dalloc(m->part, 8 * 3 * (size_t)m->npad * splits))) return rc;
     }
     bsk::Thresholds th{};
@@ -1022,6 +1028,10 @@ int eval_device(bs_mesh *m, hipStream_t s)
             if ((e = bsk::launch_gauss_all(dm, pts, P.precision, splits, (double *)m->part.p, s)))
                 return hip_fail(e, "gauss kernel");
             part = (const double *)m->part.p;
+        } else if (far_mfma) {
+            if ((e = bsk::launch_far_mfma(dm, th, P.precision, splits, (double *)m->part.p, s)))
+                return hip_fail(e, "far-field kernel");
+            part = (const double *)m->part.p;
         } else if (fixed_like) {
             if ((e = bsk::launch_gauss_all(dm, 1, P.precision, splits, (double *)m->part.p, s)))
                 return hip_fail(e, "far-field kernel");
@@ -1030,7 +1040,7 @@ int eval_device(bs_mesh *m, hipStream_t s)
     }
     (void)hipEventRecord(m->ev[1], s);
     if (m->T > 0 && fixed_like) {
-        if ((e = bsk::launch_band(dm, th, P.precision, (double *)m->band.p, cnt, s)))
+        if ((e = bsk::launch_band(dm, th, P.precision, far_mfma ? 0 : 1, (double *)m->band.p, cnt, s)))
             return hip_fail(e, "band kernel");
         band = (const double *)m->band.p;
     }
@@ -1114,9 +1124,11 @@ int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, 
     g_err.clear();
     if (!m) return fail(BS_E_STATE, "null mesh");
     if (!vel) return fail(BS_E_ARG, "null output");
-    if (vel_flags & ~BS_PTR_DEVICE) return fail(BS_E_ARG, "unknown flags 0x%x", vel_flags);
+    if (vel_flags & ~(BS_PTR_DEVICE | BS_EVAL_VALU_FAR)) return fail(BS_E_ARG, "unknown flags 0x%x", vel_flags);
     hipStream_t s = (hipStream_t)stream;
+    m->far_mode = (vel_flags & BS_EVAL_VALU_FAR) ? 1 : 0;
     int rc = eval_device(m, s);
+    m->far_mode = 0;
     if (rc) return rc;
     hipError_t e;
     const size_t vbytes = 8 * 3 * (size_t)m->n;

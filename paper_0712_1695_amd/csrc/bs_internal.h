@@ -82,7 +82,11 @@ constexpr int kNumCounters = 8;
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_gauss_all(const DevMesh &m, int rule_pts, int precision, int splits, double *part,
                             hipStream_t s);
-hipError_t launch_band(const DevMesh &m, const Thresholds &th, int precision, double *band,
+// Far field of the fixed-rule policies (G1 pairs only), precision 0 or 1.
+hipError_t launch_far_mfma(const DevMesh &m, const Thresholds &th, int precision, int splits, double *part,
+                           hipStream_t s);
+// sub_g1: also remove the G1 term of non-G1 pairs (after launch_gauss_all).
+hipError_t launch_band(const DevMesh &m, const Thresholds &th, int precision, int sub_g1, double *band,
                        unsigned long long *cnt, hipStream_t s);
 hipError_t launch_rt(const DevMesh &m, const Thresholds &th, const AngTab &ang, const LearnParams &lp,
                      int all_pairs, int precision, double *rtv, unsigned long long *cnt, const int *node_list,

@@ -25,8 +25,10 @@
 // Kernels:
 //   k_gauss_all  every pair by one Gauss rule (G1 for the fixed policy:
 //                the far field of all pairs), tet records wave-uniform;
-//   k_band       per 64-node block: for pairs whose fixed rule is not G1,
-//                remove the G1 term and add the G4 / G11 one;
+//   k_far_mfma   the G1 pairs of the fixed rule on the matrix cores (FP32
+//                MFMA; pairs with another rule masked out);
+//   k_band       per 64-node block: pairs whose fixed rule is G4 / G11
+//                (after k_gauss_all: also remove their G1 term);
 //   k_rt         one wave per node: ray tracing of its near tetrahedra;
 //   k_combine    FP64 sum of the partials, back to input node order.
 #include "bs_internal.h"
@@ -265,6 +267,254 @@ hipError_t launch_gauss_all(const DevMesh &m, int rule_pts, int precision, int s
 }
 
 // ---------------------------------------------------------------------------
+// Far field of the fixed-rule policies on the matrix cores.
+//
+// With positions relative to the centre c of a 64-node block (x' = x - c,
+// p' = p - c) the 1-point term of a pair is s W x (x' - p') with
+// s = |x' - p'|^-3, so the block's far field is
+//   v(x) = (sum_t s W_t) x x' - sum_t s (W_t x p'_t).
+// Both sums over the tets are contractions:
+//   |x' - p'|^2 = |x'|^2 + [x', 1] . [-2 p', |p'|^2]        (K = 4)
+// on v_mfma_f32_16x16x4f32 (rows = 16 tets, columns = 16 nodes), then
+//   sum_t s [W, W x p']
+// on the 16 independent 4x4 blocks of v_mfma_f32_4x4x1f32.  The operand
+// lanes of the second line up with the output lanes of the first (block b =
+// lanes 4b..4b+3 = one tet and four nodes), so the reciprocal cubes pass from
+// one to the other in registers.
+// Pairs whose rule is not G1 are masked out: in a tile of 16 tets any of
+// whose centroids lies within r_band of the block's bounding sphere, every
+// pair is classified by fixed_rule (the band and ray-tracing kernels take
+// the others); outside the band every pair of the block is G1.
+//
+// Workgroup = 4 waves = one block of 64 nodes (4 node tiles of 16) and one
+// split of the tet range.  Every chunk of 256 tets is prepared once into LDS
+// (double buffered); wave w takes tet tiles w, w+4, w+8, w+12 of the chunk
+// against all four node tiles.  Lane l: node l%16 of a node tile, tets
+// 4(l/16)+j, j < 4, of a tet tile.
+// The records of chunk k+2 are loaded into registers while chunk k is
+// computed and stored to LDS in the next step, so the loads' latency hides
+// behind a whole chunk of work.
+// PREC 0: FP32 accumulation throughout; PREC 1: the FP32 sums of every two
+// chunks are added in FP64.
+constexpr int kFarChunk = 256;
+
+struct FarLds {
+    union {
+        struct {
+            float a1[2][16][64];           // [buf][tile][k*16 + i]: -2p'_k (k < 3), |p'|^2 (k = 3) of tet i
+            float a2[2][16][4][4][8];      // [buf][tile][q][c][2j + h]: component 4h + c of [W, W x p'] of tet 4q + j
+            float4 pc[2][kFarChunk];       // binary32 centroid (the rule's) of each tet of the chunk
+            int4 ids[2][kFarChunk];        // vertex ids (sorted numbering)
+            unsigned long long band[2][4]; // per 64 tets: bit = centroid within the band of the block
+        } c;
+        double red[4][4][6][16];           // [wave][node tile][component][node]
+    };
+    float4 xn[64];                         // binary32 node coordinates (the rule's), by node of the block
+};
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int PREC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_far_mfma(DevMesh m, Thresholds th, int per_split,
+                                                  double *__restrict__ part)
+{
+    __shared__ FarLds S;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int q = lane >> 4, i16 = lane & 15, c4 = lane & 3;
+    const int b = blockIdx.x;
+    const int t0 = blockIdx.y * per_split;
+    const int t1 = min(m.T, t0 + per_split);
+    const float4 bc = m.blk[b];
+    const float rb = bc.w + th.r_band;
+    const float rb2 = rb * rb;
+
+    // node operands: B = [x', 1] (component q of the lane), C = |x'|^2
+    float B1[4], Cin[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int i = b * kBlockNodes + 16 * nt + i16;
+        float xp[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float cc = c == 0 ? bc.x : c == 1 ? bc.y : bc.z;
+            xp[c] = i < m.n ? (m.xh[c * m.npad + i] - cc) + m.xl[c * m.npad + i] : 0.f;
+        }
+        B1[nt] = q == 0 ? xp[0] : q == 1 ? xp[1] : q == 2 ? xp[2] : 1.f;
+        Cin[nt] = i < m.n ? (xp[0] * xp[0] + xp[1] * xp[1]) + xp[2] * xp[2] : 1e30f;
+    }
+    if (tid < 64) {
+        const int i = b * kBlockNodes + tid;
+        S.xn[tid] = make_float4(m.xh[i], m.xh[m.npad + i], m.xh[2 * m.npad + i], 0.f);
+    }
+
+    f32x4 D0[4], D1[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) D0[nt] = D1[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}; // node 16q + i16 of the block after each fold
+
+    // the record of tet c0 + tid, in flight in registers until stored (the
+    // index is clamped so that the loads need no branch; tets past the end
+    // of the split are replaced at the store)
+    float4 pg;
+    float2 pw;
+    int4 pid;
+    int pt;
+    auto load = [&](int c0) {
+        pt = c0 + tid;
+        const int t = min(pt, t1 - 1);
+        const float *g = m.g1 + (size_t)t * kRecG;
+        pg = *(const float4 *)g;
+        pw = *(const float2 *)(g + 4);
+        pid = m.tid[t];
+    };
+    auto store = [&](int buf) {
+        const int tile = tid >> 4, i = tid & 15, qq = i >> 2, j = i & 3;
+        const bool pok = pt < t1;
+        float pr[6] = {pg.x, pg.y, pg.z, pg.w, pw.x, pw.y};
+        if (!pok) {
+            pr[0] = bc.x;
+            pr[1] = bc.y;
+            pr[2] = bc.z;
+            pr[3] = pr[4] = pr[5] = 0.f;
+        }
+        const float px = pr[0] - bc.x, py = pr[1] - bc.y, pz = pr[2] - bc.z;
+        const float n2 = (px * px + py * py) + pz * pz;
+        const bool inb = pok && n2 < rb2;
+        S.c.a1[buf][tile][i] = -2.f * px;
+        S.c.a1[buf][tile][16 + i] = -2.f * py;
+        S.c.a1[buf][tile][32 + i] = -2.f * pz;
+        S.c.a1[buf][tile][48 + i] = pok ? n2 : 1e30f;
+        const float comp[8] = {pr[3], pr[4], pr[5], pr[4] * pz - pr[5] * py, pr[5] * px - pr[3] * pz,
+                               pr[3] * py - pr[4] * px, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) S.c.a2[buf][tile][qq][c][2 * j + h] = comp[4 * h + c];
+        S.c.pc[buf][tid] = make_float4(pr[0], pr[1], pr[2], 0.f);
+        S.c.ids[buf][tid] = pok ? pid : make_int4(-1, -1, -1, -1);
+        const unsigned long long bal = __ballot(inb);
+        if (lane == 0) S.c.band[buf][wave] = bal;
+    };
+    // sum the four tet streams of every node (lanes l, l^16, l^32, l^48) in
+    // FP32 and add node tile q's six sums into acc in FP64
+    auto fold = [&]() {
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                float v = r < 4 ? D0[nt][r] : D1[nt][r - 4];
+                v += __shfl_xor(v, 16, 64);
+                v += __shfl_xor(v, 32, 64);
+                if (q == nt) acc[r] += (double)v;
+            }
+            D0[nt] = D1[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        }
+    };
+
+    if (t0 < t1) {
+        load(t0);
+        store(0);
+        if (t0 + kFarChunk < t1) load(t0 + kFarChunk);
+    }
+    __syncthreads();
+    int k = 0;
+    for (int c0 = t0; c0 < t1; c0 += kFarChunk, ++k) {
+        const int buf = k & 1;
+        if (c0 + kFarChunk < t1) {
+            store(buf ^ 1);
+            if (c0 + 2 * kFarChunk < t1) load(c0 + 2 * kFarChunk);
+        }
+#pragma unroll 1
+        for (int u = 0; u < 4; ++u) {
+            const int tile = wave + 4 * u;
+            const unsigned long long bw = S.c.band[buf][tile >> 2];
+            const unsigned bmask = __builtin_amdgcn_readfirstlane((unsigned)(bw >> (16 * (tile & 3))) & 0xffffu);
+            const float A1 = S.c.a1[buf][tile][lane];
+            const float4 v0 = *(const float4 *)&S.c.a2[buf][tile][q][c4][0];
+            const float4 v1 = *(const float4 *)&S.c.a2[buf][tile][q][c4][4];
+            const float A2[4][2] = {{v0.x, v0.y}, {v0.z, v0.w}, {v1.x, v1.y}, {v1.z, v1.w}};
+            f32x4 r2[4];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                r2[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A1, B1[nt], (f32x4){Cin[nt], Cin[nt], Cin[nt], Cin[nt]},
+                                                             0, 0, 0);
+            float sv[4][4];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float iv = __builtin_amdgcn_rsqf(r2[nt][j]);
+                    sv[nt][j] = iv * iv * iv;
+                }
+            if (bmask) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int e = tile * 16 + 4 * q + j;
+                    const float4 pc = S.c.pc[buf][e];
+                    const int4 id = S.c.ids[buf][e];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const float4 xn = S.xn[16 * nt + i16];
+                        const int rule = fixed_rule(xn.x, xn.y, xn.z, pc.x, pc.y, pc.z, id,
+                                                    b * kBlockNodes + 16 * nt + i16, th);
+                        sv[nt][j] = rule == RULE_G1 ? sv[nt][j] : 0.f;
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    D0[nt] = __builtin_amdgcn_mfma_f32_4x4x1f32(A2[j][0], sv[nt][j], D0[nt], 0, 0, 0);
+                    D1[nt] = __builtin_amdgcn_mfma_f32_4x4x1f32(A2[j][1], sv[nt][j], D1[nt], 0, 0, 0);
+                }
+        }
+        if (PREC == 1 && (k & 1)) fold();
+        __syncthreads();
+    }
+    fold();
+    // combine the waves (each took a quarter of every chunk)
+#pragma unroll
+    for (int r = 0; r < 6; ++r) S.red[wave][q][r][i16] = acc[r];
+    __syncthreads();
+    if (tid < 64) {
+        const int nt = tid >> 4, n16 = tid & 15;
+        double sw[6];
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+            sw[r] = ((S.red[0][nt][r][n16] + S.red[1][nt][r][n16]) + S.red[2][nt][r][n16]) + S.red[3][nt][r][n16];
+        const int i = b * kBlockNodes + tid;
+        double xp[3] = {0.0, 0.0, 0.0};
+        if (i < m.n) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float cc = c == 0 ? bc.x : c == 1 ? bc.y : bc.z;
+                xp[c] = (double)((m.xh[c * m.npad + i] - cc) + m.xl[c * m.npad + i]);
+            }
+        }
+        double *o = part + (size_t)blockIdx.y * 3 * m.npad;
+        o[i] = (sw[1] * xp[2] - sw[2] * xp[1]) - sw[3];
+        o[m.npad + i] = (sw[2] * xp[0] - sw[0] * xp[2]) - sw[4];
+        o[2 * m.npad + i] = (sw[0] * xp[1] - sw[1] * xp[0]) - sw[5];
+    }
+}
+
+hipError_t launch_far_mfma(const DevMesh &m, const Thresholds &th, int precision, int splits, double *part,
+                           hipStream_t s)
+{
+    if (splits < 1 || precision < 0 || precision > 1) return hipErrorInvalidValue;
+    const int per = ((m.T + splits - 1) / splits + kFarChunk - 1) / kFarChunk * kFarChunk;
+    const dim3 grid(m.nblk, splits);
+    if (precision == 0)
+        hipLaunchKernelGGL(k_far_mfma<0>, grid, dim3(256), 0, s, m, th, per, part);
+    else
+        hipLaunchKernelGGL(k_far_mfma<1>, grid, dim3(256), 0, s, m, th, per, part);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Rows of bins (fixed y, z; x range clipped to the ball) intersecting the
 // ball (c, R); next() yields the contiguous tet range of each row in turn.
 struct RowIter {
@@ -316,13 +566,15 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // Band corrections.  One workgroup of kBandWaves waves per 64 consecutive
 // (Morton-ordered) nodes; lane = node, the waves take the bin rows of the
 // block's neighbourhood in turn.  For every tet whose centroid lies within
-// r_band of the block's bounding sphere: lanes whose pair rule is not G1
-// subtract the G1 term added by k_gauss_all, then lanes with G4 / G11 add
-// that rule (ray-traced pairs are added by k_rt).  The waves' partial sums
+// r_band of the block's bounding sphere: with SUB (the far field came from
+// k_gauss_all, which took every pair by G1) lanes whose pair rule is not G1
+// subtract that G1 term; then lanes with G4 / G11 add that rule (ray-traced
+// pairs are added by k_rt).  Without SUB the far field (k_far_mfma) already
+// left out every pair that is not G1.  The waves' partial sums
 // are combined in FP64 through LDS.
 constexpr int kBandWaves = 4;
 
-template <int PREC>
+template <int PREC, bool SUB>
 __global__ void __launch_bounds__(64 * kBandWaves) k_band(DevMesh m, Thresholds th, double *__restrict__ band,
                                                           unsigned long long *__restrict__ cnt)
 {
@@ -346,7 +598,7 @@ __global__ void __launch_bounds__(64 * kBandWaves) k_band(DevMesh m, Thresholds 
             const int4 id = m.tid[t];
             const float gx = g[0], gy = g[1], gz = g[2];
             const int rule = valid ? fixed_rule(x, y, z, gx, gy, gz, id, i, th) : RULE_G1;
-            if (rule != RULE_G1) {
+            if (SUB && rule != RULE_G1) {
                 float a = 0.f, b = 0.f, c = 0.f;
                 gauss_point(x, y, z, g, a, b, c);
                 ax -= a;
@@ -406,16 +658,25 @@ __global__ void __launch_bounds__(64 * kBandWaves) k_band(DevMesh m, Thresholds 
     }
 }
 
-hipError_t launch_band(const DevMesh &m, const Thresholds &th, int precision, double *band,
+hipError_t launch_band(const DevMesh &m, const Thresholds &th, int precision, int sub_g1, double *band,
                        unsigned long long *cnt, hipStream_t s)
 {
     const dim3 blk(64 * kBandWaves);
-    if (precision == 0)
-        hipLaunchKernelGGL(k_band<0>, dim3(m.nblk), blk, 0, s, m, th, band, cnt);
-    else if (precision == 1)
-        hipLaunchKernelGGL(k_band<1>, dim3(m.nblk), blk, 0, s, m, th, band, cnt);
-    else
-        hipLaunchKernelGGL(k_band<2>, dim3(m.nblk), blk, 0, s, m, th, band, cnt);
+    if (sub_g1) {
+        if (precision == 0)
+            hipLaunchKernelGGL((k_band<0, true>), dim3(m.nblk), blk, 0, s, m, th, band, cnt);
+        else if (precision == 1)
+            hipLaunchKernelGGL((k_band<1, true>), dim3(m.nblk), blk, 0, s, m, th, band, cnt);
+        else
+            hipLaunchKernelGGL((k_band<2, true>), dim3(m.nblk), blk, 0, s, m, th, band, cnt);
+    } else {
+        if (precision == 0)
+            hipLaunchKernelGGL((k_band<0, false>), dim3(m.nblk), blk, 0, s, m, th, band, cnt);
+        else if (precision == 1)
+            hipLaunchKernelGGL((k_band<1, false>), dim3(m.nblk), blk, 0, s, m, th, band, cnt);
+        else
+            hipLaunchKernelGGL((k_band<2, false>), dim3(m.nblk), blk, 0, s, m, th, band, cnt);
+    }
     return hipGetLastError();
 }
 
