@@ -117,9 +117,12 @@ void bs_mesh_free(bs_mesh *m);
  *   d_g11 <= d < d_g4                  -> 4-point rule,
  *   d >= d_g4                          -> 1-point rule.
  * The comparison is taken in binary32 on d^2.  LEARNED uses a 16-64-64-4
- * network (BF16 weights, layout documented at bs_mlp_* below) to pick a
- * cheaper rule for pairs the fixed rule sends to RT or G11; below conf_min
- * softmax confidence it keeps the fixed rule. */
+ * network (BF16 weights, layout documented at bs_mlp_* below) for the pairs
+ * the fixed rule ray-traces whose tet does not contain the node: with p the
+ * softmax of its logits over (G1, G4, G11, RT), the pair takes the cheapest
+ * Gauss rule r with p_G1 + ... + p_r >= conf_min (the predicted probability
+ * that r meets the error budget it was trained on), else keeps the fixed
+ * rule. */
 typedef struct {
     int kind;                 /* BS_POLICY_*                                    */
     int n_phi, n_theta;       /* N, M: each in [1, 256]                         */

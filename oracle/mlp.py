@@ -8,6 +8,12 @@ class-weighted softmax cross-entropy:
 Backward pass written out from the chain rule (no autodiff); pinned by
 central finite differences in the tests.
 
+forward_bf16 / decide_bf16 take the decision in the precision of a BF16
+inference (the selector's own precision): the standardised inputs and the
+two hidden activations are rounded to bfloat16 there, products and sums
+are exact here (FP64); decide_bf16 also flags the rows whose outcome a
+rounding difference in those sums could change.
+
 Parameter blob layout (the same order as the library's packed BF16 blob):
 mu[16], inv_sigma[16], W1[16][64], b1[64], W2[64][64], b2[64], W3[64][4], b3[4].
 """
@@ -81,14 +87,51 @@ def loss_and_grads(p, X, y, class_w):
     return loss, g
 
 
+def _ordinal(z, fallback, conf_min):
+    """Cheapest class r in (0, 1, 2) whose softmax mass p_0 + ... + p_r is
+    at least conf_min (classes ordered by cost); rows where none is keep
+    the fallback."""
+    e = np.exp(z - z.max(axis=1, keepdims=True))
+    C = np.cumsum(e / e.sum(axis=1, keepdims=True), axis=1)
+    rule = np.array(np.broadcast_to(np.asarray(fallback), (z.shape[0],)), dtype=np.int64)
+    for r in (2, 1, 0):
+        rule = np.where(C[:, r] >= conf_min, r, rule)
+    return rule, C
+
+
 def decide(p, X, fallback, conf_min):
-    """Rule per row: argmax of the logits (ties to the more expensive rule,
-    i.e. the larger index); rows whose softmax maximum is below conf_min
-    keep the fallback rule."""
-    z3 = forward(p, X)["z3"]
-    zmax = z3.max(axis=1, keepdims=True)
-    e = np.exp(z3 - zmax)
-    prob = e / e.sum(axis=1, keepdims=True)
-    arg = 3 - np.argmax(z3[:, ::-1], axis=1)
-    keep = prob.max(axis=1) < conf_min
-    return np.where(keep, np.asarray(fallback), arg)
+    """Rule per row: the cheapest Gauss rule r whose predicted probability of
+    meeting the error budget, P(label <= r), is at least conf_min; rows
+    where no Gauss rule is keep the fallback."""
+    return _ordinal(forward(p, X)["z3"], fallback, conf_min)[0]
+
+
+def forward_bf16(p, X):
+    """Logits with the rounding points of a BF16 inference."""
+    xs = bf16_round((np.asarray(X, dtype=np.float64) - p["mu"]) * p["inv_sigma"])
+    a1 = bf16_round(np.maximum(xs @ p["W1"] + p["b1"], 0.0))
+    a2 = bf16_round(np.maximum(a1 @ p["W2"] + p["b2"], 0.0))
+    return a2 @ p["W3"] + p["b3"]
+
+
+def decide_bf16(p, X, fallback, conf_min, margin=0.01):
+    """decide() with forward_bf16.  Returns (rule [P], alternatives [P, 3]):
+    the other rules (-1 = none) that a rounding difference in the network's
+    sums could give.  The decision only moves when a cumulative probability
+    crosses conf_min, and it is monotone in them, so the possible outcomes
+    are the classes between the decisions taken at conf_min - margin and at
+    conf_min + margin ("no Gauss rule" counted as class 3, the fallback)."""
+    z = forward_bf16(p, X)
+    P = z.shape[0]
+    fb = np.broadcast_to(np.asarray(fallback), (P,))
+    none = np.full(P, 3)
+    rule3, C = _ordinal(z, none, conf_min)
+    lo, _ = _ordinal(z, none, conf_min - margin)
+    hi, _ = _ordinal(z, none, conf_min + margin)
+    rule = np.where(rule3 == 3, fb, rule3)
+    alt = np.full((P, 3), -1, dtype=np.int64)
+    for row in np.nonzero(lo != hi)[0]:
+        outs = [r if r < 3 else int(fb[row]) for r in range(lo[row], hi[row] + 1)]
+        outs = [o for o in outs if o != rule[row]][:3]
+        alt[row, :len(outs)] = outs
+    return rule, alt

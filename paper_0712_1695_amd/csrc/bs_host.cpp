@@ -225,7 +225,8 @@ struct bs_mesh {
     // policy
     bs_policy pol{};
     int ang_N = 0, ang_M = 0;
-    DBuf mlp; // BF16 network blob of the learned policy
+    DBuf mlp; // the learned policy's network in the fused inference's operand order
+    DBuf sel; // learned policy on walk meshes: ray-traced lists, their counts and farthest centroids
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
@@ -792,6 +793,53 @@ bsk::DevMesh dev_view(const bs_mesh *m)
     return d;
 }
 
+// The selector's BF16 blob (mu[16], inv_sigma[16], W1[16][64], b1[64],
+// W2[64][64], b2[64], W3[64][4], b3[4]) in the operand order of the fused
+// inference (the byte layout of bsk::PackedNet): A-operand vectors of the
+// transposed layers, with the K index k = 8h + s of k-tile kt of layers 2
+// and 3 reading unit U(kt, h, s) = 32(kt/2) + 8(2(kt%2) + s/4) + 4h + s%4,
+// and the biases in output-register order.
+std::vector<uint8_t> pack_network(const uint16_t *blob)
+{
+    const uint16_t *mu = blob, *isg = blob + 16, *W1 = blob + 32, *b1 = W1 + 16 * 64, *W2 = b1 + 64,
+                   *b2 = W2 + 64 * 64, *W3 = b2 + 64, *b3 = W3 + 64 * 4;
+    auto f32 = [](uint16_t b) {
+        const uint32_t u = (uint32_t)b << 16;
+        float x;
+        std::memcpy(&x, &u, 4);
+        return x;
+    };
+    auto U = [](int kt, int h, int s) { return 32 * (kt >> 1) + 8 * (2 * (kt & 1) + (s >> 2)) + 4 * h + (s & 3); };
+    std::vector<uint8_t> out((size_t)bsk::kPackedNetBytes, 0);
+    uint16_t *w1 = (uint16_t *)out.data(); // [2][64][8]
+    uint16_t *w2 = w1 + 2 * 64 * 8;        // [2][4][64][8]
+    uint16_t *w3 = w2 + 2 * 4 * 64 * 8;    // [4][64][8]
+    float *fb = (float *)(w3 + 4 * 64 * 8);
+    float *fb1 = fb, *fb2 = fb + 64, *fb3 = fb + 128, *fmu = fb + 132, *fisg = fb + 148;
+    for (int l = 0; l < 64; ++l)
+        for (int sidx = 0; sidx < 8; ++sidx) {
+            const int h = l >> 5, col = l & 31;
+            for (int rt = 0; rt < 2; ++rt) {
+                w1[(rt * 64 + l) * 8 + sidx] = W1[(8 * h + sidx) * 64 + 32 * rt + col];
+                for (int kt = 0; kt < 4; ++kt) w2[((rt * 4 + kt) * 64 + l) * 8 + sidx] = W2[U(kt, h, sidx) * 64 + 32 * rt + col];
+            }
+            for (int kt = 0; kt < 4; ++kt) w3[(kt * 64 + l) * 8 + sidx] = col < 4 ? W3[U(kt, h, sidx) * 4 + col] : 0;
+        }
+    for (int rt = 0; rt < 2; ++rt)
+        for (int h = 0; h < 2; ++h)
+            for (int r = 0; r < 16; ++r) {
+                const int u = 32 * rt + 8 * (r >> 2) + 4 * h + (r & 3);
+                fb1[(rt * 2 + h) * 16 + r] = f32(b1[u]);
+                fb2[(rt * 2 + h) * 16 + r] = f32(b2[u]);
+            }
+    for (int c = 0; c < 4; ++c) fb3[c] = f32(b3[c]);
+    for (int k = 0; k < 16; ++k) {
+        fmu[k] = f32(mu[k]);
+        fisg[k] = f32(isg[k]);
+    }
+    return out;
+}
+
 int check_policy(const bs_policy *p)
 {
     if (p->kind < BS_POLICY_FIXED || p->kind > BS_POLICY_LEARNED)
@@ -948,7 +996,7 @@ void bs_mesh_free(bs_mesh *m)
     DBuf *bufs[] = {&m->xh, &m->xl, &m->om, &m->blk, &m->node_orig, &m->g1, &m->g4, &m->g11, &m->tid,
                     &m->nbr, &m->inc_start, &m->inc_list, &m->fallback,
                     &m->cell_start, &m->part, &m->band, &m->rtv, &m->vel, &m->cnt, &m->nonfinite, &m->dir,
-                    &m->dir64, &m->cphi, &m->dia, &m->mlp};
+                    &m->dir64, &m->cphi, &m->dia, &m->mlp, &m->sel};
     for (DBuf *b : bufs) dfree(*b);
     for (auto &e : m->ev)
         if (e) (void)hipEventDestroy(e);
@@ -963,8 +1011,9 @@ int bs_set_policy(bs_mesh *m, const bs_policy *p)
     int rc = check_policy(p);
     if (rc) return rc;
     if (p->kind == BS_POLICY_LEARNED) {
-        if ((rc = dalloc(m->mlp, 2 * bsk::kMlpBlobLen))) return rc;
-        hipError_t e = hipMemcpy(m->mlp.p, p->mlp_bf16, 2 * bsk::kMlpBlobLen, hipMemcpyHostToDevice);
+        const std::vector<uint8_t> img = pack_network(p->mlp_bf16);
+        if ((rc = dalloc(m->mlp, img.size()))) return rc;
+        hipError_t e = hipMemcpy(m->mlp.p, img.data(), img.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "upload network");
     }
     m->pol = *p;
@@ -1007,6 +1056,8 @@ int eval_device(bs_mesh *m, hipStream_t s)
     th.g4_2 = (float)(c_4 * c_4);
     th.r_band = (float)(std::max(c_4, m->max_vc) * (1.0 + 1e-4) + 1e-6);
     th.r_rt = (float)(std::max(c_rt, m->max_vc) * (1.0 + 1e-4) + 1e-6);
+    th.vc = (float)(m->max_vc * (1.0 + 1e-4) + 1e-6);
+    th.inc_far = m->max_vc < c_4 * (1.0 - 1e-5) ? 0 : 1;
     bsk::AngTab ang{};
     ang.dir = (const float4 *)m->dir.p;
     ang.dir64 = (const double *)m->dir64.p;
@@ -1046,7 +1097,7 @@ int eval_device(bs_mesh *m, hipStream_t s)
     }
     (void)hipEventRecord(m->ev[2], s);
     bsk::LearnParams lp{};
-    lp.w = P.kind == BS_POLICY_LEARNED ? (const __bf16 *)m->mlp.p : nullptr;
+    lp.net = P.kind == BS_POLICY_LEARNED ? (const bsk::PackedNet *)m->mlp.p : nullptr;
     lp.conf_min = P.conf_min;
     lp.hbar = (float)m->hbar;
     if (m->T > 0 && (fixed_like || P.kind == BS_POLICY_PURE_RT)) {
@@ -1055,9 +1106,20 @@ int eval_device(bs_mesh *m, hipStream_t s)
             if ((rc = dalloc(m->fallback, 4 * ((size_t)m->n + 1)))) return rc;
             int *nfb = (int *)m->fallback.p + m->n;
             const float r_stop = all ? 3.0e38f : (float)((std::max(c_rt, m->max_vc) + m->max_vc) * (1.0 + 1e-4) + 1e-6);
+            int *sel_list = nullptr, *sel_n = nullptr;
+            float *sel_dmax = nullptr;
+            if (lp.net) {
+                const size_t nn = (size_t)m->n;
+                if ((rc = dalloc(m->sel, 4 * (nn * bsk::kSelListCap + 2 * nn)))) return rc;
+                sel_list = (int *)m->sel.p;
+                sel_n = sel_list + nn * bsk::kSelListCap;
+                sel_dmax = (float *)(sel_n + nn);
+            }
             if ((e = hipMemsetAsync(nfb, 0, 4, s)) ||
-                (e = bsk::launch_rt_walk(dm, th, ang, lp, all, r_stop, P.precision, (double *)m->rtv.p, cnt,
-                                         (int *)m->fallback.p, nfb, s)) ||
+                (lp.net && (e = bsk::launch_select(dm, th, lp, P.precision, (double *)m->rtv.p, cnt, sel_list, sel_n,
+                                                   sel_dmax, s))) ||
+                (e = bsk::launch_rt_walk(dm, th, ang, all, r_stop, P.precision, (double *)m->rtv.p, cnt,
+                                         (int *)m->fallback.p, nfb, sel_list, sel_n, sel_dmax, s)) ||
                 (e = bsk::launch_rt(dm, th, ang, lp, all, P.precision, (double *)m->rtv.p, cnt,
                                     (const int *)m->fallback.p, nfb, s)))
                 return hip_fail(e, "ray-tracing walk");

@@ -43,6 +43,8 @@ struct Thresholds {
     float rt2, g11_2, g4_2; // squared cut distances, binary32
     float r_band;           // scan radius of the band kernel (>= d_g4 hbar, max vertex-centroid distance)
     float r_rt;             // scan radius of the ray-tracing kernel
+    float vc;               // largest vertex-centroid distance of any tet (with margin)
+    int inc_far;            // 1 if a tet having the node as a vertex can lie beyond the G4 cut
 };
 
 struct AngTab {
@@ -53,10 +55,14 @@ struct AngTab {
     int N, M2;            // rows, columns (2M)
 };
 
-// Learned rule selector: BF16 weight blob (device), softmax confidence
-// threshold, mean edge length (feature scale).  w == nullptr: fixed rule.
+struct PackedNet; // the selector's weights in MFMA operand order (bs_mlp_dev.h)
+// bytes of a PackedNet: w1, w2, w3 (BF16 operand vectors), b1, b2, b3, mu, isg (FP32)
+constexpr int kPackedNetBytes = 2 * (2 * 64 * 8 + 2 * 4 * 64 * 8 + 4 * 64 * 8) + 4 * (64 + 64 + 4 + 16 + 16);
+
+// Learned rule selector: packed network (device), confidence threshold,
+// mean edge length (feature scale).  net == nullptr: fixed rule.
 struct LearnParams {
-    const __bf16 *w;
+    const PackedNet *net;
     float conf_min;
     float hbar;
 };
@@ -91,11 +97,18 @@ hipError_t launch_band(const DevMesh &m, const Thresholds &th, int precision, in
 hipError_t launch_rt(const DevMesh &m, const Thresholds &th, const AngTab &ang, const LearnParams &lp,
                      int all_pairs, int precision, double *rtv, unsigned long long *cnt, const int *node_list,
                      const int *node_count, hipStream_t s);
+// The learned policy's selection pass for the walk: Gauss terms of the pairs
+// the selector moves (written to rtv) and the pairs still ray traced
+// (sel_list[n][kSelListCap], sel_n[n] = count or -1: left to launch_rt).
+constexpr int kSelListCap = 128;
+hipError_t launch_select(const DevMesh &m, const Thresholds &th, const LearnParams &lp, int precision, double *rtv,
+                         unsigned long long *cnt, int *sel_list, int *sel_n, float *sel_dmax, hipStream_t s);
 // Walk variant (convex meshes); nodes it cannot hold are appended to
-// fallback[*n_fallback] for launch_rt in node-list mode.
-hipError_t launch_rt_walk(const DevMesh &m, const Thresholds &th, const AngTab &ang, const LearnParams &lp,
-                          int all_pairs, float r_stop, int precision, double *rtv, unsigned long long *cnt,
-                          int *fallback, int *n_fallback, hipStream_t s);
+// fallback[*n_fallback] for launch_rt in node-list mode.  With sel_n the
+// ray-traced tets come from launch_select and the walk adds to rtv.
+hipError_t launch_rt_walk(const DevMesh &m, const Thresholds &th, const AngTab &ang, int all_pairs, float r_stop,
+                          int precision, double *rtv, unsigned long long *cnt, int *fallback, int *n_fallback,
+                          const int *sel_list, const int *sel_n, const float *sel_dmax, hipStream_t s);
 hipError_t launch_combine(const DevMesh &m, const int *node_orig, const double *part, int splits,
                           const double *band, const double *rtv, double *vel, int *nonfinite, hipStream_t s);
 

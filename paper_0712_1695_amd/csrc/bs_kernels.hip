@@ -38,6 +38,8 @@
 
 namespace bsk {
 
+static_assert(sizeof(PackedNet) == kPackedNetBytes, "packed network layout");
+
 #define RULE_G1 0
 #define RULE_G4 1
 #define RULE_G11 2
@@ -281,10 +283,14 @@ hipError_t launch_gauss_all(const DevMesh &m, int rule_pts, int precision, int s
 // lanes of the second line up with the output lanes of the first (block b =
 // lanes 4b..4b+3 = one tet and four nodes), so the reciprocal cubes pass from
 // one to the other in registers.
-// Pairs whose rule is not G1 are masked out: in a tile of 16 tets any of
-// whose centroids lies within r_band of the block's bounding sphere, every
-// pair is classified by fixed_rule (the band and ray-tracing kernels take
-// the others); outside the band every pair of the block is G1.
+// Pairs whose rule is not G1 are masked out: for a tile of 16 tets any of
+// whose centroids lies within r_band of a node tile's bounding sphere, every
+// pair of that node tile is classified with the comparisons of fixed_rule
+// (the band and ray-tracing kernels take the others); outside the band
+// every pair is G1.  The cut distances are ordered (checked on the host),
+// so a pair is G1 exactly when it is not incident and !(d^2 < g4^2); the
+// incidence test is needed only when a tet's vertex can lie beyond the G4
+// cut from its centroid.
 //
 // Workgroup = 4 waves = one block of 64 nodes (4 node tiles of 16) and one
 // split of the tet range.  Every chunk of 256 tets is prepared once into LDS
@@ -298,18 +304,21 @@ hipError_t launch_gauss_all(const DevMesh &m, int rule_pts, int precision, int s
 // chunks are added in FP64.
 constexpr int kFarChunk = 256;
 
+constexpr int kA1Stride = 80; // floats per tile in a1 (64 used; the pad spreads the banks of the stores)
+
 struct FarLds {
     union {
         struct {
-            float a1[2][16][64];           // [buf][tile][k*16 + i]: -2p'_k (k < 3), |p'|^2 (k = 3) of tet i
-            float a2[2][16][4][4][8];      // [buf][tile][q][c][2j + h]: component 4h + c of [W, W x p'] of tet 4q + j
-            float4 pc[2][kFarChunk];       // binary32 centroid (the rule's) of each tet of the chunk
-            int4 ids[2][kFarChunk];        // vertex ids (sorted numbering)
-            unsigned long long band[2][4]; // per 64 tets: bit = centroid within the band of the block
+            float a1[2][16][kA1Stride];       // [buf][tile][k*16 + i]: -2p'_k (k < 3), |p'|^2 (k = 3) of tet i
+            float a2[2][16][4][4][8];         // [buf][tile][c][q][2j + h]: component 4h + c of [W, W x p'] of tet 4q + j
+            float4 pc[2][kFarChunk];          // binary32 centroid (the rule's) of each tet of the chunk
+            int4 ids[2][kFarChunk];           // vertex ids (sorted numbering)
+            unsigned long long band[2][4][4]; // [buf][64 tets][node tile]: bit = centroid within the band
         } c;
-        double red[4][4][6][16];           // [wave][node tile][component][node]
+        double red[4][4][6][16];              // [wave][node tile][component][node]
     };
-    float4 xn[64];                         // binary32 node coordinates (the rule's), by node of the block
+    float4 xn[64];                            // binary32 node coordinates (the rule's), by node of the block
+    float4 nts[4];                            // bounding sphere of each node tile (radius < 0: no node)
 };
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -327,8 +336,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     const int t0 = blockIdx.y * per_split;
     const int t1 = min(m.T, t0 + per_split);
     const float4 bc = m.blk[b];
-    const float rb = bc.w + th.r_band;
-    const float rb2 = rb * rb;
 
     // node operands: B = [x', 1] (component q of the lane), C = |x'|^2
     float B1[4], Cin[4];
@@ -347,6 +354,34 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     if (tid < 64) {
         const int i = b * kBlockNodes + tid;
         S.xn[tid] = make_float4(m.xh[i], m.xh[m.npad + i], m.xh[2 * m.npad + i], 0.f);
+    }
+    __syncthreads();
+    if (tid < 4) {
+        float lo[3] = {3e38f, 3e38f, 3e38f}, hi[3] = {-3e38f, -3e38f, -3e38f};
+        const int nv = min(16, m.n - (b * kBlockNodes + 16 * tid));
+        for (int k = 0; k < nv; ++k) {
+            const float4 x = S.xn[16 * tid + k];
+            lo[0] = fminf(lo[0], x.x), hi[0] = fmaxf(hi[0], x.x);
+            lo[1] = fminf(lo[1], x.y), hi[1] = fmaxf(hi[1], x.y);
+            lo[2] = fminf(lo[2], x.z), hi[2] = fmaxf(hi[2], x.z);
+        }
+        const float cx = 0.5f * (lo[0] + hi[0]), cy = 0.5f * (lo[1] + hi[1]), cz = 0.5f * (lo[2] + hi[2]);
+        float r2 = 0.f;
+        for (int k = 0; k < nv; ++k) {
+            const float4 x = S.xn[16 * tid + k];
+            const float dx = x.x - cx, dy = x.y - cy, dz = x.z - cz;
+            r2 = fmaxf(r2, (dx * dx + dy * dy) + dz * dz);
+        }
+        S.nts[tid] = nv > 0 ? make_float4(cx, cy, cz, sqrtf(r2) * (1.f + 1e-5f) + 1e-6f) : make_float4(0.f, 0.f, 0.f, -1.f);
+    }
+    __syncthreads();
+    float4 nts[4];
+    float rb2[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        nts[nt] = S.nts[nt];
+        const float rb = nts[nt].w + th.r_band;
+        rb2[nt] = nts[nt].w < 0.f ? -1.f : rb * rb;
     }
 
     f32x4 D0[4], D1[4];
@@ -381,7 +416,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         }
         const float px = pr[0] - bc.x, py = pr[1] - bc.y, pz = pr[2] - bc.z;
         const float n2 = (px * px + py * py) + pz * pz;
-        const bool inb = pok && n2 < rb2;
         S.c.a1[buf][tile][i] = -2.f * px;
         S.c.a1[buf][tile][16 + i] = -2.f * py;
         S.c.a1[buf][tile][32 + i] = -2.f * pz;
@@ -391,11 +425,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int h = 0; h < 2; ++h) S.c.a2[buf][tile][qq][c][2 * j + h] = comp[4 * h + c];
+            for (int h = 0; h < 2; ++h) S.c.a2[buf][tile][c][qq][2 * j + h] = comp[4 * h + c];
         S.c.pc[buf][tid] = make_float4(pr[0], pr[1], pr[2], 0.f);
         S.c.ids[buf][tid] = pok ? pid : make_int4(-1, -1, -1, -1);
-        const unsigned long long bal = __ballot(inb);
-        if (lane == 0) S.c.band[buf][wave] = bal;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const float dx = pr[0] - nts[nt].x, dy = pr[1] - nts[nt].y, dz = pr[2] - nts[nt].z;
+            const unsigned long long bal = __ballot(pok && (dx * dx + dy * dy) + dz * dz < rb2[nt]);
+            if (lane == 0) S.c.band[buf][wave][nt] = bal;
+        }
     };
     // sum the four tet streams of every node (lanes l, l^16, l^32, l^48) in
     // FP32 and add node tile q's six sums into acc in FP64
@@ -429,11 +467,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 #pragma unroll 1
         for (int u = 0; u < 4; ++u) {
             const int tile = wave + 4 * u;
-            const unsigned long long bw = S.c.band[buf][tile >> 2];
-            const unsigned bmask = __builtin_amdgcn_readfirstlane((unsigned)(bw >> (16 * (tile & 3))) & 0xffffu);
+            unsigned bmask[4];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const unsigned long long bw = S.c.band[buf][tile >> 2][nt];
+                bmask[nt] = __builtin_amdgcn_readfirstlane((unsigned)(bw >> (16 * (tile & 3))) & 0xffffu);
+            }
             const float A1 = S.c.a1[buf][tile][lane];
-            const float4 v0 = *(const float4 *)&S.c.a2[buf][tile][q][c4][0];
-            const float4 v1 = *(const float4 *)&S.c.a2[buf][tile][q][c4][4];
+            const float4 v0 = *(const float4 *)&S.c.a2[buf][tile][c4][q][0];
+            const float4 v1 = *(const float4 *)&S.c.a2[buf][tile][c4][q][4];
             const float A2[4][2] = {{v0.x, v0.y}, {v0.z, v0.w}, {v1.x, v1.y}, {v1.z, v1.w}};
             f32x4 r2[4];
 #pragma unroll
@@ -448,19 +490,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                     const float iv = __builtin_amdgcn_rsqf(r2[nt][j]);
                     sv[nt][j] = iv * iv * iv;
                 }
-            if (bmask) {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                if (!bmask[nt]) continue;
+                const float4 xn = S.xn[16 * nt + i16];
+                const int self = b * kBlockNodes + 16 * nt + i16;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int e = tile * 16 + 4 * q + j;
                     const float4 pc = S.c.pc[buf][e];
-                    const int4 id = S.c.ids[buf][e];
-#pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) {
-                        const float4 xn = S.xn[16 * nt + i16];
-                        const int rule = fixed_rule(xn.x, xn.y, xn.z, pc.x, pc.y, pc.z, id,
-                                                    b * kBlockNodes + 16 * nt + i16, th);
-                        sv[nt][j] = rule == RULE_G1 ? sv[nt][j] : 0.f;
+                    const float dx = xn.x - pc.x, dy = xn.y - pc.y, dz = xn.z - pc.z;
+                    const float sx = dx * dx, sy = dy * dy, sz = dz * dz;
+                    bool g1 = !((sx + sy) + sz < th.g4_2);
+                    if (th.inc_far) {
+                        const int4 id = S.c.ids[buf][e];
+                        g1 = g1 && !((id.x == self) | (id.y == self) | (id.z == self) | (id.w == self));
                     }
+                    sv[nt][j] = g1 ? sv[nt][j] : 0.f;
                 }
             }
 #pragma unroll
@@ -722,6 +768,7 @@ template <bool LEARNED> struct RtShared {
         InferLds n;
     } u;
     int list[128]; // pending ray-traced tets
+    int cand[128]; // pairs waiting for the selector
 };
 template <> struct RtShared<false> {
     union {
@@ -1108,20 +1155,23 @@ __device__ __forceinline__ void rt_batch(const DevMesh &m, const AngTab &ang, Rt
     __syncthreads();
 }
 
-// Learned rule choice for the pairs of one scan step (lane = tet t): the
-// network picks a rule for pairs the fixed rule ray-traces whose tet does
-// not contain the node; below conf_min softmax confidence the pair stays
-// ray traced.  Pairs given a Gauss rule are evaluated here (the band kernel
-// removed their 1-point term, as for any ray-traced pair).  Returns the
-// pair's final rule.
+// Learned rule choice for a batch of n <= 64 candidate pairs (lane p: tet
+// cand[p], p < n): pairs the fixed rule ray-traces whose tet does not
+// contain the node.  The pair takes the cheapest Gauss rule whose predicted
+// probability of meeting the error budget (the softmax mass of the classes
+// up to it) is at least conf_min; if none, it stays ray traced.  Pairs given
+// a Gauss rule are evaluated here (no other kernel adds a term for a pair the
+// fixed rule ray-traces).  Returns the lane's rule (RULE_RT for p >= n) and
+// its tet in *t_out.
 template <int PREC>
-__device__ __forceinline__ int learned_rule(const DevMesh &m, const LearnParams &lp, InferLds &L, int lane, int t,
-                                            bool cand, int self, const float *xhv, const float *xlv, RtAcc &A,
-                                            unsigned long long *n_by_rule)
+__device__ __forceinline__ int learned_batch(const DevMesh &m, const LearnParams &lp, InferLds &L, const int *cand,
+                                             int n, int lane, const float *xhv, const float *xlv, RtAcc &A,
+                                             unsigned long long *n_by_rule, int *t_out)
 {
-    const __bf16 *W = lp.w;
-    const __bf16 *mu = W, *isg = W + 16, *W1 = W + 32, *b1 = W1 + 1024, *W2 = b1 + 64, *b2 = W2 + 4096,
-                 *W3 = b2 + 64, *b3 = W3 + 256;
+    const PackedNet *W = lp.net;
+    const bool act = lane < n;
+    const int t = cand[act ? lane : 0];
+    *t_out = t;
     const int4 id4 = m.tid[t];
     const int id[4] = {id4.x, id4.y, id4.z, id4.w};
     float a[4][3];
@@ -1133,25 +1183,30 @@ __device__ __forceinline__ int learned_rule(const DevMesh &m, const LearnParams 
     float f[16];
     pair_features(a, lp.hbar, false, f);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) L.x[lane][q] = (__bf16)(cand ? (f[q] - (float)mu[q]) * (float)isg[q] : 0.f);
+    for (int q = 0; q < 16; ++q) L.x[lane][q] = (__bf16)(act ? (f[q] - W->mu[q]) * W->isg[q] : 0.f);
     __syncthreads();
-    mlp_forward_tile(L, W1, b1, W2, b2, W3, b3, lane);
+    mlp_forward_packed(W, L.x, L.z3, lane);
+    __syncthreads();
     int rule = RULE_RT;
-    if (cand) {
+    if (act) {
         float z[4], zm = -3e38f;
-        int arg = 0;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             z[c] = L.z3[lane][c];
-            if (z[c] >= zm) { // ties go to the more expensive rule
-                zm = z[c];
-                arg = c;
-            }
+            zm = fmaxf(zm, z[c]);
         }
-        float se = 0.f;
+        float e[4], se = 0.f;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) se += __expf(z[c] - zm);
-        if (1.0f / se >= lp.conf_min) rule = arg;
+        for (int c = 0; c < 4; ++c) {
+            e[c] = __expf(z[c] - zm);
+            se += e[c];
+        }
+        const float need = lp.conf_min * se;
+        // cumulative sums in class order; the cheapest sufficient class wins
+        const float c0 = e[0], c1 = c0 + e[1], c2 = c1 + e[2];
+        rule = c2 >= need ? RULE_G11 : RULE_RT;
+        rule = c1 >= need ? RULE_G4 : rule;
+        rule = c0 >= need ? RULE_G1 : rule;
         if (rule != RULE_RT) {
             float a0 = 0.f, a1 = 0.f, a2 = 0.f;
             const int np = rule == RULE_G1 ? 1 : rule == RULE_G4 ? 4 : 11;
@@ -1164,6 +1219,29 @@ __device__ __forceinline__ int learned_rule(const DevMesh &m, const LearnParams 
     }
     __syncthreads();
     return rule;
+}
+
+// Append the tets t of the lanes with take to list[n..] (wave-uniform n).
+__device__ __forceinline__ void list_append(int *list, int &n, bool take, int t, int lane)
+{
+    const unsigned long long mk = __ballot(take);
+    if (take) list[n + __popcll(mk & ((1ull << lane) - 1ull))] = t;
+    n += __popcll(mk);
+}
+
+// Drop the first `used` entries of list[0..n) (wave-uniform).
+__device__ __forceinline__ void list_shift(int *list, int &n, int used, int lane)
+{
+    const int rest = n - used;
+    int keep[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) keep[k] = lane + 64 * k < rest ? list[used + lane + 64 * k] : 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+        if (lane + 64 * k < rest) list[lane + 64 * k] = keep[k];
+    __syncthreads();
+    n = rest;
 }
 
 template <int PREC, bool LEARNED>
@@ -1188,7 +1266,7 @@ __global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang,
     A.pairs = A.hits = 0;
     A.retests = 0;
     unsigned long long n_by_rule[3] = {0, 0, 0};
-    int nlist = 0; // uniform
+    int nlist = 0, ncand = 0; // uniform
 
     RowIter rows(m, xhv[0], xhv[1], xhv[2], th.r_rt);
     int t0 = 0, t1 = all_pairs ? m.T : 0;
@@ -1207,27 +1285,46 @@ __global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang,
                 }
             }
             if constexpr (LEARNED) {
+                // the selector's pairs wait for a full batch; the rest are listed now
                 const bool cand = is_rt && !inc;
-                if (__ballot(cand))
-                    is_rt = learned_rule<PREC>(m, lp, S.u.n, lane, t < t1 ? t : t0, cand, self, xhv, xlv, A,
-                                               n_by_rule) == RULE_RT && is_rt;
+                list_append(S.cand, ncand, cand, t, lane);
+                is_rt = is_rt && !cand;
             }
-            const unsigned long long mask = __ballot(is_rt);
-            const int pos = nlist + __popcll(mask & ((1ull << lane) - 1ull));
-            if (is_rt) S.list[pos] = t;
-            nlist += __popcll(mask);
+            list_append(S.list, nlist, is_rt, t, lane);
             __syncthreads();
             if (nlist >= 64) {
                 rt_batch<PREC>(m, ang, S.u.b, S.list, 64, lane, self, xhv, xlv, omx, A);
-                const int rest = nlist - 64;
-                const int keep = lane < rest ? S.list[64 + lane] : 0;
-                __syncthreads();
-                if (lane < rest) S.list[lane] = keep;
-                __syncthreads();
-                nlist = rest;
+                list_shift(S.list, nlist, 64, lane);
+            }
+            if constexpr (LEARNED) {
+                if (ncand >= 64) {
+                    int tt;
+                    const bool keep = learned_batch<PREC>(m, lp, S.u.n, S.cand, 64, lane, xhv, xlv, A, n_by_rule,
+                                                          &tt) == RULE_RT;
+                    list_shift(S.cand, ncand, 64, lane);
+                    list_append(S.list, nlist, keep, tt, lane);
+                    __syncthreads();
+                    if (nlist >= 64) {
+                        rt_batch<PREC>(m, ang, S.u.b, S.list, 64, lane, self, xhv, xlv, omx, A);
+                        list_shift(S.list, nlist, 64, lane);
+                    }
+                }
             }
         }
         have = all_pairs ? false : rows.next(t0, t1);
+    }
+    if constexpr (LEARNED) {
+        if (ncand > 0) {
+            int tt;
+            const bool keep = learned_batch<PREC>(m, lp, S.u.n, S.cand, ncand, lane, xhv, xlv, A, n_by_rule, &tt) ==
+                                  RULE_RT && lane < ncand;
+            list_append(S.list, nlist, keep, tt, lane);
+            __syncthreads();
+            if (nlist >= 64) {
+                rt_batch<PREC>(m, ang, S.u.b, S.list, 64, lane, self, xhv, xlv, omx, A);
+                list_shift(S.list, nlist, 64, lane);
+            }
+        }
     }
     if (nlist > 0) rt_batch<PREC>(m, ang, S.u.b, S.list, nlist, lane, self, xhv, xlv, omx, A);
 
@@ -1275,9 +1372,11 @@ __global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang,
 // by the same shared edge values, so chords join exactly.  A tet adds its
 // chord when its pair with the node is ray traced (a sorted LDS list built
 // by the scan; every tet for the pure ray-tracing policy).  The walk stops
-// at the boundary or once the ray is farther than r_stop (no ray-traced tet
-// lies beyond: r_rt plus the largest vertex-centroid distance).  Nodes whose
-// lists exceed the LDS capacity are handed to k_rt.
+// at the boundary or once the ray is farther than any listed tet reaches
+// (the largest centroid distance in the list plus the largest
+// vertex-centroid distance, at most r_stop = r_rt plus that distance; the
+// learned selector, which takes pairs off the list, shortens the walks).
+// Nodes whose lists exceed the LDS capacity are handed to k_rt.
 constexpr int kWalkCap = 1024; // ray-traced tets per node
 constexpr int kIncCap = 64;    // incident tets per node
 constexpr int kMaxSteps = 1 << 13; // tets per ray: bounds a walk that stalls on a degenerate crossing
@@ -1295,13 +1394,6 @@ struct WalkLds {
     int nlist, ninc, overflow;
 };
 
-template <bool LEARNED> struct WalkShared {
-    WalkLds w;
-    InferLds n;
-};
-template <> struct WalkShared<false> {
-    WalkLds w;
-};
 
 // value [d, A, B] for the canonical ordering (smaller node id first); FP64
 // sign when tiny.  Returns the value for (A, B) in the given order.
@@ -1334,14 +1426,152 @@ __device__ __forceinline__ bool in_sorted(const int *a, int n, int v)
     return lo < n && a[lo] == v;
 }
 
-template <int PREC, bool LEARNED>
-__global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab ang, LearnParams lp,
-                                                int all_pairs, float r_stop, double *__restrict__ rtv,
-                                                unsigned long long *__restrict__ cnt, int *__restrict__ fallback,
-                                                int *__restrict__ n_fallback)
+// Append ray-traced tets to the walk list (entries past the capacity are
+// counted, not stored) and track the farthest centroid.
+__device__ __forceinline__ void walk_list_add(const DevMesh &m, int *list, int &n, bool take, int t, int lane,
+                                              const float *xhv, float &dmax)
 {
-    __shared__ WalkShared<LEARNED> S;
-    WalkLds &W = S.w;
+    const unsigned long long mk = __ballot(take);
+    const int pos = n + __popcll(mk & ((1ull << lane) - 1ull));
+    if (take && pos < kWalkCap) list[pos] = t;
+    n += __popcll(mk);
+    if (take) {
+        const float *g = m.g1 + (size_t)t * kRecG;
+        const float dx = xhv[0] - g[0], dy = xhv[1] - g[1], dz = xhv[2] - g[2];
+        dmax = fmaxf(dmax, sqrtf((dx * dx + dy * dy) + dz * dz));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The learned policy's selection pass (walk meshes): one wave per node scans
+// the tets its fixed rule ray-traces, runs the selector on the non-incident
+// ones 64 at a time, adds the Gauss terms of the pairs it moves to rtv, and
+// leaves the pairs still ray traced (incident ones included) in
+// sel_list[node][kSelCap] with their count and farthest centroid distance
+// for k_rt_walk.  A node with more than kSelCap such pairs, or without
+// incident tets the walk can start from, is marked with count -1 and left
+// to k_rt (nothing is written for it here).
+constexpr int kSelCap = kSelListCap;
+
+__device__ __forceinline__ void sel_add(const DevMesh &m, int *list, int &n, bool take, int t, int lane,
+                                        const float *xhv, float &dmax)
+{
+    const unsigned long long mk = __ballot(take);
+    const int pos = n + __popcll(mk & ((1ull << lane) - 1ull));
+    if (take && pos < kSelCap) list[pos] = t;
+    n += __popcll(mk);
+    if (take) {
+        const float *g = m.g1 + (size_t)t * kRecG;
+        const float dx = xhv[0] - g[0], dy = xhv[1] - g[1], dz = xhv[2] - g[2];
+        dmax = fmaxf(dmax, sqrtf((dx * dx + dy * dy) + dz * dz));
+    }
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_select(DevMesh m, Thresholds th, LearnParams lp, double *__restrict__ rtv,
+                                               unsigned long long *__restrict__ cnt, int *__restrict__ sel_list,
+                                               int *__restrict__ sel_n, float *__restrict__ sel_dmax)
+{
+    __shared__ InferLds L;
+    __shared__ int cand[128];
+    const int lane = threadIdx.x;
+    const int self = blockIdx.x;
+    const int ninc = m.inc_start[self + 1] - m.inc_start[self];
+    if (ninc == 0 || ninc > kIncCap) {
+        if (lane == 0) sel_n[self] = -1;
+        return;
+    }
+    float xhv[3], xlv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        xhv[c] = m.xh[c * m.npad + self];
+        xlv[c] = m.xl[c * m.npad + self];
+    }
+    RtAcc A;
+    A.ax = A.ay = A.az = A.sx = A.sy = A.sz = A.cx = A.cy = A.cz = 0.f;
+    A.dx = A.dy = A.dz = 0.0;
+    A.pairs = A.hits = 0;
+    A.retests = 0;
+    unsigned long long n_by_rule[3] = {0, 0, 0};
+    int *list = sel_list + (size_t)self * kSelCap;
+    int nlist = 0, ncand = 0;
+    float dmax = 0.f;
+    RowIter rows(m, xhv[0], xhv[1], xhv[2], th.r_rt);
+    int t0, t1;
+    while (rows.next(t0, t1)) {
+        for (int b0 = t0; b0 < t1; b0 += 64) {
+            const int t = b0 + lane;
+            bool is_rt = false, inc = false;
+            if (t < t1) {
+                const int4 id = m.tid[t];
+                inc = (id.x == self) | (id.y == self) | (id.z == self) | (id.w == self);
+                const float *g = m.g1 + (size_t)t * kRecG;
+                is_rt = fixed_rule(xhv[0], xhv[1], xhv[2], g[0], g[1], g[2], id, self, th) == RULE_RT;
+            }
+            const bool c = is_rt && !inc;
+            list_append(cand, ncand, c, t, lane);
+            sel_add(m, list, nlist, is_rt && !c, t, lane, xhv, dmax);
+            __syncthreads();
+            if (ncand >= 64) {
+                int tt;
+                const bool keep = learned_batch<PREC>(m, lp, L, cand, 64, lane, xhv, xlv, A, n_by_rule, &tt) == RULE_RT;
+                list_shift(cand, ncand, 64, lane);
+                sel_add(m, list, nlist, keep, tt, lane, xhv, dmax);
+            }
+        }
+    }
+    if (ncand > 0) {
+        int tt;
+        const bool keep =
+            learned_batch<PREC>(m, lp, L, cand, ncand, lane, xhv, xlv, A, n_by_rule, &tt) == RULE_RT && lane < ncand;
+        sel_add(m, list, nlist, keep, tt, lane, xhv, dmax);
+    }
+    for (int o = 32; o > 0; o >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, o, 64));
+    if (nlist > kSelCap) {
+        if (lane == 0) sel_n[self] = -1;
+        return;
+    }
+    double vx, vy, vz;
+    if (PREC == 0) {
+        vx = A.ax;
+        vy = A.ay;
+        vz = A.az;
+    } else if (PREC == 1) {
+        vx = (double)A.sx + (double)A.cx;
+        vy = (double)A.sy + (double)A.cy;
+        vz = (double)A.sz + (double)A.cz;
+    } else {
+        vx = A.dx;
+        vy = A.dy;
+        vz = A.dz;
+    }
+    vx = wave_sum_f64(vx);
+    vy = wave_sum_f64(vy);
+    vz = wave_sum_f64(vz);
+    unsigned long long lr[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) lr[k] = wave_sum_u64(n_by_rule[k]);
+    if (lane == 0) {
+        rtv[self] = vx;
+        rtv[m.npad + self] = vy;
+        rtv[2 * m.npad + self] = vz;
+        sel_n[self] = nlist;
+        sel_dmax[self] = dmax;
+        if (cnt)
+            for (int k = 0; k < 3; ++k) atomicAdd(&cnt[5 + k], lr[k]);
+    }
+}
+
+// LISTED: the ray-traced tets of every node come from k_select (which also
+// wrote the node's Gauss terms to rtv: the walk adds to them).
+template <int PREC, bool LISTED>
+__global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab ang, int all_pairs, float r_stop,
+                                                double *__restrict__ rtv, unsigned long long *__restrict__ cnt,
+                                                int *__restrict__ fallback, int *__restrict__ n_fallback,
+                                                const int *__restrict__ sel_list, const int *__restrict__ sel_n,
+                                                const float *__restrict__ sel_dmax)
+{
+    __shared__ WalkLds W;
     const int lane = threadIdx.x;
     const int self = blockIdx.x;
     float xhv[3], xlv[3], omx[3];
@@ -1356,40 +1586,44 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
     A.dx = A.dy = A.dz = 0.0;
     A.pairs = A.hits = 0;
     A.retests = 0;
-    unsigned long long n_by_rule[3] = {0, 0, 0};
     if (lane == 0) {
         W.nlist = 0;
         W.overflow = 0;
     }
     __syncthreads();
 
-    // ---- A. ray-traced tets of the node (not needed when every pair is)
+    // ---- A. ray-traced tets of the node (not needed when every pair is);
+    // the walk stops past the farthest of them
     int nlist = 0;
+    float stop = r_stop;
     if (!all_pairs) {
-        RowIter rows(m, xhv[0], xhv[1], xhv[2], th.r_rt);
-        int t0, t1;
-        while (rows.next(t0, t1)) {
-            for (int b0 = t0; b0 < t1; b0 += 64) {
-                const int t = b0 + lane;
-                bool is_rt = false, inc = false;
-                if (t < t1) {
-                    const int4 id = m.tid[t];
-                    inc = (id.x == self) | (id.y == self) | (id.z == self) | (id.w == self);
-                    const float *g = m.g1 + (size_t)t * kRecG;
-                    is_rt = fixed_rule(xhv[0], xhv[1], xhv[2], g[0], g[1], g[2], id, self, th) == RULE_RT;
-                }
-                if constexpr (LEARNED) {
-                    const bool cand = is_rt && !inc;
-                    if (__ballot(cand))
-                        is_rt = learned_rule<PREC>(m, lp, S.n, lane, t < t1 ? t : t0, cand, self, xhv, xlv, A,
-                                                   n_by_rule) == RULE_RT && is_rt;
-                }
-                const unsigned long long mask = __ballot(is_rt);
-                const int pos = nlist + __popcll(mask & ((1ull << lane) - 1ull));
-                if (is_rt && pos < kWalkCap) W.list[pos] = t;
-                nlist += __popcll(mask);
+        float dmax = 0.f;
+        if constexpr (LISTED) {
+            nlist = sel_n[self];
+            if (nlist < 0) {
+                if (lane == 0) fallback[atomicAdd(n_fallback, 1)] = self;
+                return;
             }
+            for (int k = lane; k < nlist; k += 64) W.list[k] = sel_list[(size_t)self * kSelCap + k];
+            dmax = sel_dmax[self];
+        } else {
+            RowIter rows(m, xhv[0], xhv[1], xhv[2], th.r_rt);
+            int t0, t1;
+            while (rows.next(t0, t1)) {
+                for (int b0 = t0; b0 < t1; b0 += 64) {
+                    const int t = b0 + lane;
+                    bool is_rt = false;
+                    if (t < t1) {
+                        const int4 id = m.tid[t];
+                        const float *g = m.g1 + (size_t)t * kRecG;
+                        is_rt = fixed_rule(xhv[0], xhv[1], xhv[2], g[0], g[1], g[2], id, self, th) == RULE_RT;
+                    }
+                    walk_list_add(m, W.list, nlist, is_rt, t, lane, xhv, dmax);
+                }
+            }
+            for (int o = 32; o > 0; o >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, o, 64));
         }
+        stop = fminf(r_stop, (dmax + th.vc) * (1.f + 1e-4f) + 1e-6f);
         if (nlist > kWalkCap) {
             if (lane == 0) fallback[atomicAdd(n_fallback, 1)] = self;
             return;
@@ -1525,7 +1759,7 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
         int T = W.inb[start];
         int ent[3] = {W.iid[start][0], W.iid[start][1], W.iid[start][2]};
         int steps = 0;
-        while (T >= 0 && rho < r_stop && steps < kMaxSteps) {
+        while (T >= 0 && rho < stop && steps < kMaxSteps) {
             ++steps;
             const int4 id4 = m.tid[T];
             const int id[4] = {id4.x, id4.y, id4.z, id4.w};
@@ -1615,10 +1849,12 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
     vz = wave_sum_f64(vz);
     const unsigned long long hits = wave_sum_u64(A.hits);
     const unsigned long long rts = wave_sum_u64((unsigned long long)A.retests);
-    unsigned long long lr[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) lr[k] = LEARNED ? wave_sum_u64(n_by_rule[k]) : 0;
     if (lane == 0) {
+        if (LISTED) {
+            vx += rtv[self];
+            vy += rtv[m.npad + self];
+            vz += rtv[2 * m.npad + self];
+        }
         rtv[self] = vx;
         rtv[m.npad + self] = vy;
         rtv[2 * m.npad + self] = vz;
@@ -1626,8 +1862,6 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
             atomicAdd(&cnt[2], A.pairs);
             atomicAdd(&cnt[3], hits);
             atomicAdd(&cnt[4], rts);
-            if (LEARNED)
-                for (int k = 0; k < 3; ++k) atomicAdd(&cnt[5 + k], lr[k]);
         }
     }
 }
@@ -1637,7 +1871,7 @@ hipError_t launch_rt(const DevMesh &m, const Thresholds &th, const AngTab &ang, 
                      const int *node_count, hipStream_t s)
 {
     if (m.n == 0) return hipSuccess;
-    const bool L = lp.w != nullptr;
+    const bool L = lp.net != nullptr;
 #define BS_RT(P, LL)                                                                                               \
     hipLaunchKernelGGL((k_rt<P, LL>), dim3(m.n), dim3(64), 0, s, m, th, ang, lp, all_pairs, rtv, cnt, node_list,  \
                        node_count)
@@ -1652,15 +1886,28 @@ hipError_t launch_rt(const DevMesh &m, const Thresholds &th, const AngTab &ang, 
     return hipGetLastError();
 }
 
-hipError_t launch_rt_walk(const DevMesh &m, const Thresholds &th, const AngTab &ang, const LearnParams &lp,
-                          int all_pairs, float r_stop, int precision, double *rtv, unsigned long long *cnt,
-                          int *fallback, int *n_fallback, hipStream_t s)
+hipError_t launch_select(const DevMesh &m, const Thresholds &th, const LearnParams &lp, int precision, double *rtv,
+                         unsigned long long *cnt, int *sel_list, int *sel_n, float *sel_dmax, hipStream_t s)
 {
     if (m.n == 0) return hipSuccess;
-    const bool L = lp.w != nullptr;
+    if (precision == 0)
+        hipLaunchKernelGGL(k_select<0>, dim3(m.n), dim3(64), 0, s, m, th, lp, rtv, cnt, sel_list, sel_n, sel_dmax);
+    else if (precision == 1)
+        hipLaunchKernelGGL(k_select<1>, dim3(m.n), dim3(64), 0, s, m, th, lp, rtv, cnt, sel_list, sel_n, sel_dmax);
+    else
+        hipLaunchKernelGGL(k_select<2>, dim3(m.n), dim3(64), 0, s, m, th, lp, rtv, cnt, sel_list, sel_n, sel_dmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_rt_walk(const DevMesh &m, const Thresholds &th, const AngTab &ang, int all_pairs, float r_stop,
+                          int precision, double *rtv, unsigned long long *cnt, int *fallback, int *n_fallback,
+                          const int *sel_list, const int *sel_n, const float *sel_dmax, hipStream_t s)
+{
+    if (m.n == 0) return hipSuccess;
+    const bool L = sel_n != nullptr;
 #define BS_RW(P, LL)                                                                                               \
-    hipLaunchKernelGGL((k_rt_walk<P, LL>), dim3(m.n), dim3(64), 0, s, m, th, ang, lp, all_pairs, r_stop, rtv, cnt, \
-                       fallback, n_fallback)
+    hipLaunchKernelGGL((k_rt_walk<P, LL>), dim3(m.n), dim3(64), 0, s, m, th, ang, all_pairs, r_stop, rtv, cnt,     \
+                       fallback, n_fallback, sel_list, sel_n, sel_dmax)
     if (precision == 0) {
         if (L) BS_RW(0, true); else BS_RW(0, false);
     } else if (precision == 1) {

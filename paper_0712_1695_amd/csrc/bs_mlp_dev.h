@@ -195,11 +195,88 @@ __device__ void mlp_forward_tile(LDS &L, const __bf16 *W1, const __bf16 *b1, con
 }
 
 
-// Forward-only scratch (the fused inference of the ray-tracing kernel).
+// ------------------------------------------------- fused inference network
+//
+// The ray-tracing kernels run the network on the pairs of one node, 64 at a
+// time, with every layer transposed (rows = units, columns = pairs):
+//   Z1^T = W1^T X^T,  Z2^T = W2^T relu(Z1)^T,  Z3^T = W3^T relu(Z2)^T.
+// A 32 x 32 output tile leaves lane l holding units 8j + 4(l/32) + i
+// (j, i < 4) of pair l % 32; that is the B operand of the next layer once
+// the K index k = 8h + s of k-tile kt (lane half h = l/32) is mapped to the
+// unit
+//   U(kt, h, s) = 32 (kt/2) + 8 (2 (kt%2) + s/4) + 4 h + s%4,
+// so activations never leave registers.  The weights are repacked on the
+// host into these A-operand vectors (one 16-byte load per lane and MFMA).
+struct PackedNet {
+    bf16x8 w1[2][64];    // layer 1, [row tile][lane]: W1[8(l/32) + s][32 rt + l%32]
+    bf16x8 w2[2][4][64]; // layer 2, [row tile][k tile][lane]: W2[U(kt, l/32, s)][32 rt + l%32]
+    bf16x8 w3[4][64];    // layer 3, [k tile][lane]: W3[U(kt, l/32, s)][l%32] for l%32 < 4, else 0
+    float b1[2][2][16];  // bias of output register r: [row tile][l/32][r] = b1[32 rt + 8(r/4) + 4(l/32) + r%4]
+    float b2[2][2][16];
+    float b3[4];
+    float mu[16], isg[16];
+};
+
+__device__ __forceinline__ int packed_unit(int kt, int h, int s) { return 32 * (kt >> 1) + 8 * (2 * (kt & 1) + (s >> 2)) + 4 * h + (s & 3); }
+
+// Logits of 64 pairs: xb[p] = standardised features of pair p (BF16); the
+// logits of pair p land in zs[p].  Every lane of the wave takes part.
+__device__ __forceinline__ void mlp_forward_packed(const PackedNet *__restrict__ W, const __bf16 (*xb)[16],
+                                                   float (*zs)[4], int lane)
+{
+    // both column tiles (pairs 0..31, 32..63) per weight vector, so that each
+    // weight vector is used as soon as it is loaded
+    const int h = lane >> 5, col = lane & 31;
+    bf16x8 xv[2];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) xv[ct] = *(const bf16x8 *)&xb[32 * ct + col][8 * h];
+    bf16x8 a1[2][4];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        const bf16x8 w = W->w1[rt][lane];
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            f32x16 c = {};
+            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, xv[ct], c, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                a1[ct][2 * rt + (r >> 3)][r & 7] = (__bf16)fmaxf(c[r] + W->b1[rt][h][r], 0.f);
+        }
+    }
+    bf16x8 a2[2][4];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        f32x16 c[2] = {{}, {}};
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) {
+            const bf16x8 w = W->w2[rt][kt][lane];
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) c[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, a1[ct][kt], c[ct], 0, 0, 0);
+        }
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                a2[ct][2 * rt + (r >> 3)][r & 7] = (__bf16)fmaxf(c[ct][r] + W->b2[rt][h][r], 0.f);
+    }
+    f32x16 c[2] = {{}, {}};
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) {
+        const bf16x8 w = W->w3[kt][lane];
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) c[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, a2[ct][kt], c[ct], 0, 0, 0);
+    }
+    if (h == 0) {
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) zs[32 * ct + col][r] = c[ct][r] + W->b3[r];
+    }
+}
+
+// LDS of the fused inference: staged features and logits of one batch.
 struct InferLds {
     __bf16 x[64][16];
-    __bf16 a1[64][64];
-    __bf16 a2[64][64];
     float z3[64][4];
 };
 

@@ -62,10 +62,37 @@ def test_bf16_rounding_and_pack():
     assert M.BLOB_LEN == 5540
 
 
-def test_decision_rule_ties_and_fallback():
+def test_decision_rule_cumulative_and_fallback():
+    """All logits equal: p = 1/4 each, so P(label <= r) = (r + 1)/4; the
+    cheapest rule reaching conf_min is chosen, else the fallback."""
     p = {k: np.zeros(s) for k, s in M.SIZES}
     p["inv_sigma"][:] = 1.0
     X = np.zeros((3, 16))
-    # all logits equal: tie -> most expensive rule (3); confidence 0.25
-    assert list(M.decide(p, X, fallback=[1, 1, 1], conf_min=0.0)) == [3, 3, 3]
-    assert list(M.decide(p, X, fallback=[1, 2, 0], conf_min=0.5)) == [1, 2, 0]
+    assert list(M.decide(p, X, fallback=[3, 3, 3], conf_min=0.2)) == [0, 0, 0]
+    assert list(M.decide(p, X, fallback=[3, 3, 3], conf_min=0.5)) == [1, 1, 1]
+    assert list(M.decide(p, X, fallback=[3, 3, 3], conf_min=0.7)) == [2, 2, 2]
+    assert list(M.decide(p, X, fallback=[3, 1, 0], conf_min=0.9)) == [3, 1, 0]
+    # one logit up: G4 gets e/(e+3) of the mass
+    p["b3"][:] = [0.0, 1.0, 0.0, 0.0]
+    g4 = np.e / (np.e + 3)
+    assert list(M.decide(p, X[:1], fallback=3, conf_min=g4 + 1 / (np.e + 3) - 1e-9)) == [1]
+    assert list(M.decide(p, X[:1], fallback=3, conf_min=g4 + 1 / (np.e + 3) + 1e-9)) == [2]
+    # the BF16 variant agrees away from the threshold and flags rows near it
+    r, alt = M.decide_bf16(p, X[:1], 3, conf_min=g4 + 1 / (np.e + 3) + 1e-3, margin=1e-2)
+    assert r[0] == 2 and 1 in alt[0]
+
+
+def test_pair_features_batch_matches_definition():
+    import oracle
+    import workloads as W
+    from oracle import features as F
+
+    m = W.make_config("C1")
+    rng = np.random.default_rng(0)
+    tets = rng.integers(0, m.n_tets, 200)
+    nodes = np.where(rng.random(200) < 0.3, m.tets[tets, 0], rng.integers(0, m.n_nodes, 200))
+    hb = oracle.mean_edge(m.xyz, m.tets)
+    inc = np.array([n in m.tets[t] for n, t in zip(nodes, tets)])
+    B = F.pair_features_batch(m.xyz[nodes], m.xyz[m.tets[tets]], hb, inc)
+    S = np.stack([F.pair_features(m.xyz[n], m.xyz[m.tets[t]], hb, i) for n, t, i in zip(nodes, tets, inc)])
+    assert np.allclose(B, S, rtol=1e-12, atol=1e-12)
