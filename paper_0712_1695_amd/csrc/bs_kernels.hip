@@ -1378,20 +1378,19 @@ __global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang,
 // learned selector, which takes pairs off the list, shortens the walks).
 // Nodes whose lists exceed the LDS capacity are handed to k_rt.
 constexpr int kWalkCap = 1024; // ray-traced tets per node
-constexpr int kIncCap = 64;    // incident tets per node
+constexpr int kIncCap = 48;    // incident tets per node (more: left to k_rt)
 constexpr int kMaxSteps = 1 << 13; // tets per ray: bounds a walk that stalls on a degenerate crossing
 
 struct WalkLds {
     int list[kWalkCap];
     // incident tets: the three vertices of the face opposite the node
-    float ia[kIncCap][9];  // relative positions (p, q, r)
     float iw[kIncCap][9];  // vorticity
     float in[kIncCap][9];  // canonical normals of the edges pq, qr, pr
     int iid[kIncCap][3];   // node ids of p, q, r
     int imeta[kIncCap];    // bits 0-2: flip of pq, qr, pr
     int inb[kIncCap];      // tet across the face (-1: boundary)
     float ivol[kIncCap];   // [a_p, a_q, a_r]
-    int nlist, ninc, overflow;
+    float4 icone[kIncCap]; // cone around the face seen from the node: unit axis, cos(half angle) (-2: none)
 };
 
 
@@ -1586,11 +1585,6 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
     A.dx = A.dy = A.dz = 0.0;
     A.pairs = A.hits = 0;
     A.retests = 0;
-    if (lane == 0) {
-        W.nlist = 0;
-        W.overflow = 0;
-    }
-    __syncthreads();
 
     // ---- A. ray-traced tets of the node (not needed when every pair is);
     // the walk stops past the farthest of them
@@ -1680,7 +1674,6 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 a[q][c] = (m.xh[c * m.npad + nid] - xhv[c]) + (m.xl[c * m.npad + nid] - xlv[c]);
-                W.ia[lane][3 * q + c] = a[q][c];
                 W.iw[lane][3 * q + c] = m.om[c * m.npad + nid];
             }
         }
@@ -1704,18 +1697,46 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
         W.ivol[lane] = fmaf(a[0][0], N[0], fmaf(a[0][1], N[1], a[0][2] * N[2]));
         W.imeta[lane] = flips;
         W.inb[lane] = nb[f];
+        // the directions that enter this tet form the spherical triangle of
+        // the face; a cap narrower than a hemisphere that holds its three
+        // corners holds all of it
+        float u[3][3], ax[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const float il = 1.f / sqrtf((a[q][0] * a[q][0] + a[q][1] * a[q][1]) + a[q][2] * a[q][2]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                u[q][c] = a[q][c] * il;
+                ax[c] += u[q][c];
+            }
+        }
+        const float iax = 1.f / sqrtf((ax[0] * ax[0] + ax[1] * ax[1]) + ax[2] * ax[2]);
+        float cmin = 1.f;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) cmin = fminf(cmin, (ax[0] * u[q][0] + ax[1] * u[q][1] + ax[2] * u[q][2]) * iax);
+        W.icone[lane] = make_float4(ax[0] * iax, ax[1] * iax, ax[2] * iax, cmin > 0.02f ? cmin - 1e-5f : -2.f);
     }
     __syncthreads();
 
-    // ---- C. rays
-    const int nrays = ang.N * ang.M2;
-    for (int l = lane; l < nrays; l += 64) {
+    // ---- C. rays, 8 x 8 blocks of (row, column) per step so that the rays
+    // of the wave point into a small solid angle
+    const int bcols = (ang.M2 + 7) >> 3, nblk = ((ang.N + 7) >> 3) * bcols;
+    for (int bi = 0; bi < nblk; ++bi) {
+        const int row = 8 * (bi / bcols) + (lane >> 3), col = 8 * (bi % bcols) + (lane & 7);
+        const bool valid = row < ang.N && col < ang.M2;
+        const int l = valid ? row * ang.M2 + col : 0;
         const float4 d = ang.dir[l];
         const double *d64 = ang.dir64 + 3 * (size_t)l;
-        // start: the incident tet whose opposite face the ray crosses
+        // start: the incident tet whose opposite face the ray crosses (tets
+        // whose cone no ray of the wave enters are skipped)
         int start = -1;
         float rho = 0.f, w_in[3] = {0.f, 0.f, 0.f};
-        for (int i = 0; i < ninc && start < 0; ++i) {
+        for (int i = 0; i < ninc; ++i) {
+            if (!__ballot(valid && start < 0)) break;
+            const float4 cone = W.icone[i];
+            const bool pass = valid && start < 0 && fmaf(d.x, cone.x, fmaf(d.y, cone.y, d.z * cone.z)) >= cone.w;
+            if (!__ballot(pass)) continue;
+            if (!pass) continue;
             const int meta = W.imeta[i];
             float ce[3];
             int se[3];
@@ -1748,7 +1769,7 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
             rho = r;
             start = i;
         }
-        if (start < 0) continue;
+        if (!valid || start < 0) continue;
         {
             const float h = 0.5f * d.w * rho;
             const float sx = omx[0] + w_in[0], sy = omx[1] + w_in[1], sz = omx[2] + w_in[2];
