@@ -111,6 +111,7 @@ def main():
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", type=int, default=1)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-policy leg")
     ap.add_argument("--valu-far", action="store_true",
                     help="far field on the vector ALUs instead of the matrix cores (comparison)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -159,6 +160,36 @@ def main():
     pairs = mesh.n_nodes * mesh.n_tets
     ms = wall / args.steps * 1e3
     value = pairs / (wall / args.steps)
+
+    learned = None
+    if not args.no_learned:
+        # the selector is trained on the GPU by the library's own kernels
+        # (outside the timed region), on pairs of two smaller meshes, then
+        # the same evaluation is timed with the learned policy
+        from paper_0712_1695_amd import selector
+
+        train_meshes = [W.make_config("C1"), W.make_config("C2", scale=(32, 32, 11))]
+        blob, info = selector.train([(t.xyz, t.omega, t.tets) for t in train_meshes])
+        conf_min = 0.9
+        bs.bs_set_policy(h, kind=bs.BS_POLICY_LEARNED, n_phi=16, n_theta=16, precision=args.precision,
+                         mlp_bf16=blob, conf_min=conf_min)
+        for _ in range(args.warmup):
+            bs.bs_eval_velocity(h, out=out, valu_far=args.valu_far)
+        torch.cuda.synchronize()
+        kl = np.zeros(4)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, st_l = bs.bs_eval_velocity(h, out=out, stats=True, valu_far=args.valu_far)
+            kl += np.array(st_l["t_kernel_s"])
+        torch.cuda.synchronize()
+        wall_l = time.perf_counter() - t0
+        kl /= max(args.steps, 1)
+        value_l = pairs / (wall_l / args.steps)
+        learned = {"value": value_l, "unit": "pairs/s", "ms_per_step": wall_l / args.steps * 1e3,
+                   "vs_fixed": value_l / value, "conf_min": conf_min, "pairs_by_rule": st_l["pairs_by_rule"],
+                   "rt_hit_lines": st_l["rt_hit_lines"],
+                   "kernel_ms": {"far": kl[0] * 1e3, "band": kl[1] * 1e3, "rt": kl[2] * 1e3, "sum": kl[3] * 1e3},
+                   "selector": {**info, "trained_on": [t.name for t in train_meshes]}}
     flops = algorithmic_flops(stats, nm)
     g1_pairs = stats["pairs_by_rule"][0]
     far_flops = FLOPS_PER_POINT * g1_pairs  # the method's flops of the G1 pairs
@@ -202,6 +233,8 @@ def main():
         },
         "roofline": roof,
     }
+    if learned is not None:
+        line["learned"] = learned
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(mesh)
     bs.bs_mesh_free(h)

@@ -130,6 +130,10 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise ImportError(f"{p} not found: build it with `python -m paper_0712_1695_amd.build`")
+    # torch first: its HIP runtime is then the one the library binds to, so
+    # torch's streams and device memory are valid arguments of every call
+    import torch  # noqa: F401
+
     L = ctypes.CDLL(p)
     vp = ctypes.c_void_p
     L.bs_mesh_upload.argtypes = [ctypes.POINTER(MeshDesc), ctypes.POINTER(vp)]

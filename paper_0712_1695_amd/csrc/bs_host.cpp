@@ -236,7 +236,8 @@ int check_device(int *dev)
 {
     int count = 0;
     hipError_t e = hipGetDeviceCount(&count);
-    if (e != hipSuccess || count == 0) return fail(BS_E_DEVICE, "no HIP device available");
+    if (e != hipSuccess || count == 0)
+        return fail(BS_E_DEVICE, "no HIP device available (hipGetDeviceCount: %s, count %d)", hipGetErrorString(e), count);
     int d = 0;
     e = hipGetDevice(&d);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");

@@ -39,6 +39,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--dt", type=float, default=0.005)
     ap.add_argument("--cells", type=int, default=80)
+    ap.add_argument("--learned", action="store_true", help="learned policy (selector trained on the GPU first)")
     args = ap.parse_args()
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     if root not in sys.path:
@@ -46,10 +47,21 @@ def main():
     import workloads as W
 
     m = W.make_config("C5", scale=None if args.cells == 80 else (args.cells,) * 3)
-    pos, secs, _ = run(m.xyz, m.omega, m.tets, args.steps, args.dt)
+    policy = dict(kind=BS_POLICY_FIXED, precision=BS_PREC_FP32_COMP)
+    sel = None
+    if args.learned:
+        from . import BS_POLICY_LEARNED, selector
+
+        tm = [W.make_config("C1"), W.make_config("C2", scale=(32, 32, 11))]
+        blob, sel = selector.train([(t.xyz, t.omega, t.tets) for t in tm])
+        policy = dict(kind=BS_POLICY_LEARNED, precision=BS_PREC_FP32_COMP, mlp_bf16=blob, conf_min=0.9)
+    pos, secs, _ = run(m.xyz, m.omega, m.tets, args.steps, args.dt, policy)
     disp = np.linalg.norm(pos - m.xyz, axis=1)
     print(json.dumps({"workload": m.name, "nodes": m.n_nodes, "tets": m.n_tets, "steps": args.steps, "dt": args.dt,
-                      "step_seconds": [float(s) for s in secs], "max_displacement": float(disp.max())}))
+                      "policy": "learned" if args.learned else "fixed",
+                      "pairs_per_eval": m.n_nodes * m.n_tets, "evals": 2 * args.steps,
+                      "step_seconds": [float(s) for s in secs], "max_displacement": float(disp.max()),
+                      "selector": sel}), flush=True)
 
 
 if __name__ == "__main__":
