@@ -1042,8 +1042,8 @@ int eval_device(bs_mesh *m, hipStream_t s)
     // the fixed-rule far field runs on the matrix cores except in FP64 mode
     const bool far_mfma = fixed_like && P.precision != BS_PREC_FP64 && m->far_mode == 0;
     if (gauss_all && m->T > 0) {
-        if (far_mfma)
-            splits = std::max(1, std::min<int>((4096 + m->nblk - 1) / m->nblk, (int)((m->T + 2047) / 2048)));
+        if (far_mfma) // eight splits: one per XCD (see k_far_mfma)
+            splits = std::max(1, std::min<int>(8, (int)((m->T + 2047) / 2048)));
         else
             splits = std::max(1, std::min<int>((int)((4096 + 4 * node_blocks - 1) / (4 * node_blocks)),
                                                (int)((m->T + 255) / 256)));

@@ -324,16 +324,20 @@ struct FarLds {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int PREC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_far_mfma(DevMesh m, Thresholds th, int per_split,
-                                                  double *__restrict__ part)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_far_mfma(DevMesh m, Thresholds th, int splits,
+                                                  int per_split, double *__restrict__ part)
 {
     __shared__ FarLds S;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int q = lane >> 4, i16 = lane & 15, c4 = lane & 3;
-    const int b = blockIdx.x;
-    const int t0 = blockIdx.y * per_split;
+    // workgroup id = block * splits + split: consecutive ids go to the eight
+    // XCDs in turn, so with eight splits each XCD streams one eighth of the
+    // tets through its own L2
+    const int b = blockIdx.x / splits;
+    const int split = blockIdx.x - b * splits;
+    const int t0 = split * per_split;
     const int t1 = min(m.T, t0 + per_split);
     const float4 bc = m.blk[b];
 
@@ -402,7 +406,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         const float *g = m.g1 + (size_t)t * kRecG;
         pg = *(const float4 *)g;
         pw = *(const float2 *)(g + 4);
-        pid = m.tid[t];
+        pid = th.inc_far ? m.tid[t] : make_int4(-1, -1, -1, -1);
     };
     auto store = [&](int buf) {
         const int tile = tid >> 4, i = tid & 15, qq = i >> 2, j = i & 3;
@@ -540,7 +544,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                 xp[c] = (double)((m.xh[c * m.npad + i] - cc) + m.xl[c * m.npad + i]);
             }
         }
-        double *o = part + (size_t)blockIdx.y * 3 * m.npad;
+        double *o = part + (size_t)split * 3 * m.npad;
         o[i] = (sw[1] * xp[2] - sw[2] * xp[1]) - sw[3];
         o[m.npad + i] = (sw[2] * xp[0] - sw[0] * xp[2]) - sw[4];
         o[2 * m.npad + i] = (sw[0] * xp[1] - sw[1] * xp[0]) - sw[5];
@@ -552,11 +556,11 @@ hipError_t launch_far_mfma(const DevMesh &m, const Thresholds &th, int precision
 {
     if (splits < 1 || precision < 0 || precision > 1) return hipErrorInvalidValue;
     const int per = ((m.T + splits - 1) / splits + kFarChunk - 1) / kFarChunk * kFarChunk;
-    const dim3 grid(m.nblk, splits);
+    const dim3 grid(m.nblk * splits);
     if (precision == 0)
-        hipLaunchKernelGGL(k_far_mfma<0>, grid, dim3(256), 0, s, m, th, per, part);
+        hipLaunchKernelGGL(k_far_mfma<0>, grid, dim3(256), 0, s, m, th, splits, per, part);
     else
-        hipLaunchKernelGGL(k_far_mfma<1>, grid, dim3(256), 0, s, m, th, per, part);
+        hipLaunchKernelGGL(k_far_mfma<1>, grid, dim3(256), 0, s, m, th, splits, per, part);
     return hipGetLastError();
 }
 
@@ -627,10 +631,16 @@ __global__ void __launch_bounds__(64 * kBandWaves) k_band(DevMesh m, Thresholds 
     __shared__ double red[kBandWaves][3][64];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); // uniform within the wave
-    const int i = blockIdx.x * kBlockNodes + lane;
+    // consecutive workgroup ids go to the eight XCDs in turn: give each XCD a
+    // contiguous range of (spatially ordered) blocks, whose neighbourhoods
+    // overlap in its L2
+    const int per_xcd = (m.nblk + 7) >> 3;
+    const int blk = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (blk >= m.nblk) return;
+    const int i = blk * kBlockNodes + lane;
     const bool valid = i < m.n;
     const float x = m.xh[i], y = m.xh[m.npad + i], z = m.xh[2 * m.npad + i];
-    const float4 bc = m.blk[blockIdx.x];
+    const float4 bc = m.blk[blk];
     float sx = 0.f, sy = 0.f, sz = 0.f, ccx = 0.f, ccy = 0.f, ccz = 0.f;
     double dx = 0.0, dy = 0.0, dz = 0.0;
     unsigned long long n4 = 0, n11 = 0;
@@ -708,20 +718,21 @@ hipError_t launch_band(const DevMesh &m, const Thresholds &th, int precision, in
                        unsigned long long *cnt, hipStream_t s)
 {
     const dim3 blk(64 * kBandWaves);
+    const dim3 grid(8 * ((m.nblk + 7) / 8));
     if (sub_g1) {
         if (precision == 0)
-            hipLaunchKernelGGL((k_band<0, true>), dim3(m.nblk), blk, 0, s, m, th, band, cnt);
+            hipLaunchKernelGGL((k_band<0, true>), grid, blk, 0, s, m, th, band, cnt);
         else if (precision == 1)
-            hipLaunchKernelGGL((k_band<1, true>), dim3(m.nblk), blk, 0, s, m, th, band, cnt);
+            hipLaunchKernelGGL((k_band<1, true>), grid, blk, 0, s, m, th, band, cnt);
         else
-            hipLaunchKernelGGL((k_band<2, true>), dim3(m.nblk), blk, 0, s, m, th, band, cnt);
+            hipLaunchKernelGGL((k_band<2, true>), grid, blk, 0, s, m, th, band, cnt);
     } else {
         if (precision == 0)
-            hipLaunchKernelGGL((k_band<0, false>), dim3(m.nblk), blk, 0, s, m, th, band, cnt);
+            hipLaunchKernelGGL((k_band<0, false>), grid, blk, 0, s, m, th, band, cnt);
         else if (precision == 1)
-            hipLaunchKernelGGL((k_band<1, false>), dim3(m.nblk), blk, 0, s, m, th, band, cnt);
+            hipLaunchKernelGGL((k_band<1, false>), grid, blk, 0, s, m, th, band, cnt);
         else
-            hipLaunchKernelGGL((k_band<2, false>), dim3(m.nblk), blk, 0, s, m, th, band, cnt);
+            hipLaunchKernelGGL((k_band<2, false>), grid, blk, 0, s, m, th, band, cnt);
     }
     return hipGetLastError();
 }
