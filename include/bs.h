@@ -58,6 +58,11 @@ extern "C" {
  * other pairs removed) instead of the matrix cores (G1 pairs only, FP32
  * MFMA contractions).  Both compute the same sum; for comparison. */
 #define BS_EVAL_VALU_FAR 0x10u
+/* bs_eval_velocity only: run every kernel on the given stream, one after
+ * another, instead of the band and ray-tracing kernels on two library
+ * streams beside the far field (same results; per-kernel times then
+ * measure each kernel alone). */
+#define BS_EVAL_SERIAL 0x20u
 
 /* Rules a (node, tetrahedron) pair can be evaluated with. */
 #define BS_RULE_G1 0  /* 1-point Gauss rule (centroid), degree 1              */
@@ -158,7 +163,10 @@ typedef struct {
 
 /* Velocity at every node, written to vel ([n_nodes][3] FP64, input node
  * order; host memory unless vel_flags has BS_PTR_DEVICE; BS_EVAL_VALU_FAR
- * selects the vector-ALU far field).  Uses the policy last set (defaults if
+ * selects the vector-ALU far field, BS_EVAL_SERIAL one stream).  The band
+ * and ray-tracing kernels run on two streams owned by the mesh, joined back
+ * to `stream` before the final sum, so the call is ordered on `stream` like
+ * a single kernel.  Uses the policy last set (defaults if
  * none).  st may be NULL.  Errors: BS_E_STATE (NULL mesh), BS_E_ARG (NULL
  * vel, unknown flag), BS_E_DEVICE (launch or runtime failure). */
 int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, bs_stats *st);

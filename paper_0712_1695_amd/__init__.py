@@ -38,6 +38,7 @@ BS_E_POLICY = -8
 BS_PTR_HOST = 0
 BS_PTR_DEVICE = 1
 BS_EVAL_VALU_FAR = 0x10
+BS_EVAL_SERIAL = 0x20
 
 BS_RULE_G1, BS_RULE_G4, BS_RULE_G11, BS_RULE_RT = 0, 1, 2, 3
 BS_POLICY_FIXED, BS_POLICY_PURE_RT, BS_POLICY_GAUSS_ONLY, BS_POLICY_LEARNED = 0, 1, 2, 3
@@ -282,13 +283,15 @@ def bs_set_policy(mesh: BsMesh, policy: Optional[Policy] = None, **kw):
     return p
 
 
-def bs_eval_velocity(mesh: BsMesh, out=None, stream=None, stats: bool = False, valu_far: bool = False):
+def bs_eval_velocity(mesh: BsMesh, out=None, stream=None, stats: bool = False, valu_far: bool = False,
+                     serial: bool = False):
     """Velocity at every node ([n,3] float64, input node order).  out: a
     device torch tensor to fill (returned), else a new numpy array.
-    valu_far: far field on the vector ALUs instead of the matrix cores."""
+    valu_far: far field on the vector ALUs instead of the matrix cores;
+    serial: every kernel on one stream (per-kernel times of each alone)."""
     L = load_library()
     st = Stats() if stats else None
-    extra = BS_EVAL_VALU_FAR if valu_far else 0
+    extra = (BS_EVAL_VALU_FAR if valu_far else 0) | (BS_EVAL_SERIAL if serial else 0)
     if out is None:
         vel = np.empty((mesh.n_nodes, 3), dtype=np.float64)
         rc = L.bs_eval_velocity(mesh.handle, ctypes.c_void_p(vel.ctypes.data), BS_PTR_HOST | extra,

@@ -220,6 +220,7 @@ struct bs_mesh {
     DBuf part, band, rtv, vel, cnt, nonfinite, fallback;
     int rt_mode = 0; // 0: walk where the boundary is convex, 1: always the candidate kernel
     int far_mode = 0; // 0: matrix-core far field (fixed-rule policies, FP32 modes), 1: vector-ALU kernel
+    int serial = 0;   // 1: every kernel on the caller's stream
     DBuf dir, dir64, cphi, dia;
     int part_splits = 0;
     // policy
@@ -227,7 +228,10 @@ struct bs_mesh {
     int ang_N = 0, ang_M = 0;
     DBuf mlp; // the learned policy's network in the fused inference's operand order
     DBuf sel; // learned policy on walk meshes: ray-traced lists, their counts and farthest centroids
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    // timing: 0 start, 1 far field done (caller's stream); 2-3 band (aux[0]);
+    // 4-5 ray tracing (aux[1]); 6-7 combine (caller's stream)
+    hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipStream_t aux[2] = {nullptr, nullptr}; // the band and ray-tracing kernels run beside the far field
 };
 
 namespace {
@@ -971,6 +975,11 @@ int bs_mesh_upload(const bs_mesh_desc *d, bs_mesh **out)
             bs_mesh_free(m);
             return fail(BS_E_DEVICE, "hipEventCreate");
         }
+    for (auto &a : m->aux)
+        if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess) {
+            bs_mesh_free(m);
+            return fail(BS_E_DEVICE, "hipStreamCreateWithFlags");
+        }
     *out = m;
     return BS_OK;
 }
@@ -999,8 +1008,12 @@ void bs_mesh_free(bs_mesh *m)
                     &m->cell_start, &m->part, &m->band, &m->rtv, &m->vel, &m->cnt, &m->nonfinite, &m->dir,
                     &m->dir64, &m->cphi, &m->dia, &m->mlp, &m->sel};
     for (DBuf *b : bufs) dfree(*b);
+    for (auto &a : m->aux)
+        if (a) (void)hipStreamSynchronize(a);
     for (auto &e : m->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto &a : m->aux)
+        if (a) (void)hipStreamDestroy(a);
     delete m;
 }
 
@@ -1074,6 +1087,8 @@ int eval_device(bs_mesh *m, hipStream_t s)
         return hip_fail(e, "clear counters");
     const double *part = nullptr, *band = nullptr, *rtv = nullptr;
     (void)hipEventRecord(m->ev[0], s);
+    if ((e = hipStreamWaitEvent(m->aux[0], m->ev[0], 0)) || (e = hipStreamWaitEvent(m->aux[1], m->ev[0], 0)))
+        return hip_fail(e, "fork streams");
     if (m->T > 0) {
         if (P.kind == BS_POLICY_GAUSS_ONLY) {
             const int pts = P.gauss_rule == BS_RULE_G1 ? 1 : P.gauss_rule == BS_RULE_G4 ? 4 : 11;
@@ -1091,12 +1106,16 @@ int eval_device(bs_mesh *m, hipStream_t s)
         }
     }
     (void)hipEventRecord(m->ev[1], s);
+    // band and ray tracing on their own streams, concurrent with the far field
+    hipStream_t sb = m->serial ? s : m->aux[0], sr = m->serial ? s : m->aux[1];
+    (void)hipEventRecord(m->ev[2], sb);
     if (m->T > 0 && fixed_like) {
-        if ((e = bsk::launch_band(dm, th, P.precision, far_mfma ? 0 : 1, (double *)m->band.p, cnt, s)))
+        if ((e = bsk::launch_band(dm, th, P.precision, far_mfma ? 0 : 1, (double *)m->band.p, cnt, sb)))
             return hip_fail(e, "band kernel");
         band = (const double *)m->band.p;
     }
-    (void)hipEventRecord(m->ev[2], s);
+    (void)hipEventRecord(m->ev[3], sb);
+    (void)hipEventRecord(m->ev[4], sr);
     bsk::LearnParams lp{};
     lp.net = P.kind == BS_POLICY_LEARNED ? (const bsk::PackedNet *)m->mlp.p : nullptr;
     lp.conf_min = P.conf_min;
@@ -1116,25 +1135,28 @@ int eval_device(bs_mesh *m, hipStream_t s)
                 sel_n = sel_list + nn * bsk::kSelListCap;
                 sel_dmax = (float *)(sel_n + nn);
             }
-            if ((e = hipMemsetAsync(nfb, 0, 4, s)) ||
+            if ((e = hipMemsetAsync(nfb, 0, 4, sr)) ||
                 (lp.net && (e = bsk::launch_select(dm, th, lp, P.precision, (double *)m->rtv.p, cnt, sel_list, sel_n,
-                                                   sel_dmax, s))) ||
+                                                   sel_dmax, sr))) ||
                 (e = bsk::launch_rt_walk(dm, th, ang, all, r_stop, P.precision, (double *)m->rtv.p, cnt,
-                                         (int *)m->fallback.p, nfb, sel_list, sel_n, sel_dmax, s)) ||
+                                         (int *)m->fallback.p, nfb, sel_list, sel_n, sel_dmax, sr)) ||
                 (e = bsk::launch_rt(dm, th, ang, lp, all, P.precision, (double *)m->rtv.p, cnt,
-                                    (const int *)m->fallback.p, nfb, s)))
+                                    (const int *)m->fallback.p, nfb, sr)))
                 return hip_fail(e, "ray-tracing walk");
         } else if ((e = bsk::launch_rt(dm, th, ang, lp, all, P.precision, (double *)m->rtv.p, cnt, nullptr, nullptr,
-                                       s))) {
+                                       sr))) {
             return hip_fail(e, "ray-tracing kernel");
         }
         rtv = (const double *)m->rtv.p;
     }
-    (void)hipEventRecord(m->ev[3], s);
+    (void)hipEventRecord(m->ev[5], sr);
+    if ((e = hipStreamWaitEvent(s, m->ev[3], 0)) || (e = hipStreamWaitEvent(s, m->ev[5], 0)))
+        return hip_fail(e, "join streams");
+    (void)hipEventRecord(m->ev[6], s);
     if ((e = bsk::launch_combine(dm, (const int *)m->node_orig.p, part, part ? splits : 0, band, rtv,
                                  (double *)m->vel.p, (int *)m->nonfinite.p, s)))
         return hip_fail(e, "combine kernel");
-    (void)hipEventRecord(m->ev[4], s);
+    (void)hipEventRecord(m->ev[7], s);
     return BS_OK;
 }
 
@@ -1149,11 +1171,11 @@ int read_stats(bs_mesh *m, bs_stats *st)
     const bs_policy &P = m->pol;
     std::memset(st, 0, sizeof *st);
     float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, m->ev[0], m->ev[4]);
+    (void)hipEventElapsedTime(&ms, m->ev[0], m->ev[7]);
     st->t_eval_s = ms * 1e-3;
     for (int k = 0; k < 4; ++k) {
         float mk = 0.f;
-        (void)hipEventElapsedTime(&mk, m->ev[k], m->ev[k + 1]);
+        (void)hipEventElapsedTime(&mk, m->ev[2 * k], m->ev[2 * k + 1]);
         st->t_kernel_s[k] = mk * 1e-3;
     }
     st->pairs = m->n * m->T;
@@ -1187,11 +1209,14 @@ int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, 
     g_err.clear();
     if (!m) return fail(BS_E_STATE, "null mesh");
     if (!vel) return fail(BS_E_ARG, "null output");
-    if (vel_flags & ~(BS_PTR_DEVICE | BS_EVAL_VALU_FAR)) return fail(BS_E_ARG, "unknown flags 0x%x", vel_flags);
+    if (vel_flags & ~(BS_PTR_DEVICE | BS_EVAL_VALU_FAR | BS_EVAL_SERIAL))
+        return fail(BS_E_ARG, "unknown flags 0x%x", vel_flags);
     hipStream_t s = (hipStream_t)stream;
     m->far_mode = (vel_flags & BS_EVAL_VALU_FAR) ? 1 : 0;
+    m->serial = (vel_flags & BS_EVAL_SERIAL) ? 1 : 0;
     int rc = eval_device(m, s);
     m->far_mode = 0;
+    m->serial = 0;
     if (rc) return rc;
     hipError_t e;
     const size_t vbytes = 8 * 3 * (size_t)m->n;
@@ -1225,7 +1250,7 @@ int bs_advect_heun(bs_mesh *m, double dt, int steps, double *xyz_out, uint32_t f
             (e = hipStreamSynchronize(s)))
             return hip_fail(e, "read velocity");
         float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, m->ev[0], m->ev[4]);
+        (void)hipEventElapsedTime(&ms, m->ev[0], m->ev[7]);
         t_dev += ms * 1e-3;
         return BS_OK;
     };
