@@ -4,10 +4,14 @@ on the same seeded inputs.
 Tolerance: relative L2 error <= 1e-6 over all nodes and components for the
 FP32 path (the stated target), per policy.  Rule decisions (binary32 on both
 sides) must match exactly, pair counts included."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 import oracle
+from oracle import references as R
 import paper_0712_1695_amd as bs
 import workloads as W
 
@@ -299,3 +303,49 @@ def test_walk_and_candidate_kernels_agree():
     b.omega = W.field_gaussian_swirl(b.xyz)
     vb, _ = gpu_eval(b)
     assert rel_l2(vb, oracle.evaluate(b.xyz, b.omega, b.tets)) <= TOL
+
+
+def test_concurrent_and_serial_streams_agree():
+    """The band and ray-tracing kernels on the mesh's own streams give the
+    same bits as every kernel on one stream."""
+    m = W.make_config("C1", scale=(12, 12, 12))
+    h = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
+    for kind in (bs.BS_POLICY_FIXED, bs.BS_POLICY_PURE_RT):
+        bs.bs_set_policy(h, kind=kind)
+        a = bs.bs_eval_velocity(h)
+        b = bs.bs_eval_velocity(h, serial=True)
+        assert np.array_equal(a, b)
+    bs.bs_mesh_free(h)
+
+
+def test_pure_ray_tracing_convergence():
+    """The paper's method alone (every pair ray traced) on the GPU: error
+    against the analytic velocity of a smooth vortex under refinement
+    (Section 3.2, Figure 4: about second order), on jittered Kuhn meshes of
+    [-2, 2]^3, 24 x 24 lines; every node with 0.3 sigma < |x| < 1.6 sigma is
+    compared.  At the coarsest mesh the GPU also matches the oracle."""
+    claims = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_claims.json")))
+    paper_p = claims["convergence_under_refinement"]["exponent"]
+    L, sig = 2.0, 0.5
+    hs, errs = [], []
+    for cells in (16, 24, 32, 48):
+        xyz, tets, hh, b = W.kuhn_grid((-L,) * 3, (L,) * 3, (cells,) * 3)
+        xyz = W.jitter_interior(xyz, b, hh, 0.1, 11)
+        tets = W.orient_positive(xyz, tets)
+        om, v = R.gaussian_vortex(xyz, sig)
+        vg, st = gpu_eval((xyz, om, tets), kind=bs.BS_POLICY_PURE_RT, n_phi=24, n_theta=24)
+        r = np.linalg.norm(xyz, axis=1)
+        sel = np.nonzero((r < 1.6 * sig) & (r > 0.3 * sig))[0]
+        err = np.sqrt(np.sum((vg[sel] - v[sel]) ** 2) / np.sum(v[sel] ** 2))
+        _say(f"pure RT, {cells}^3 cells (h {hh[0]:.4f}, {xyz.shape[0]} nodes): rel error {err:.3e}, "
+             f"t_eval {st['t_eval_s'] * 1e3:.1f} ms")
+        hs.append(hh[0])
+        errs.append(err)
+        if cells == 16:
+            tg = np.random.default_rng(0).choice(sel, size=16, replace=False)
+            ref = oracle.evaluate(xyz, om, tets, oracle.make_policy("pure_rt", n_phi=24, n_theta=24), targets=tg)
+            assert rel_l2(vg[tg], ref) <= TOL
+    p = np.polyfit(np.log(hs), np.log(errs), 1)[0]
+    _say(f"fitted order {p:.2f} (the paper's fit: {paper_p})")
+    assert 1.5 < p < 2.8
+    assert abs(p - paper_p) < 0.7
