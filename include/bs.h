@@ -171,6 +171,22 @@ typedef struct {
  * vel, unknown flag), BS_E_DEVICE (launch or runtime failure). */
 int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, bs_stats *st);
 
+/* Velocity at n_pts arbitrary points pts ([n_pts][3] FP64; Section 3.1
+ * evaluates the method at points that are not mesh nodes), written to vel
+ * ([n_pts][3] FP64, the order of pts); pts and vel are device memory when
+ * flags has BS_PTR_DEVICE, else host (BS_EVAL_VALU_FAR and BS_EVAL_SERIAL as
+ * for bs_eval_velocity).  Every tet contributes by the current policy's
+ * rule for its pair with the point; no tet has a point as a vertex, so a
+ * point inside a tet is ray traced from inside it (its chords start at the
+ * point, with the tet's linear vorticity there) and a point outside the
+ * mesh sees only whole chords.  The points are kept with the mesh (a new
+ * set re-runs the per-element precompute once; the nodes' own evaluation is
+ * unaffected); n_pts = 0 clears them.  Errors: BS_E_STATE (NULL mesh),
+ * BS_E_ARG (n_pts < 0 or above 2^28, NULL pointer, unknown flag),
+ * BS_E_NONFINITE (a coordinate), BS_E_DEVICE. */
+int bs_eval_points(bs_mesh *m, int64_t n_pts, const double *pts, double *vel, uint32_t flags, void *stream,
+                   bs_stats *st);
+
 /* Lagrangian motion of the nodes (the paper's setting, Sections 1 and 3:
  * control points move with the flow and the velocity is re-evaluated every
  * step): `steps` Heun (RK2) steps of size dt,

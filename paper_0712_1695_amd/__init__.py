@@ -95,7 +95,7 @@ class Stats(ctypes.Structure):
 
 # every symbol include/bs.h declares
 EXPORTS = ["bs_mesh_upload", "bs_mesh_update", "bs_mesh_free", "bs_policy_default", "bs_set_policy",
-           "bs_eval_velocity", "bs_advect_heun", "bs_learn_sample_pairs", "bs_learn_pairs", "bs_mlp_train",
+           "bs_eval_velocity", "bs_eval_points", "bs_advect_heun", "bs_learn_sample_pairs", "bs_learn_pairs", "bs_mlp_train",
            "bs_mlp_grad", "bs_mlp_logits", "bs_status_string", "bs_last_error"]
 
 BS_MLP_BLOB_LEN = 5540
@@ -149,6 +149,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     L.bs_set_policy.restype = ctypes.c_int
     L.bs_eval_velocity.argtypes = [vp, vp, ctypes.c_uint32, vp, ctypes.POINTER(Stats)]
     L.bs_eval_velocity.restype = ctypes.c_int
+    L.bs_eval_points.argtypes = [vp, ctypes.c_int64, vp, vp, ctypes.c_uint32, vp, ctypes.POINTER(Stats)]
+    L.bs_eval_points.restype = ctypes.c_int
     L.bs_advect_heun.argtypes = [vp, ctypes.c_double, ctypes.c_int, vp, ctypes.c_uint32, vp, vp,
                                  ctypes.POINTER(Stats)]
     L.bs_advect_heun.restype = ctypes.c_int
@@ -306,6 +308,34 @@ def bs_eval_velocity(mesh: BsMesh, out=None, stream=None, stats: bool = False, v
         rc = L.bs_eval_velocity(mesh.handle, ctypes.c_void_p(out.data_ptr()), BS_PTR_DEVICE | extra,
                                 _stream_handle(stream), ctypes.byref(st) if st is not None else None)
     _check(rc, "bs_eval_velocity")
+    return (vel, st.as_dict()) if stats else vel
+
+
+def bs_eval_points(mesh: BsMesh, pts, out=None, stream=None, stats: bool = False, valu_far: bool = False,
+                   serial: bool = False):
+    """Velocity at arbitrary points pts ([k,3] float64: numpy, or a device
+    tensor, then out must be a device tensor too).  Returns [k,3] (numpy, or
+    `out`)[, stats dict]."""
+    L = load_library()
+    st = Stats() if stats else None
+    extra = (BS_EVAL_VALU_FAR if valu_far else 0) | (BS_EVAL_SERIAL if serial else 0)
+    if _is_torch(pts) and pts.is_cuda:
+        if out is None or not (_is_torch(out) and out.is_cuda and out.is_contiguous()):
+            raise ValueError("device points need a contiguous device output tensor")
+        if tuple(out.shape) != tuple(pts.shape):
+            raise ValueError("out must have the shape of pts")
+        p = pts.contiguous()
+        rc = L.bs_eval_points(mesh.handle, int(p.shape[0]), ctypes.c_void_p(p.data_ptr()),
+                              ctypes.c_void_p(out.data_ptr()), BS_PTR_DEVICE | extra, _stream_handle(stream),
+                              ctypes.byref(st) if st is not None else None)
+        vel = out
+    else:
+        p = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+        vel = np.empty_like(p)
+        rc = L.bs_eval_points(mesh.handle, int(p.shape[0]), ctypes.c_void_p(p.ctypes.data),
+                              ctypes.c_void_p(vel.ctypes.data), BS_PTR_HOST | extra, _stream_handle(stream),
+                              ctypes.byref(st) if st is not None else None)
+    _check(rc, "bs_eval_points")
     return (vel, st.as_dict()) if stats else vel
 
 

@@ -218,6 +218,13 @@ struct bs_mesh {
     // device buffers
     DBuf xh, xl, om, blk, node_orig, g1, g4, g11, tid, cell_start, nbr, inc_start, inc_list;
     DBuf part, band, rtv, vel, cnt, nonfinite, fallback;
+    // evaluation points (bs_eval_points): FP64 copy, count, first node index
+    // and first block in the node arrays, their order and output
+    std::vector<double> tgt;
+    int64_t tn = 0;
+    int t0 = 0, tblk0 = 0, tnblk = 0;
+    DBuf torig, tlist, tvel;
+    bool last_targets = false; // the last evaluation was of the points
     int rt_mode = 0; // 0: walk where the boundary is convex, 1: always the candidate kernel
     int far_mode = 0; // 0: matrix-core far field (fixed-rule policies, FP32 modes), 1: vector-ALU kernel
     int serial = 0;   // 1: every kernel on the caller's stream
@@ -445,69 +452,54 @@ bool boundary_convex(const bs_mesh *m)
 
 // Everything that depends on coordinates and vorticity: node order, bins,
 // per-tet records.  Connectivity is already validated.
-int build_device_mesh(bs_mesh *m, hipStream_t s)
+// Order of n points (FP64 [n][3]) in which recursive median splits across
+// the longest axis, at multiples of 64, leave every consecutive 64 spatially
+// compact.
+std::vector<int32_t> kd_leaf_order(const double *X, int64_t n)
 {
-    const int64_t n = m->n, T = m->T;
-    const double *X = m->xyz.data(), *W = m->omega.data();
-    m->hbar = T > 0 ? mean_edge(n, X, T, m->tets.data()) : 0.0;
-
-    // ---- nodes ordered by a k-d split into leaves of 64 (one band-kernel
-    // block per leaf): recursive median splits across the longest axis, at
-    // multiples of the leaf size, give compact blocks
-    std::vector<int32_t> orig((size_t)n), rank((size_t)n);
+    std::vector<int32_t> orig((size_t)n);
     for (int64_t i = 0; i < n; ++i) orig[(size_t)i] = (int32_t)i;
-    {
-        struct Range {
-            int64_t a, b;
-        };
-        std::vector<Range> stack{{0, n}};
-        while (!stack.empty()) {
-            const Range r = stack.back();
-            stack.pop_back();
-            const int64_t len = r.b - r.a;
-            if (len <= bsk::kBlockNodes) continue;
-            double lo3[3] = {1e300, 1e300, 1e300}, hi3[3] = {-1e300, -1e300, -1e300};
-            for (int64_t k = r.a; k < r.b; ++k)
-                for (int c = 0; c < 3; ++c) {
-                    const double v = X[3 * (int64_t)orig[(size_t)k] + c];
-                    lo3[c] = std::min(lo3[c], v);
-                    hi3[c] = std::max(hi3[c], v);
-                }
-            int ax = 0;
-            for (int c = 1; c < 3; ++c)
-                if (hi3[c] - lo3[c] > hi3[ax] - lo3[ax]) ax = c;
-            int64_t k = ((len / 2 + bsk::kBlockNodes / 2) / bsk::kBlockNodes) * bsk::kBlockNodes;
-            k = std::min(std::max<int64_t>(k, bsk::kBlockNodes), len - 1);
-            std::nth_element(orig.begin() + r.a, orig.begin() + r.a + k, orig.begin() + r.b,
-                             [&](int32_t u, int32_t v) {
-                                 const double xu = X[3 * (int64_t)u + ax], xv = X[3 * (int64_t)v + ax];
-                                 return xu < xv || (xu == xv && u < v);
-                             });
-            stack.push_back({r.a + k, r.b});
-            stack.push_back({r.a, r.a + k});
-        }
+    struct Range {
+        int64_t a, b;
+    };
+    std::vector<Range> stack{{0, n}};
+    while (!stack.empty()) {
+        const Range r = stack.back();
+        stack.pop_back();
+        const int64_t len = r.b - r.a;
+        if (len <= bsk::kBlockNodes) continue;
+        double lo3[3] = {1e300, 1e300, 1e300}, hi3[3] = {-1e300, -1e300, -1e300};
+        for (int64_t k = r.a; k < r.b; ++k)
+            for (int c = 0; c < 3; ++c) {
+                const double v = X[3 * (int64_t)orig[(size_t)k] + c];
+                lo3[c] = std::min(lo3[c], v);
+                hi3[c] = std::max(hi3[c], v);
+            }
+        int ax = 0;
+        for (int c = 1; c < 3; ++c)
+            if (hi3[c] - lo3[c] > hi3[ax] - lo3[ax]) ax = c;
+        int64_t k = ((len / 2 + bsk::kBlockNodes / 2) / bsk::kBlockNodes) * bsk::kBlockNodes;
+        k = std::min(std::max<int64_t>(k, bsk::kBlockNodes), len - 1);
+        std::nth_element(orig.begin() + r.a, orig.begin() + r.a + k, orig.begin() + r.b, [&](int32_t u, int32_t v) {
+            const double xu = X[3 * (int64_t)u + ax], xv = X[3 * (int64_t)v + ax];
+            return xu < xv || (xu == xv && u < v);
+        });
+        stack.push_back({r.a + k, r.b});
+        stack.push_back({r.a, r.a + k});
     }
-    for (int64_t i = 0; i < n; ++i) rank[(size_t)orig[(size_t)i]] = (int32_t)i;
-    const int npad = (int)(((n + 1023) / 1024) * 1024);
-    const int nblk = (int)((n + bsk::kBlockNodes - 1) / bsk::kBlockNodes);
-    m->npad = npad;
-    m->nblk = nblk;
-    std::vector<float> xh((size_t)3 * npad), xl((size_t)3 * npad), om((size_t)3 * npad);
-    for (int64_t p = 0; p < npad; ++p) {
-        const int64_t i = p < n ? orig[(size_t)p] : orig[0];
-        for (int c = 0; c < 3; ++c) {
-            const double x = X[3 * i + c];
-            const float h = (float)x;
-            xh[(size_t)c * npad + p] = h;
-            xl[(size_t)c * npad + p] = (float)(x - (double)h);
-            om[(size_t)c * npad + p] = (float)W[3 * i + c];
-        }
-    }
-    std::vector<float4> blk((size_t)nblk);
-    for (int b = 0; b < nblk; ++b) {
+    return orig;
+}
+
+// Bounding spheres of the 64-point blocks of points [p0, p0 + count) of the
+// binary32 SoA coordinates (stride npad): centre of the box, radius with a
+// margin.
+void block_spheres(const std::vector<float> &xh, int npad, int64_t p0, int64_t count, float4 *out)
+{
+    const int nb = (int)((count + bsk::kBlockNodes - 1) / bsk::kBlockNodes);
+    for (int b = 0; b < nb; ++b) {
         float bl[3] = {3e38f, 3e38f, 3e38f}, bh[3] = {-3e38f, -3e38f, -3e38f};
-        const int64_t e = std::min<int64_t>(n, (int64_t)(b + 1) * bsk::kBlockNodes);
-        for (int64_t p = (int64_t)b * bsk::kBlockNodes; p < e; ++p)
+        const int64_t a = p0 + (int64_t)b * bsk::kBlockNodes, e = p0 + std::min<int64_t>(count, (int64_t)(b + 1) * bsk::kBlockNodes);
+        for (int64_t p = a; p < e; ++p)
             for (int c = 0; c < 3; ++c) {
                 bl[c] = std::min(bl[c], xh[(size_t)c * npad + p]);
                 bh[c] = std::max(bh[c], xh[(size_t)c * npad + p]);
@@ -515,7 +507,7 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
         float cc[3];
         for (int c = 0; c < 3; ++c) cc[c] = 0.5f * (bl[c] + bh[c]);
         double r2 = 0.0;
-        for (int64_t p = (int64_t)b * bsk::kBlockNodes; p < e; ++p) {
+        for (int64_t p = a; p < e; ++p) {
             double d2 = 0.0;
             for (int c = 0; c < 3; ++c) {
                 const double d = (double)xh[(size_t)c * npad + p] - cc[c];
@@ -523,8 +515,52 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
             }
             r2 = std::max(r2, d2);
         }
-        blk[(size_t)b] = make_float4(cc[0], cc[1], cc[2], (float)(std::sqrt(r2) * (1 + 1e-5) + 1e-6));
+        out[b] = make_float4(cc[0], cc[1], cc[2], (float)(std::sqrt(r2) * (1 + 1e-5) + 1e-6));
     }
+}
+
+int build_device_mesh(bs_mesh *m, hipStream_t s)
+{
+    const int64_t n = m->n, T = m->T;
+    const double *X = m->xyz.data(), *W = m->omega.data();
+    m->hbar = T > 0 ? mean_edge(n, X, T, m->tets.data()) : 0.0;
+
+    // ---- nodes ordered by a k-d split into leaves of 64 (one band-kernel
+    // block per leaf); evaluation points (bs_eval_points) follow the nodes
+    // from t0 = n rounded up to 1024, ordered the same way among themselves
+    const std::vector<int32_t> orig = kd_leaf_order(X, n);
+    std::vector<int32_t> rank((size_t)n);
+    for (int64_t i = 0; i < n; ++i) rank[(size_t)orig[(size_t)i]] = (int32_t)i;
+    const int64_t tn = m->tn;
+    const std::vector<int32_t> torig = kd_leaf_order(m->tgt.data(), tn);
+    const int64_t t0 = tn > 0 ? ((n + 1023) / 1024) * 1024 : n;
+    const int npad = (int)(((t0 + tn + 1023) / 1024) * 1024);
+    const int nblk = (int)((n + bsk::kBlockNodes - 1) / bsk::kBlockNodes);
+    const int tblk0 = (int)(t0 / bsk::kBlockNodes);
+    const int tnblk = (int)((tn + bsk::kBlockNodes - 1) / bsk::kBlockNodes);
+    m->npad = npad;
+    m->nblk = nblk;
+    m->t0 = (int)t0;
+    m->tblk0 = tblk0;
+    m->tnblk = tnblk;
+    std::vector<float> xh((size_t)3 * npad), xl((size_t)3 * npad), om((size_t)3 * npad);
+    for (int64_t p = 0; p < npad; ++p) {
+        const bool is_t = p >= t0 && p < t0 + tn;
+        const int64_t i = p < n ? orig[(size_t)p] : is_t ? torig[(size_t)(p - t0)] : (n > 0 ? orig[0] : 0);
+        for (int c = 0; c < 3; ++c) {
+            const double x = is_t ? m->tgt[3 * i + c] : (n > 0 ? X[3 * i + c] : 0.0);
+            const float h = (float)x;
+            xh[(size_t)c * npad + p] = h;
+            xl[(size_t)c * npad + p] = (float)(x - (double)h);
+            om[(size_t)c * npad + p] = (is_t || n == 0) ? 0.f : (float)W[3 * i + c];
+        }
+    }
+    std::vector<float4> blk((size_t)std::max(nblk, tblk0 + tnblk));
+    block_spheres(xh, npad, 0, n, blk.data());
+    if (tn > 0) block_spheres(xh, npad, t0, tn, blk.data() + tblk0);
+    std::vector<int32_t> tlist((size_t)tn + 1);
+    for (int64_t k = 0; k < tn; ++k) tlist[(size_t)k] = (int32_t)(t0 + k);
+    tlist[(size_t)tn] = (int32_t)tn;
 
     // ---- tets: centroids, bins
     std::vector<double> cen((size_t)(3 * T));
@@ -674,7 +710,9 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
     int rc;
     const size_t nb = sizeof(float) * 3 * (size_t)npad;
     if ((rc = dalloc(m->xh, nb)) || (rc = dalloc(m->xl, nb)) || (rc = dalloc(m->om, nb)) ||
-        (rc = dalloc(m->blk, sizeof(float4) * (size_t)nblk)) || (rc = dalloc(m->node_orig, 4 * (size_t)n)) ||
+        (rc = dalloc(m->blk, sizeof(float4) * blk.size())) || (rc = dalloc(m->node_orig, 4 * (size_t)n)) ||
+        (rc = dalloc(m->torig, 4 * torig.size())) || (rc = dalloc(m->tlist, 4 * tlist.size())) ||
+        (rc = dalloc(m->tvel, 8 * 3 * (size_t)tn)) ||
         (rc = dalloc(m->g1, 4 * g1.size())) || (rc = dalloc(m->g4, 4 * g4.size())) ||
         (rc = dalloc(m->g11, 4 * g11.size())) || (rc = dalloc(m->tid, sizeof(int4) * (size_t)T)) ||
         (rc = dalloc(m->cell_start, 4 * cell_start.size())) || (rc = dalloc(m->band, 8 * 3 * (size_t)npad)) ||
@@ -694,6 +732,8 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
     BS_UP(om, om)
     BS_UP(blk, blk)
     BS_UP(node_orig, orig)
+    BS_UP(torig, torig)
+    BS_UP(tlist, tlist)
     BS_UP(g1, g1)
     BS_UP(g4, g4)
     BS_UP(g11, g11)
@@ -795,6 +835,8 @@ bsk::DevMesh dev_view(const bs_mesh *m)
     d.inc_start = (const int *)m->inc_start.p;
     d.inc_list = (const int *)m->inc_list.p;
     d.bins = m->bins;
+    d.blk0 = 0;
+    d.nv = (int)m->n;
     return d;
 }
 
@@ -1006,7 +1048,7 @@ void bs_mesh_free(bs_mesh *m)
     DBuf *bufs[] = {&m->xh, &m->xl, &m->om, &m->blk, &m->node_orig, &m->g1, &m->g4, &m->g11, &m->tid,
                     &m->nbr, &m->inc_start, &m->inc_list, &m->fallback,
                     &m->cell_start, &m->part, &m->band, &m->rtv, &m->vel, &m->cnt, &m->nonfinite, &m->dir,
-                    &m->dir64, &m->cphi, &m->dia, &m->mlp, &m->sel};
+                    &m->dir64, &m->cphi, &m->dia, &m->mlp, &m->sel, &m->torig, &m->tlist, &m->tvel};
     for (DBuf *b : bufs) dfree(*b);
     for (auto &a : m->aux)
         if (a) (void)hipStreamSynchronize(a);
@@ -1040,12 +1082,21 @@ int bs_set_policy(bs_mesh *m, const bs_policy *p)
 namespace {
 
 // One evaluation into m->vel (device, input node order), on stream s.
-int eval_device(bs_mesh *m, hipStream_t s)
+// targets: the evaluation points after the nodes (bs_eval_points) instead
+// of the nodes; their velocities go to m->tvel.
+int eval_device(bs_mesh *m, hipStream_t s, bool targets)
 {
     int rc = install_angular(m);
     if (rc) return rc;
     const bs_policy &P = m->pol;
     bsk::DevMesh dm = dev_view(m);
+    if (targets) {
+        dm.n = (int)m->tn;
+        dm.blk0 = m->tblk0;
+        dm.nblk = m->tnblk;
+        dm.nv = m->t0 + (int)m->tn;
+    }
+    m->last_targets = targets;
 
     // tet splits of the all-pairs Gauss kernel: enough waves to fill 256 CUs
     const int node_blocks = m->npad / 1024;
@@ -1122,7 +1173,7 @@ int eval_device(bs_mesh *m, hipStream_t s)
     lp.hbar = (float)m->hbar;
     if (m->T > 0 && (fixed_like || P.kind == BS_POLICY_PURE_RT)) {
         const int all = P.kind == BS_POLICY_PURE_RT;
-        if (m->convex && m->rt_mode == 0) {
+        if (m->convex && m->rt_mode == 0 && !targets) {
             if ((rc = dalloc(m->fallback, 4 * ((size_t)m->n + 1)))) return rc;
             int *nfb = (int *)m->fallback.p + m->n;
             const float r_stop = all ? 3.0e38f : (float)((std::max(c_rt, m->max_vc) + m->max_vc) * (1.0 + 1e-4) + 1e-6);
@@ -1143,8 +1194,9 @@ int eval_device(bs_mesh *m, hipStream_t s)
                 (e = bsk::launch_rt(dm, th, ang, lp, all, P.precision, (double *)m->rtv.p, cnt,
                                     (const int *)m->fallback.p, nfb, sr)))
                 return hip_fail(e, "ray-tracing walk");
-        } else if ((e = bsk::launch_rt(dm, th, ang, lp, all, P.precision, (double *)m->rtv.p, cnt, nullptr, nullptr,
-                                       sr))) {
+        } else if ((e = bsk::launch_rt(dm, th, ang, lp, all, P.precision, (double *)m->rtv.p, cnt,
+                                       targets ? (const int *)m->tlist.p : nullptr,
+                                       targets ? (const int *)m->tlist.p + m->tn : nullptr, sr))) {
             return hip_fail(e, "ray-tracing kernel");
         }
         rtv = (const double *)m->rtv.p;
@@ -1153,8 +1205,8 @@ int eval_device(bs_mesh *m, hipStream_t s)
     if ((e = hipStreamWaitEvent(s, m->ev[3], 0)) || (e = hipStreamWaitEvent(s, m->ev[5], 0)))
         return hip_fail(e, "join streams");
     (void)hipEventRecord(m->ev[6], s);
-    if ((e = bsk::launch_combine(dm, (const int *)m->node_orig.p, part, part ? splits : 0, band, rtv,
-                                 (double *)m->vel.p, (int *)m->nonfinite.p, s)))
+    if ((e = bsk::launch_combine(dm, (const int *)(targets ? m->torig.p : m->node_orig.p), part, part ? splits : 0,
+                                 band, rtv, (double *)(targets ? m->tvel.p : m->vel.p), (int *)m->nonfinite.p, s)))
         return hip_fail(e, "combine kernel");
     (void)hipEventRecord(m->ev[7], s);
     return BS_OK;
@@ -1178,7 +1230,7 @@ int read_stats(bs_mesh *m, bs_stats *st)
         (void)hipEventElapsedTime(&mk, m->ev[2 * k], m->ev[2 * k + 1]);
         st->t_kernel_s[k] = mk * 1e-3;
     }
-    st->pairs = m->n * m->T;
+    st->pairs = (m->last_targets ? m->tn : m->n) * m->T;
     if (P.kind == BS_POLICY_FIXED || P.kind == BS_POLICY_LEARNED) {
         // c[2] counts the pairs actually ray traced; the learned selector's
         // moves out of the ray-traced band are c[5..7]
@@ -1214,7 +1266,7 @@ int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, 
     hipStream_t s = (hipStream_t)stream;
     m->far_mode = (vel_flags & BS_EVAL_VALU_FAR) ? 1 : 0;
     m->serial = (vel_flags & BS_EVAL_SERIAL) ? 1 : 0;
-    int rc = eval_device(m, s);
+    int rc = eval_device(m, s, false);
     m->far_mode = 0;
     m->serial = 0;
     if (rc) return rc;
@@ -1224,6 +1276,55 @@ int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, 
                                                                           : hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return hip_fail(e, "copy velocity");
     if (!(vel_flags & BS_PTR_DEVICE) || st) {
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "evaluation");
+    }
+    if (st && (rc = read_stats(m, st))) return rc;
+    return BS_OK;
+}
+
+int bs_eval_points(bs_mesh *m, int64_t n_pts, const double *pts, double *vel, uint32_t flags, void *stream,
+                   bs_stats *st)
+{
+    g_err.clear();
+    if (!m) return fail(BS_E_STATE, "null mesh");
+    if (n_pts < 0 || (n_pts > 0 && (!pts || !vel))) return fail(BS_E_ARG, "n_pts < 0 or null pointer");
+    if (n_pts > (int64_t)1 << 28) return fail(BS_E_ARG, "too many points (%lld)", (long long)n_pts);
+    if (flags & ~(BS_PTR_DEVICE | BS_EVAL_VALU_FAR | BS_EVAL_SERIAL)) return fail(BS_E_ARG, "unknown flags 0x%x", flags);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    std::vector<double> p((size_t)3 * n_pts);
+    if (n_pts > 0) {
+        if (flags & BS_PTR_DEVICE) {
+            if ((e = hipMemcpyAsync(p.data(), pts, 8 * p.size(), hipMemcpyDeviceToHost, s)) ||
+                (e = hipStreamSynchronize(s)))
+                return hip_fail(e, "read points");
+        } else {
+            std::memcpy(p.data(), pts, 8 * p.size());
+        }
+    }
+    for (double v : p)
+        if (!std::isfinite(v)) return fail(BS_E_NONFINITE, "non-finite point coordinate");
+    int rc;
+    if (p != m->tgt) {
+        // the points join the node arrays after the nodes (one re-upload)
+        m->tgt.swap(p);
+        m->tn = n_pts;
+        if ((rc = build_device_mesh(m, s))) return rc;
+    }
+    if (n_pts == 0) {
+        if (st) std::memset(st, 0, sizeof *st);
+        return BS_OK;
+    }
+    m->far_mode = (flags & BS_EVAL_VALU_FAR) ? 1 : 0;
+    m->serial = (flags & BS_EVAL_SERIAL) ? 1 : 0;
+    rc = eval_device(m, s, true);
+    m->far_mode = 0;
+    m->serial = 0;
+    if (rc) return rc;
+    e = hipMemcpyAsync(vel, m->tvel.p, 8 * 3 * (size_t)n_pts,
+                       (flags & BS_PTR_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "copy velocity");
+    if (!(flags & BS_PTR_DEVICE) || st) {
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "evaluation");
     }
     if (st && (rc = read_stats(m, st))) return rc;
@@ -1244,7 +1345,7 @@ int bs_advect_heun(bs_mesh *m, double dt, int steps, double *xyz_out, uint32_t f
     int rc = BS_OK;
     hipError_t e;
     auto eval_to = [&](std::vector<double> &v) -> int {
-        int r = eval_device(m, s);
+        int r = eval_device(m, s, false);
         if (r) return r;
         if ((e = hipMemcpyAsync(v.data(), m->vel.p, 8 * n3, hipMemcpyDeviceToHost, s)) ||
             (e = hipStreamSynchronize(s)))

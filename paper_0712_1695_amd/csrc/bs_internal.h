@@ -67,8 +67,13 @@ struct LearnParams {
     float hbar;
 };
 
+// A view of the mesh for one evaluation.  The targets are the nodes
+// [64 blk0, nv) of the node arrays in blocks blk0 .. blk0+nblk-1, n of them:
+// the mesh's own nodes (blk0 = 0, nv = n), or points placed after them
+// (bs_eval_points; no tet has them as a vertex).
 struct DevMesh {
     int n, npad, T, nblk;
+    int blk0, nv;
     const float *xh, *xl, *om;
     const float4 *blk;
     const float *g1, *g4, *g11;

@@ -119,14 +119,14 @@ __device__ __forceinline__ void gauss_point_n(const float *x, const float *y, co
 // scalar operands.  PREC: 0 naive FP32, 1 TwoSum-compensated FP32 tiles,
 // 2 FP64 accumulation.
 template <int NPTS, int NPL, int PREC>
-__global__ void __launch_bounds__(256) k_gauss_all(const float *__restrict__ xh, int npad,
+__global__ void __launch_bounds__(256) k_gauss_all(const float *__restrict__ xh, int npad, int node0,
                                                    const float *__restrict__ rec, int T, int per_split,
                                                    double *__restrict__ part)
 {
     constexpr int kTile = 32;
     const int t0 = blockIdx.y * per_split;
     const int t1 = min(T, t0 + per_split);
-    const int base = blockIdx.x * (256 * NPL) + threadIdx.x;
+    const int base = node0 + blockIdx.x * (256 * NPL) + threadIdx.x;
     float x[NPL], y[NPL], z[NPL];
     float ax[NPL], ay[NPL], az[NPL];
     float sx[NPL], sy[NPL], sz[NPL], cx[NPL], cy[NPL], cz[NPL];
@@ -199,13 +199,13 @@ __global__ void __launch_bounds__(256) k_gauss_all(const float *__restrict__ xh,
 // per-term FP64 variant (every pair term converted and added in FP64) is
 // this one, used for BS_PREC_FP64.
 template <int NPTS, int NPL>
-__global__ void __launch_bounds__(256) k_gauss_all_f64(const float *__restrict__ xh, int npad,
+__global__ void __launch_bounds__(256) k_gauss_all_f64(const float *__restrict__ xh, int npad, int node0,
                                                        const float *__restrict__ rec, int T, int per_split,
                                                        double *__restrict__ part)
 {
     const int t0 = blockIdx.y * per_split;
     const int t1 = min(T, t0 + per_split);
-    const int base = blockIdx.x * (256 * NPL) + threadIdx.x;
+    const int base = node0 + blockIdx.x * (256 * NPL) + threadIdx.x;
     float x[NPL], y[NPL], z[NPL];
     double dx[NPL], dy[NPL], dz[NPL];
 #pragma unroll
@@ -245,15 +245,16 @@ template <int NPTS>
 static hipError_t launch_gauss_pts(const DevMesh &m, int precision, int splits, double *part, hipStream_t s)
 {
     const int per = (m.T + splits - 1) / splits;
-    dim3 grid(m.npad / (256 * kNpl), splits);
+    const int node0 = m.blk0 * kBlockNodes; // a multiple of 1024 (see build_device_mesh)
+    dim3 grid((m.nv - node0 + 256 * kNpl - 1) / (256 * kNpl), splits);
     if (precision == 0)
-        hipLaunchKernelGGL((k_gauss_all<NPTS, kNpl, 0>), grid, dim3(256), 0, s, m.xh, m.npad, NPTS == 1 ? m.g1
+        hipLaunchKernelGGL((k_gauss_all<NPTS, kNpl, 0>), grid, dim3(256), 0, s, m.xh, m.npad, node0, NPTS == 1 ? m.g1
                            : NPTS == 4 ? m.g4 : m.g11, m.T, per, part);
     else if (precision == 1)
-        hipLaunchKernelGGL((k_gauss_all<NPTS, kNpl, 1>), grid, dim3(256), 0, s, m.xh, m.npad, NPTS == 1 ? m.g1
+        hipLaunchKernelGGL((k_gauss_all<NPTS, kNpl, 1>), grid, dim3(256), 0, s, m.xh, m.npad, node0, NPTS == 1 ? m.g1
                            : NPTS == 4 ? m.g4 : m.g11, m.T, per, part);
     else
-        hipLaunchKernelGGL((k_gauss_all_f64<NPTS, kNpl>), grid, dim3(256), 0, s, m.xh, m.npad, NPTS == 1 ? m.g1
+        hipLaunchKernelGGL((k_gauss_all_f64<NPTS, kNpl>), grid, dim3(256), 0, s, m.xh, m.npad, node0, NPTS == 1 ? m.g1
                            : NPTS == 4 ? m.g4 : m.g11, m.T, per, part);
     return hipGetLastError();
 }
@@ -335,8 +336,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     // workgroup id = block * splits + split: consecutive ids go to the eight
     // XCDs in turn, so with eight splits each XCD streams one eighth of the
     // tets through its own L2
-    const int b = blockIdx.x / splits;
-    const int split = blockIdx.x - b * splits;
+    const int bl = blockIdx.x / splits;
+    const int split = blockIdx.x - bl * splits;
+    const int b = m.blk0 + bl;
     const int t0 = split * per_split;
     const int t1 = min(m.T, t0 + per_split);
     const float4 bc = m.blk[b];
@@ -350,10 +352,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const float cc = c == 0 ? bc.x : c == 1 ? bc.y : bc.z;
-            xp[c] = i < m.n ? (m.xh[c * m.npad + i] - cc) + m.xl[c * m.npad + i] : 0.f;
+            xp[c] = i < m.nv ? (m.xh[c * m.npad + i] - cc) + m.xl[c * m.npad + i] : 0.f;
         }
         B1[nt] = q == 0 ? xp[0] : q == 1 ? xp[1] : q == 2 ? xp[2] : 1.f;
-        Cin[nt] = i < m.n ? (xp[0] * xp[0] + xp[1] * xp[1]) + xp[2] * xp[2] : 1e30f;
+        Cin[nt] = i < m.nv ? (xp[0] * xp[0] + xp[1] * xp[1]) + xp[2] * xp[2] : 1e30f;
     }
     if (tid < 64) {
         const int i = b * kBlockNodes + tid;
@@ -362,7 +364,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     __syncthreads();
     if (tid < 4) {
         float lo[3] = {3e38f, 3e38f, 3e38f}, hi[3] = {-3e38f, -3e38f, -3e38f};
-        const int nv = min(16, m.n - (b * kBlockNodes + 16 * tid));
+        const int nv = min(16, m.nv - (b * kBlockNodes + 16 * tid));
         for (int k = 0; k < nv; ++k) {
             const float4 x = S.xn[16 * tid + k];
             lo[0] = fminf(lo[0], x.x), hi[0] = fmaxf(hi[0], x.x);
@@ -537,7 +539,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
             sw[r] = ((S.red[0][nt][r][n16] + S.red[1][nt][r][n16]) + S.red[2][nt][r][n16]) + S.red[3][nt][r][n16];
         const int i = b * kBlockNodes + tid;
         double xp[3] = {0.0, 0.0, 0.0};
-        if (i < m.n) {
+        if (i < m.nv) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const float cc = c == 0 ? bc.x : c == 1 ? bc.y : bc.z;
@@ -635,10 +637,11 @@ __global__ void __launch_bounds__(64 * kBandWaves) k_band(DevMesh m, Thresholds 
     // contiguous range of (spatially ordered) blocks, whose neighbourhoods
     // overlap in its L2
     const int per_xcd = (m.nblk + 7) >> 3;
-    const int blk = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    if (blk >= m.nblk) return;
+    const int lb = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (lb >= m.nblk) return;
+    const int blk = m.blk0 + lb;
     const int i = blk * kBlockNodes + lane;
-    const bool valid = i < m.n;
+    const bool valid = i < m.nv;
     const float x = m.xh[i], y = m.xh[m.npad + i], z = m.xh[2 * m.npad + i];
     const float4 bc = m.blk[blk];
     float sx = 0.f, sy = 0.f, sz = 0.f, ccx = 0.f, ccy = 0.f, ccz = 0.f;
@@ -1952,14 +1955,15 @@ hipError_t launch_rt_walk(const DevMesh &m, const Thresholds &th, const AngTab &
 }
 
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_combine(int n, int npad, const int *__restrict__ node_orig,
+__global__ void __launch_bounds__(256) k_combine(int n, int first, int npad, const int *__restrict__ node_orig,
                                                  const double *__restrict__ part, int splits,
                                                  const double *__restrict__ band, const double *__restrict__ rtv,
                                                  double *__restrict__ vel, int *__restrict__ nonfinite)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const int o = node_orig[i];
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    const int o = node_orig[k];
+    const int i = first + k;
     bool bad = false;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -1977,8 +1981,8 @@ hipError_t launch_combine(const DevMesh &m, const int *node_orig, const double *
                           const double *band, const double *rtv, double *vel, int *nonfinite, hipStream_t s)
 {
     if (m.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_combine, dim3((m.n + 255) / 256), dim3(256), 0, s, m.n, m.npad, node_orig, part, splits,
-                       band, rtv, vel, nonfinite);
+    hipLaunchKernelGGL(k_combine, dim3((m.n + 255) / 256), dim3(256), 0, s, m.n, m.blk0 * kBlockNodes, m.npad,
+                       node_orig, part, splits, band, rtv, vel, nonfinite);
     return hipGetLastError();
 }
 

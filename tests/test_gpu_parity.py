@@ -349,3 +349,37 @@ def test_pure_ray_tracing_convergence():
     _say(f"fitted order {p:.2f} (the paper's fit: {paper_p})")
     assert 1.5 < p < 2.8
     assert abs(p - paper_p) < 0.7
+
+
+@pytest.mark.parametrize("kind", ["fixed", "pure_rt"])
+def test_off_node_points(kind):
+    """Velocities at points that are not mesh nodes (Section 3.1 evaluates
+    there): seeded points inside the mesh (inside tets), near nodes, and
+    outside the mesh.  The oracle takes them as extra nodes that no tet has
+    as a vertex.  The nodes' own evaluation is unchanged by the points."""
+    m = W.make_config("C1")
+    rng = np.random.default_rng(7)
+    inside = rng.uniform(-0.97, 0.97, size=(150, 3))
+    near = m.xyz[rng.choice(m.n_nodes, 20, replace=False)] + rng.normal(scale=1e-3, size=(20, 3))
+    outside = rng.uniform(-1.0, 1.0, size=(30, 3))
+    outside[:, 0] = np.sign(rng.uniform(-1, 1, 30)) * rng.uniform(1.05, 1.6, 30)
+    pts = np.concatenate([inside, near, outside])
+    pol = dict(kind=bs.BS_POLICY_FIXED) if kind == "fixed" else dict(kind=bs.BS_POLICY_PURE_RT)
+    _say(f"off-node points, {kind}: {len(pts)} points")
+    h = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
+    bs.bs_set_policy(h, **pol)
+    v_nodes = bs.bs_eval_velocity(h)
+    vp, st = bs.bs_eval_points(h, pts, stats=True)
+    v_nodes2 = bs.bs_eval_velocity(h)
+    empty = bs.bs_eval_points(h, np.zeros((0, 3)))
+    bs.bs_mesh_free(h)
+    assert st["pairs"] == len(pts) * m.n_tets
+    assert empty.shape == (0, 3)
+    assert np.allclose(v_nodes2, v_nodes, rtol=0, atol=1e-14 * np.abs(v_nodes).max())
+    xyz = np.concatenate([m.xyz, pts])
+    om = np.concatenate([m.omega, np.zeros_like(pts)])
+    tg = np.arange(m.n_nodes, m.n_nodes + len(pts))
+    ref = oracle.evaluate(xyz, om, m.tets, oracle.make_policy(kind), targets=tg)
+    e = rel_l2(vp, ref)
+    _say(f"  rel-L2 {e:.3e}")
+    assert e <= TOL
