@@ -147,7 +147,7 @@ def _sample_nodes(m, k, seed):
     return np.unique(np.concatenate([corners, inner]))
 
 
-@pytest.mark.parametrize("name", ["C2", "C3"])
+@pytest.mark.parametrize("name", ["C2", "C3", "C5"])
 def test_full_size_sampled(name):
     """Full workload on the GPU in the configuration the benchmark times;
     the oracle evaluates a seeded sample of nodes one by one."""
@@ -163,24 +163,31 @@ def test_full_size_sampled(name):
 
 
 def test_precision_modes_c3_sampled():
-    """Precision sweep on the 48^3 Fourier-curl workload: naive FP32
-    accumulation over ~6.6e5 terms per node drifts past 1e-6; the TwoSum
-    tiles and FP64 accumulation stay within it.  Errors are reported per
-    result (whole-sample rel-L2 and worst node)."""
+    """Precision sweep on the 48^3 Fourier-curl workload, for both far-field
+    kernels; errors reported per result (whole-sample rel-L2, worst node).
+    Compensated and FP64 accumulation stay within 1e-6.  Naive accumulation
+    is one FP32 sum per node and tet split on the vector ALUs (past 1e-6
+    there); the matrix-core kernel adds FP32 sums of its eight splits in
+    FP64 even then."""
     m = W.make_config("C3")
     tg = _sample_nodes(m, 24, seed=3)
     ref = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("fixed"), targets=tg)
-    errs = {}
-    for prec in (bs.BS_PREC_FP32_NAIVE, bs.BS_PREC_FP32_COMP, bs.BS_PREC_FP64):
-        v, st = gpu_eval(m, precision=prec)
-        err = rel_l2(v[tg], ref)
-        per = np.linalg.norm(v[tg] - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-300)
-        _say(f"C3 precision {prec}: rel-L2 {err:.3e}, max per-node {per.max():.3e}, "
-             f"t_eval {st['t_eval_s']*1e3:.1f} ms")
-        errs[prec] = err
-    assert errs[bs.BS_PREC_FP32_COMP] <= TOL and errs[bs.BS_PREC_FP64] <= TOL
-    assert errs[bs.BS_PREC_FP32_NAIVE] <= 1e-4
-    assert errs[bs.BS_PREC_FP32_NAIVE] > errs[bs.BS_PREC_FP32_COMP]
+    h = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
+    for valu in (False, True):
+        errs = {}
+        for prec in (bs.BS_PREC_FP32_NAIVE, bs.BS_PREC_FP32_COMP, bs.BS_PREC_FP64):
+            bs.bs_set_policy(h, kind=bs.BS_POLICY_FIXED, precision=prec)
+            v, st = bs.bs_eval_velocity(h, stats=True, valu_far=valu)
+            err = rel_l2(v[tg], ref)
+            per = np.linalg.norm(v[tg] - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-300)
+            _say(f"C3 precision {prec}, {'vector ALUs' if valu else 'matrix cores'}: rel-L2 {err:.3e}, "
+                 f"max per-node {per.max():.3e}, t_eval {st['t_eval_s']*1e3:.1f} ms")
+            errs[prec] = err
+        assert errs[bs.BS_PREC_FP32_COMP] <= TOL and errs[bs.BS_PREC_FP64] <= TOL
+        assert errs[bs.BS_PREC_FP32_NAIVE] <= 1e-4
+        if valu:
+            assert errs[bs.BS_PREC_FP32_NAIVE] > errs[bs.BS_PREC_FP32_COMP]
+    bs.bs_mesh_free(h)
 
 
 # ------------------------------------------------------------------ edges
