@@ -216,7 +216,7 @@ struct bs_mesh {
     bool convex = false;          // boundary is one closed, locally convex surface (rays never re-enter)
     bsk::Bins bins{};
     // device buffers
-    DBuf xh, xl, om, blk, node_orig, g1, g4, g11, tid, cell_start, nbr, inc_start, inc_list;
+    DBuf xh, xl, om, nrec, blk, node_orig, g1, g4, g11, tid, cell_start, nbr, inc_start, inc_list;
     DBuf part, band, rtv, vel, cnt, nonfinite, fallback;
     // evaluation points (bs_eval_points): FP64 copy, count, first node index
     // and first block in the node arrays, their order and output
@@ -555,6 +555,12 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
             om[(size_t)c * npad + p] = (is_t || n == 0) ? 0.f : (float)W[3 * i + c];
         }
     }
+    std::vector<float4> nrec((size_t)2 * npad);
+    for (int64_t p = 0; p < npad; ++p) {
+        const size_t i0 = (size_t)p, i1 = (size_t)(npad + p), i2 = (size_t)(2 * npad + p);
+        nrec[(size_t)(2 * p)] = make_float4(xh[i0], xh[i1], xh[i2], xl[i0]);
+        nrec[(size_t)(2 * p + 1)] = make_float4(xl[i1], xl[i2], om[i0], om[i1]);
+    }
     std::vector<float4> blk((size_t)std::max(nblk, tblk0 + tnblk));
     block_spheres(xh, npad, 0, n, blk.data());
     if (tn > 0) block_spheres(xh, npad, t0, tn, blk.data() + tblk0);
@@ -710,6 +716,7 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
     int rc;
     const size_t nb = sizeof(float) * 3 * (size_t)npad;
     if ((rc = dalloc(m->xh, nb)) || (rc = dalloc(m->xl, nb)) || (rc = dalloc(m->om, nb)) ||
+        (rc = dalloc(m->nrec, sizeof(float4) * nrec.size())) ||
         (rc = dalloc(m->blk, sizeof(float4) * blk.size())) || (rc = dalloc(m->node_orig, 4 * (size_t)n)) ||
         (rc = dalloc(m->torig, 4 * torig.size())) || (rc = dalloc(m->tlist, 4 * tlist.size())) ||
         (rc = dalloc(m->tvel, 8 * 3 * (size_t)tn)) ||
@@ -730,6 +737,7 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
     BS_UP(xh, xh)
     BS_UP(xl, xl)
     BS_UP(om, om)
+    BS_UP(nrec, nrec)
     BS_UP(blk, blk)
     BS_UP(node_orig, orig)
     BS_UP(torig, torig)
@@ -825,6 +833,7 @@ bsk::DevMesh dev_view(const bs_mesh *m)
     d.xh = (const float *)m->xh.p;
     d.xl = (const float *)m->xl.p;
     d.om = (const float *)m->om.p;
+    d.nrec = (const float4 *)m->nrec.p;
     d.blk = (const float4 *)m->blk.p;
     d.g1 = (const float *)m->g1.p;
     d.g4 = (const float *)m->g4.p;
@@ -1045,7 +1054,7 @@ int bs_mesh_update(bs_mesh *m, const double *xyz, const double *omega, uint32_t 
 void bs_mesh_free(bs_mesh *m)
 {
     if (!m) return;
-    DBuf *bufs[] = {&m->xh, &m->xl, &m->om, &m->blk, &m->node_orig, &m->g1, &m->g4, &m->g11, &m->tid,
+    DBuf *bufs[] = {&m->xh, &m->xl, &m->om, &m->nrec, &m->blk, &m->node_orig, &m->g1, &m->g4, &m->g11, &m->tid,
                     &m->nbr, &m->inc_start, &m->inc_list, &m->fallback,
                     &m->cell_start, &m->part, &m->band, &m->rtv, &m->vel, &m->cnt, &m->nonfinite, &m->dir,
                     &m->dir64, &m->cphi, &m->dia, &m->mlp, &m->sel, &m->torig, &m->tlist, &m->tvel};

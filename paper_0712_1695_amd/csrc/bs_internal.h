@@ -75,6 +75,7 @@ struct DevMesh {
     int n, npad, T, nblk;
     int blk0, nv;
     const float *xh, *xl, *om;
+    const float4 *nrec;    // [npad][2] node records (xh.x, xh.y, xh.z, xl.x), (xl.y, xl.z, om.x, om.y)
     const float4 *blk;
     const float *g1, *g4, *g11;
     const int4 *tid;

@@ -1384,20 +1384,30 @@ __global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang,
 // incident tet whose opposite face it crosses, then crosses face neighbours
 // outward: the exit face of one tet is the entry face of the next, decided
 // by the same shared edge values, so chords join exactly.  A tet adds its
-// chord when its pair with the node is ray traced (a sorted LDS list built
-// by the scan; every tet for the pure ray-tracing policy).  The walk stops
-// at the boundary or once the ray is farther than any listed tet reaches
-// (the largest centroid distance in the list plus the largest
-// vertex-centroid distance, at most r_stop = r_rt plus that distance; the
-// learned selector, which takes pairs off the list, shortens the walks).
-// Nodes whose lists exceed the LDS capacity are handed to k_rt.
-constexpr int kWalkCap = 1024; // ray-traced tets per node
+// chord when its pair with the node is ray traced: for the fixed rule the
+// rule's own test on the tet's centroid, for the learned selector a sorted
+// LDS list of the pairs it left ray traced, for the pure ray-tracing policy
+// every tet.  The walk stops at the boundary or once the ray is farther than
+// any ray-traced tet reaches (the largest centroid distance among them plus
+// the largest vertex-centroid distance, at most r_stop = r_rt plus that
+// distance; the learned selector, which takes pairs off, shortens the
+// walks).
+//
+// A step carries the entry face: its three nodes, their positions relative
+// to the node and vorticity, and its three edge values, which all have the
+// sign s of the crossing.  The tet across has one more node V (the XOR of
+// its four node ids and the face's three), so a step loads one node record
+// and forms the three edge values [d, V, P_k]; the exit face is (V, P_k,
+// P_k+1) for the one k with [d, V, P_k] of sign s and [d, V, P_k+1] of sign
+// -s (the faces through V share those edges, so no two qualify; none does
+// only when the ray meets V itself, and the ray ends there).
 constexpr int kIncCap = 48;    // incident tets per node (more: left to k_rt)
 constexpr int kMaxSteps = 1 << 13; // tets per ray: bounds a walk that stalls on a degenerate crossing
 
 struct WalkLds {
-    int list[kWalkCap];
+    int list[kSelListCap]; // learned policy: its ray-traced tets, sorted
     // incident tets: the three vertices of the face opposite the node
+    float ia[kIncCap][9];  // positions relative to the node
     float iw[kIncCap][9];  // vorticity
     float in[kIncCap][9];  // canonical normals of the edges pq, qr, pr
     int iid[kIncCap][3];   // node ids of p, q, r
@@ -1439,15 +1449,11 @@ __device__ __forceinline__ bool in_sorted(const int *a, int n, int v)
     return lo < n && a[lo] == v;
 }
 
-// Append ray-traced tets to the walk list (entries past the capacity are
-// counted, not stored) and track the farthest centroid.
-__device__ __forceinline__ void walk_list_add(const DevMesh &m, int *list, int &n, bool take, int t, int lane,
-                                              const float *xhv, float &dmax)
+// Count the ray-traced tets the wave found and track the farthest centroid.
+__device__ __forceinline__ void walk_reach_add(const DevMesh &m, int &n, bool take, int t, const float *xhv,
+                                               float &dmax)
 {
-    const unsigned long long mk = __ballot(take);
-    const int pos = n + __popcll(mk & ((1ull << lane) - 1ull));
-    if (take && pos < kWalkCap) list[pos] = t;
-    n += __popcll(mk);
+    n += __popcll(__ballot(take));
     if (take) {
         const float *g = m.g1 + (size_t)t * kRecG;
         const float dx = xhv[0] - g[0], dy = xhv[1] - g[1], dz = xhv[2] - g[2];
@@ -1600,8 +1606,8 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
     A.pairs = A.hits = 0;
     A.retests = 0;
 
-    // ---- A. ray-traced tets of the node (not needed when every pair is);
-    // the walk stops past the farthest of them
+    // ---- A. ray-traced tets of the node (not needed when every pair is):
+    // their count and the farthest centroid; the learned policy's list
     int nlist = 0;
     float stop = r_stop;
     if (!all_pairs) {
@@ -1614,6 +1620,25 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
             }
             for (int k = lane; k < nlist; k += 64) W.list[k] = sel_list[(size_t)self * kSelCap + k];
             dmax = sel_dmax[self];
+            // sort the list (bitonic, padded with INT_MAX)
+            int np2 = 1;
+            while (np2 < nlist) np2 <<= 1;
+            for (int k = nlist + lane; k < np2; k += 64) W.list[k] = 0x7fffffff;
+            __syncthreads();
+            for (int size = 2; size <= np2; size <<= 1)
+                for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                    for (int k = lane; k < np2 / 2; k += 64) {
+                        const int i = 2 * k - (k & (stride - 1));
+                        const int j = i + stride;
+                        const bool up = (i & size) == 0;
+                        const int a = W.list[i], b = W.list[j];
+                        if ((a > b) == up) {
+                            W.list[i] = b;
+                            W.list[j] = a;
+                        }
+                    }
+                    __syncthreads();
+                }
         } else {
             RowIter rows(m, xhv[0], xhv[1], xhv[2], th.r_rt);
             int t0, t1;
@@ -1626,35 +1651,12 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
                         const float *g = m.g1 + (size_t)t * kRecG;
                         is_rt = fixed_rule(xhv[0], xhv[1], xhv[2], g[0], g[1], g[2], id, self, th) == RULE_RT;
                     }
-                    walk_list_add(m, W.list, nlist, is_rt, t, lane, xhv, dmax);
+                    walk_reach_add(m, nlist, is_rt, t, xhv, dmax);
                 }
             }
             for (int o = 32; o > 0; o >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, o, 64));
         }
         stop = fminf(r_stop, (dmax + th.vc) * (1.f + 1e-4f) + 1e-6f);
-        if (nlist > kWalkCap) {
-            if (lane == 0) fallback[atomicAdd(n_fallback, 1)] = self;
-            return;
-        }
-        // sort the list (bitonic, padded with INT_MAX)
-        int np2 = 1;
-        while (np2 < nlist) np2 <<= 1;
-        for (int k = nlist + lane; k < np2; k += 64) W.list[k] = 0x7fffffff;
-        __syncthreads();
-        for (int size = 2; size <= np2; size <<= 1)
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int k = lane; k < np2 / 2; k += 64) {
-                    const int i = 2 * k - (k & (stride - 1));
-                    const int j = i + stride;
-                    const bool up = (i & size) == 0;
-                    const int a = W.list[i], b = W.list[j];
-                    if ((a > b) == up) {
-                        W.list[i] = b;
-                        W.list[j] = a;
-                    }
-                }
-                __syncthreads();
-            }
     }
 
     // ---- B. incident tets: the face opposite the node, its neighbour
@@ -1688,6 +1690,7 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 a[q][c] = (m.xh[c * m.npad + nid] - xhv[c]) + (m.xl[c * m.npad + nid] - xlv[c]);
+                W.ia[lane][3 * q + c] = a[q][c];
                 W.iw[lane][3 * q + c] = m.om[c * m.npad + nid];
             }
         }
@@ -1743,8 +1746,8 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
         const double *d64 = ang.dir64 + 3 * (size_t)l;
         // start: the incident tet whose opposite face the ray crosses (tets
         // whose cone no ray of the wave enters are skipped)
-        int start = -1;
-        float rho = 0.f, w_in[3] = {0.f, 0.f, 0.f};
+        int start = -1, sg = 1;
+        float rho = 0.f, w_in[3] = {0.f, 0.f, 0.f}, cf[3] = {0.f, 0.f, 0.f};
         for (int i = 0; i < ninc; ++i) {
             if (!__ballot(valid && start < 0)) break;
             const float4 cone = W.icone[i];
@@ -1782,6 +1785,10 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
                 w_in[c] = fmaf(lp_, W.iw[i][c], fmaf(lq, W.iw[i][3 + c], lr * W.iw[i][6 + c]));
             rho = r;
             start = i;
+            cf[0] = E1;
+            cf[1] = E2;
+            cf[2] = E3;
+            sg = se[0];
         }
         if (!valid || start < 0) continue;
         {
@@ -1791,76 +1798,100 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
                           h * fmaf(d.x, sy, -(d.y * sx)));
             ++A.hits;
         }
+        // the entry face (P0, P1, P2) and its values [d,P0,P1], [d,P1,P2],
+        // [d,P2,P0] (all of sign sg)
         int T = W.inb[start];
-        int ent[3] = {W.iid[start][0], W.iid[start][1], W.iid[start][2]};
+        int e[3];
+        float P[3][3], Wv[3][3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            e[q] = W.iid[start][q];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                P[q][c] = W.ia[start][3 * q + c];
+                Wv[q][c] = W.iw[start][3 * q + c];
+            }
+        }
         int steps = 0;
         while (T >= 0 && rho < stop && steps < kMaxSteps) {
             ++steps;
             const int4 id4 = m.tid[T];
-            const int id[4] = {id4.x, id4.y, id4.z, id4.w};
-            int fin = 0;
+            const int4 nb4 = m.nbr[T];
+            float4 cen = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (!LISTED && !all_pairs) cen = *reinterpret_cast<const float4 *>(m.g1 + (size_t)T * kRecG);
+            // the node of T off the entry face
+            const int v = (id4.x ^ id4.y ^ id4.z ^ id4.w) ^ (e[0] ^ e[1] ^ e[2]);
+            const float4 r0 = m.nrec[2 * v], r1 = m.nrec[2 * v + 1];
+            const float wz = m.om[2 * m.npad + v];
+            const float av[3] = {(r0.x - xhv[0]) + (r0.w - xlv[0]), (r0.y - xhv[1]) + (r1.x - xlv[1]),
+                                 (r0.z - xhv[2]) + (r1.y - xlv[2])};
+            const float wv[3] = {r1.z, r1.w, wz};
+            float cv[3];
+            int sv[3];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (id[j] != ent[0] && id[j] != ent[1] && id[j] != ent[2]) fin = j;
-            float a[4][3], w[4][3];
+            for (int k = 0; k < 3; ++k) cv[k] = edge_val(d, av, v, P[k], e[k], m, d64, xhv, xlv, sv[k], A.retests);
+            const bool x0 = sv[0] == sg && sv[1] != sg;
+            const bool x1 = sv[1] == sg && sv[2] != sg;
+            const bool x2 = sv[2] == sg && sv[0] != sg;
+            if (!(x0 || x1 || x2)) break; // the ray meets V: end it here
+            // exit face (V, A, B) = (V, P_k, P_k+1); O = P_k+2 is the node of T off it
+            float pa[3], pb[3], wa[3], wb[3];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    a[j][c] = (m.xh[c * m.npad + id[j]] - xhv[c]) + (m.xl[c * m.npad + id[j]] - xlv[c]);
-                    w[j][c] = m.om[c * m.npad + id[j]];
-                }
-            float ce[6];
-            int se[6];
-#pragma unroll
-            for (int e = 0; e < 6; ++e) {
-                constexpr int ea[6] = {0, 0, 0, 1, 1, 2}, eb[6] = {1, 2, 3, 2, 3, 3};
-                ce[e] = edge_val(d, a[ea[e]], id[ea[e]], a[eb[e]], id[eb[e]], m, d64, xhv, xlv, se[e], A.retests);
+            for (int c = 0; c < 3; ++c) {
+                pa[c] = x0 ? P[0][c] : (x1 ? P[1][c] : P[2][c]);
+                pb[c] = x0 ? P[1][c] : (x1 ? P[2][c] : P[0][c]);
+                wa[c] = x0 ? Wv[0][c] : (x1 ? Wv[1][c] : Wv[2][c]);
+                wb[c] = x0 ? Wv[1][c] : (x1 ? Wv[2][c] : Wv[0][c]);
             }
-            // exit: the crossed face other than the entry face, farthest along the ray
-            int fout = -1;
-            float rout = 0.f, wout[3] = {0.f, 0.f, 0.f};
+            const int ea = x0 ? e[0] : (x1 ? e[1] : e[2]);
+            const int eb = x0 ? e[1] : (x1 ? e[2] : e[0]);
+            const int eo = x0 ? e[2] : (x1 ? e[0] : e[1]);
+            const float cVA = x0 ? cv[0] : (x1 ? cv[1] : cv[2]);
+            const float cAB = x0 ? cf[0] : (x1 ? cf[1] : cf[2]);
+            const float cBV = -(x0 ? cv[1] : (x1 ? cv[2] : cv[0]));
+            const float Sm = (cVA + cAB) + cBV;
+            float N[3];
+            cross_canon(pa, pb, N);
+            const float vol = fmaf(av[0], N[0], fmaf(av[1], N[1], av[2] * N[2]));
+            const float inv = __builtin_amdgcn_rcpf(Sm);
+            const float rout = vol * inv;
+            if (!(rout < 3.0e38f) || !(rout > -3.0e38f)) break; // degenerate face: end the ray
+            const float lv = cAB * inv, la = cBV * inv, lb = cVA * inv;
+            float wout[3];
 #pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                if (f == fin) continue;
-                const int pp = f == 0 ? 1 : 0, qq = f <= 1 ? 2 : 1, rr = f <= 2 ? 3 : 2;
-                const int epq = pp == 0 ? qq - 1 : (pp == 1 ? qq + 1 : 5);
-                const int eqr = qq == 1 ? rr + 1 : 5;
-                const int epr = pp == 0 ? rr - 1 : (pp == 1 ? rr + 1 : 5);
-                const int s1 = se[epq], s2 = se[eqr], s3 = -se[epr];
-                if (s1 != s2 || s2 != s3) continue;
-                const float E1 = ce[epq], E2 = ce[eqr], E3 = -ce[epr];
-                const float Sm = (E1 + E2) + E3;
-                float N[3];
-                cross_canon(a[qq], a[rr], N);
-                const float vol = fmaf(a[pp][0], N[0], fmaf(a[pp][1], N[1], a[pp][2] * N[2]));
-                const float r = vol / Sm;
-                if (!(r < 3.0e38f) || !(r > -3.0e38f) || (fout >= 0 && r <= rout)) continue;
-                const float lp_ = E2 / Sm, lq = E3 / Sm, lr = E1 / Sm;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) wout[c] = fmaf(lp_, w[pp][c], fmaf(lq, w[qq][c], lr * w[rr][c]));
-                rout = r;
-                fout = f;
-            }
-            if (fout < 0) break; // no exit found (degenerate): end the ray here
+            for (int c = 0; c < 3; ++c) wout[c] = fmaf(lv, wv[c], fmaf(la, wa[c], lb * wb[c]));
             const float r_out = fmaxf(rout, rho);
-            if (all_pairs || in_sorted(W.list, nlist, T)) {
+            bool take = true;
+            if (!all_pairs) {
+                if constexpr (LISTED) take = in_sorted(W.list, nlist, T);
+                else take = fixed_rule(xhv[0], xhv[1], xhv[2], cen.x, cen.y, cen.z, id4, self, th) == RULE_RT;
+            }
+            if (take) {
                 const float h = 0.5f * d.w * (r_out - rho);
                 const float sx = w_in[0] + wout[0], sy = w_in[1] + wout[1], sz = w_in[2] + wout[2];
                 acc_add<PREC>(A, h * fmaf(d.y, sz, -(d.z * sy)), h * fmaf(d.z, sx, -(d.x * sz)),
                               h * fmaf(d.x, sy, -(d.y * sx)));
                 ++A.hits;
             }
-            const int4 nb4 = m.nbr[T];
-            const int nb[4] = {nb4.x, nb4.y, nb4.z, nb4.w};
-            int k = 0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (j != fout) ent[k++] = id[j];
-            T = nb[fout];
+            // across the exit face: the face of T opposite O
+            T = id4.x == eo ? nb4.x : (id4.y == eo ? nb4.y : (id4.z == eo ? nb4.z : nb4.w));
             rho = r_out;
+            e[0] = v;
+            e[1] = ea;
+            e[2] = eb;
+            cf[0] = cVA;
+            cf[1] = cAB;
+            cf[2] = cBV;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) w_in[c] = wout[c];
+            for (int c = 0; c < 3; ++c) {
+                P[0][c] = av[c];
+                P[1][c] = pa[c];
+                P[2][c] = pb[c];
+                Wv[0][c] = wv[c];
+                Wv[1][c] = wa[c];
+                Wv[2][c] = wb[c];
+                w_in[c] = wout[c];
+            }
         }
     }
     A.pairs = all_pairs ? (unsigned long long)m.T : (unsigned long long)nlist;
