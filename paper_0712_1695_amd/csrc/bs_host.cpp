@@ -206,6 +206,7 @@ struct bs_mesh {
     std::vector<int32_t> tets;     // input connectivity
     std::vector<double> xyz, omega; // current FP64 inputs
     double hbar = 0.0, max_vc = 0.0;
+    double max_abs = 0.0; // largest coordinate magnitude of any node or evaluation point
     int64_t reoriented = 0;
     std::vector<int8_t> orient; // sign of det per tet at upload (inversion check on updates)
     std::vector<int32_t> h_rank, h_order, h_cell_start; // node rank, tet order, bins (host copies)
@@ -544,12 +545,14 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
     m->tblk0 = tblk0;
     m->tnblk = tnblk;
     std::vector<float> xh((size_t)3 * npad), xl((size_t)3 * npad), om((size_t)3 * npad);
+    double max_abs = 0.0;
     for (int64_t p = 0; p < npad; ++p) {
         const bool is_t = p >= t0 && p < t0 + tn;
         const int64_t i = p < n ? orig[(size_t)p] : is_t ? torig[(size_t)(p - t0)] : (n > 0 ? orig[0] : 0);
         for (int c = 0; c < 3; ++c) {
             const double x = is_t ? m->tgt[3 * i + c] : (n > 0 ? X[3 * i + c] : 0.0);
             const float h = (float)x;
+            max_abs = std::max(max_abs, std::fabs(x));
             xh[(size_t)c * npad + p] = h;
             xl[(size_t)c * npad + p] = (float)(x - (double)h);
             om[(size_t)c * npad + p] = (is_t || n == 0) ? 0.f : (float)W[3 * i + c];
@@ -595,6 +598,7 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
         max_vc = std::max(max_vc, std::sqrt(vc));
     }
     m->max_vc = max_vc;
+    m->max_abs = max_abs;
     bsk::Bins bins{};
     double cs = 2.0 * (m->hbar > 0 ? m->hbar : 1.0);
     if (T > 0) {
@@ -1132,6 +1136,19 @@ int eval_device(bs_mesh *m, hipStream_t s, bool targets)
     th.r_rt = (float)(std::max(c_rt, m->max_vc) * (1.0 + 1e-4) + 1e-6);
     th.vc = (float)(m->max_vc * (1.0 + 1e-4) + 1e-6);
     th.inc_far = m->max_vc < c_4 * (1.0 - 1e-5) ? 0 : 1;
+    // relative margin on d^2 around the G4 cut: the rule's binary32 d^2 and
+    // the far kernel's block-relative matrix-core d^2 differ by a few units
+    // in the last place of the coordinates' magnitude relative to the cut
+    {
+        const double eps = 2e-4 + 256.0 * std::ldexp(1.0, -24) * (m->max_abs / std::max(c_4, 1e-300));
+        if (c_4 > 0.0 && eps < 0.5) {
+            th.s_g1 = (float)std::pow(c_4 * c_4 * (1.0 + eps), -1.5);
+            th.s_amb = (float)std::pow(c_4 * c_4 * (1.0 - eps), -1.5);
+        } else { // every band pair takes the rule's test
+            th.s_g1 = 0.f;
+            th.s_amb = INFINITY;
+        }
+    }
     bsk::AngTab ang{};
     ang.dir = (const float4 *)m->dir.p;
     ang.dir64 = (const double *)m->dir64.p;

@@ -314,7 +314,7 @@ struct FarLds {
             float a2[2][16][4][4][8];         // [buf][tile][c][q][2j + h]: component 4h + c of [W, W x p'] of tet 4q + j
             float4 pc[2][kFarChunk];          // binary32 centroid (the rule's) of each tet of the chunk
             int4 ids[2][kFarChunk];           // vertex ids (sorted numbering)
-            unsigned long long band[2][4][4]; // [buf][64 tets][node tile]: bit = centroid within the band
+            unsigned long long band[2][16];   // [buf][tile]: bit 16 nt + i = centroid of tet i within the band of node tile nt
         } c;
         double red[4][4][6][16];              // [wave][node tile][component][node]
     };
@@ -434,27 +434,44 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
             for (int h = 0; h < 2; ++h) S.c.a2[buf][tile][c][qq][2 * j + h] = comp[4 * h + c];
         S.c.pc[buf][tid] = make_float4(pr[0], pr[1], pr[2], 0.f);
         S.c.ids[buf][tid] = pok ? pid : make_int4(-1, -1, -1, -1);
+        unsigned long long bal[4];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
             const float dx = pr[0] - nts[nt].x, dy = pr[1] - nts[nt].y, dz = pr[2] - nts[nt].z;
-            const unsigned long long bal = __ballot(pok && (dx * dx + dy * dy) + dz * dz < rb2[nt]);
-            if (lane == 0) S.c.band[buf][wave][nt] = bal;
+            bal[nt] = __ballot(pok && (dx * dx + dy * dy) + dz * dz < rb2[nt]);
+        }
+        // the wave's 64 tets are tiles 4 wave + tl
+#pragma unroll
+        for (int tl = 0; tl < 4; ++tl) {
+            unsigned long long pk = 0;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) pk |= ((bal[nt] >> (16 * tl)) & 0xffffull) << (16 * nt);
+            if (lane == 0) S.c.band[buf][4 * wave + tl] = pk;
         }
     };
     // sum the four tet streams of every node (lanes l, l^16, l^32, l^48) in
-    // FP32 and add node tile q's six sums into acc in FP64
+    // FP32, leaving node tile q's six sums in lane group q (a reduce-scatter
+    // by lane swaps: lanes 0-31 keep node tiles 0, 1 and lanes 32-63 tiles
+    // 2, 3, then even and odd groups split those), and add them into acc in FP64
     auto fold = [&]() {
+        float y[2][6];
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int r = 0; r < 6; ++r) {
-                float v = r < 4 ? D0[nt][r] : D1[nt][r - 4];
-                v += __shfl_xor(v, 16, 64);
-                v += __shfl_xor(v, 32, 64);
-                if (q == nt) acc[r] += (double)v;
+                const float lo = r < 4 ? D0[h][r] : D1[h][r - 4];
+                const float hi = r < 4 ? D0[h + 2][r] : D1[h + 2][r - 4];
+                const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+                y[h][r] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
             }
-            D0[nt] = D1[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            const auto sw =
+                __builtin_amdgcn_permlane16_swap(__float_as_uint(y[0][r]), __float_as_uint(y[1][r]), false, false);
+            acc[r] += (double)(__uint_as_float(sw[0]) + __uint_as_float(sw[1]));
         }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) D0[nt] = D1[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
     };
 
     if (t0 < t1) {
@@ -473,12 +490,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 #pragma unroll 1
         for (int u = 0; u < 4; ++u) {
             const int tile = wave + 4 * u;
-            unsigned bmask[4];
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const unsigned long long bw = S.c.band[buf][tile >> 2][nt];
-                bmask[nt] = __builtin_amdgcn_readfirstlane((unsigned)(bw >> (16 * (tile & 3))) & 0xffffu);
-            }
+            const unsigned long long bw = S.c.band[buf][tile];
+            const unsigned blo = __builtin_amdgcn_readfirstlane((unsigned)bw);
+            const unsigned bhi = __builtin_amdgcn_readfirstlane((unsigned)(bw >> 32));
+            const unsigned bmask[4] = {blo & 0xffffu, blo >> 16, bhi & 0xffffu, bhi >> 16};
             const float A1 = S.c.a1[buf][tile][lane];
             const float4 v0 = *(const float4 *)&S.c.a2[buf][tile][c4][q][0];
             const float4 v1 = *(const float4 *)&S.c.a2[buf][tile][c4][q][4];
@@ -499,21 +514,33 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
                 if (!bmask[nt]) continue;
-                const float4 xn = S.xn[16 * nt + i16];
-                const int self = b * kBlockNodes + 16 * nt + i16;
+                // the matrix-core distance decides the pairs clear of the G4
+                // cut; a wave with a pair near it (or with incidence to test)
+                // takes the rule's own test for all its pairs
+                bool g1[4], amb = false;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const int e = tile * 16 + 4 * q + j;
-                    const float4 pc = S.c.pc[buf][e];
-                    const float dx = xn.x - pc.x, dy = xn.y - pc.y, dz = xn.z - pc.z;
-                    const float sx = dx * dx, sy = dy * dy, sz = dz * dz;
-                    bool g1 = !((sx + sy) + sz < th.g4_2);
-                    if (th.inc_far) {
-                        const int4 id = S.c.ids[buf][e];
-                        g1 = g1 && !((id.x == self) | (id.y == self) | (id.z == self) | (id.w == self));
-                    }
-                    sv[nt][j] = g1 ? sv[nt][j] : 0.f;
+                    g1[j] = sv[nt][j] < th.s_g1;
+                    amb = amb || (!g1[j] && !(sv[nt][j] > th.s_amb));
                 }
+                if (th.inc_far || __ballot(amb)) {
+                    const float4 xn = S.xn[16 * nt + i16];
+                    const int self = b * kBlockNodes + 16 * nt + i16;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int e = tile * 16 + 4 * q + j;
+                        const float4 pc = S.c.pc[buf][e];
+                        const float dx = xn.x - pc.x, dy = xn.y - pc.y, dz = xn.z - pc.z;
+                        const float sx = dx * dx, sy = dy * dy, sz = dz * dz;
+                        g1[j] = !((sx + sy) + sz < th.g4_2);
+                        if (th.inc_far) {
+                            const int4 id = S.c.ids[buf][e];
+                            g1[j] = g1[j] && !((id.x == self) | (id.y == self) | (id.z == self) | (id.w == self));
+                        }
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) sv[nt][j] = g1[j] ? sv[nt][j] : 0.f;
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j)
