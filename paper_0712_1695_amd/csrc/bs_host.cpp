@@ -1136,6 +1136,9 @@ int eval_device(bs_mesh *m, hipStream_t s, bool targets)
     th.r_rt = (float)(std::max(c_rt, m->max_vc) * (1.0 + 1e-4) + 1e-6);
     th.vc = (float)(m->max_vc * (1.0 + 1e-4) + 1e-6);
     th.inc_far = m->max_vc < c_4 * (1.0 - 1e-5) ? 0 : 1;
+    // the rule's binary32 distance of an incident pair exceeds max_vc by at
+    // most the rounding of the coordinates and the centroid
+    th.inc_band = (m->max_vc + 16.0 * std::ldexp(1.0, -24) * m->max_abs) * (1.0 + 1e-5) < c_rt ? 0 : 1;
     // relative margin on d^2 around the G4 cut: the rule's binary32 d^2 and
     // the far kernel's block-relative matrix-core d^2 differ by a few units
     // in the last place of the coordinates' magnitude relative to the cut

@@ -45,6 +45,7 @@ struct Thresholds {
     float r_rt;             // scan radius of the ray-tracing kernel
     float vc;               // largest vertex-centroid distance of any tet (with margin)
     int inc_far;            // 1 if a tet having the node as a vertex can lie beyond the G4 cut
+    int inc_band;           // 1 if it can lie beyond the ray-tracing cut (by the rule's binary32 d^2)
     // bounds on d^-3 from the matrix-core distance: below s_g1 the pair is
     // surely beyond the G4 cut by the rule's binary32 test, above s_amb surely
     // within it; between them (or NaN) the rule's test decides

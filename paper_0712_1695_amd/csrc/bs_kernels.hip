@@ -681,23 +681,32 @@ __global__ void __launch_bounds__(64 * kBandWaves) k_band(DevMesh m, Thresholds 
         float ax = 0.f, ay = 0.f, az = 0.f;
         for (int t = t0; t < t1; ++t) {
             const float *g = m.g1 + (size_t)t * kRecG;
-            const int4 id = m.tid[t];
-            const float gx = g[0], gy = g[1], gz = g[2];
-            const int rule = valid ? fixed_rule(x, y, z, gx, gy, gz, id, i, th) : RULE_G1;
-            if (SUB && rule != RULE_G1) {
+            // fixed_rule's comparisons on its own binary32 d^2; the incidence
+            // test only where an incident pair can lie beyond the ray-tracing cut
+            const float ex = x - g[0], ey = y - g[1], ez = z - g[2];
+            const float qx = ex * ex, qy = ey * ey, qz = ez * ez;
+            const float d2 = (qx + qy) + qz;
+            bool near = d2 < th.rt2;
+            if (th.inc_band) {
+                const int4 id = m.tid[t];
+                near = near || (id.x == i) | (id.y == i) | (id.z == i) | (id.w == i);
+            }
+            const bool in11 = valid && !near && d2 < th.g11_2;
+            const bool in4 = valid && !near && d2 < th.g4_2 && !(d2 < th.g11_2);
+            if (SUB && valid && (near || d2 < th.g4_2)) {
                 float a = 0.f, b = 0.f, c = 0.f;
                 gauss_point(x, y, z, g, a, b, c);
                 ax -= a;
                 ay -= b;
                 az -= c;
             }
-            if (rule == RULE_G4) {
+            if (in4) {
                 const float *g4 = m.g4 + (size_t)t * 4 * kRecG;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) gauss_point(x, y, z, g4 + q * kRecG, ax, ay, az);
                 ++n4;
             }
-            if (rule == RULE_G11) {
+            if (in11) {
                 const float *g11 = m.g11 + (size_t)t * 11 * kRecG;
 #pragma unroll
                 for (int q = 0; q < 11; ++q) gauss_point(x, y, z, g11 + q * kRecG, ax, ay, az);
