@@ -1226,10 +1226,12 @@ __device__ __forceinline__ int learned_batch(const DevMesh &m, const LearnParams
     const int id[4] = {id4.x, id4.y, id4.z, id4.w};
     float a[4][3];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            a[j][c] = (m.xh[c * m.npad + id[j]] - xhv[c]) + (m.xl[c * m.npad + id[j]] - xlv[c]);
+    for (int j = 0; j < 4; ++j) {
+        const float4 r0 = m.nrec[2 * id[j]], r1 = m.nrec[2 * id[j] + 1];
+        a[j][0] = (r0.x - xhv[0]) + (r0.w - xlv[0]);
+        a[j][1] = (r0.y - xhv[1]) + (r1.x - xlv[1]);
+        a[j][2] = (r0.z - xhv[2]) + (r1.y - xlv[2]);
+    }
     float f[16];
     pair_features(a, lp.hbar, false, f);
 #pragma unroll
@@ -1421,8 +1423,9 @@ __global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang,
 // outward: the exit face of one tet is the entry face of the next, decided
 // by the same shared edge values, so chords join exactly.  A tet adds its
 // chord when its pair with the node is ray traced: for the fixed rule the
-// rule's own test on the tet's centroid, for the learned selector a sorted
-// LDS list of the pairs it left ray traced, for the pure ray-tracing policy
+// rule's own test on the tet's centroid, for the learned selector that test
+// and then a sorted LDS list of the pairs it left ray traced (a subset of
+// the fixed rule's), for the pure ray-tracing policy
 // every tet.  The walk stops at the boundary or once the ray is farther than
 // any ray-traced tet reaches (the largest centroid distance among them plus
 // the largest vertex-centroid distance, at most r_stop = r_rt plus that
@@ -1854,7 +1857,7 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
             const int4 id4 = m.tid[T];
             const int4 nb4 = m.nbr[T];
             float4 cen = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (!LISTED && !all_pairs) cen = *reinterpret_cast<const float4 *>(m.g1 + (size_t)T * kRecG);
+            if (!all_pairs) cen = *reinterpret_cast<const float4 *>(m.g1 + (size_t)T * kRecG);
             // the node of T off the entry face
             const int v = (id4.x ^ id4.y ^ id4.z ^ id4.w) ^ (e[0] ^ e[1] ^ e[2]);
             const float4 r0 = m.nrec[2 * v], r1 = m.nrec[2 * v + 1];
@@ -1897,10 +1900,11 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
 #pragma unroll
             for (int c = 0; c < 3; ++c) wout[c] = fmaf(lv, wv[c], fmaf(la, wa[c], lb * wb[c]));
             const float r_out = fmaxf(rout, rho);
+            // the selector's list holds only pairs the fixed rule ray-traces
             bool take = true;
             if (!all_pairs) {
-                if constexpr (LISTED) take = in_sorted(W.list, nlist, T);
-                else take = fixed_rule(xhv[0], xhv[1], xhv[2], cen.x, cen.y, cen.z, id4, self, th) == RULE_RT;
+                take = fixed_rule(xhv[0], xhv[1], xhv[2], cen.x, cen.y, cen.z, id4, self, th) == RULE_RT;
+                if constexpr (LISTED) take = take && in_sorted(W.list, nlist, T);
             }
             if (take) {
                 const float h = 0.5f * d.w * (r_out - rho);

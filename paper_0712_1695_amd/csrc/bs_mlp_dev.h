@@ -24,13 +24,16 @@ __device__ __forceinline__ void sort4_desc(float &a, float &b, float &c, float &
 #undef BS_SWP
 }
 
-// a[4][3]: vertex positions relative to x; inc: incident flag.
+// a[4][3]: vertex positions relative to x; inc: incident flag.  Quotients
+// are products with hardware reciprocals and reciprocal square roots (one
+// unit in the last place).
 __device__ inline void pair_features(const float (&a)[4][3], float hbar, bool inc, float *f)
 {
     float c[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) c[k] = 0.25f * ((a[0][k] + a[1][k]) + (a[2][k] + a[3][k]));
-    const float d = sqrtf(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    const float d2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+    const float id = __builtin_amdgcn_rsqf(d2), d = d2 * id;
     float hmax2 = 0.f, hmin2 = 3e38f;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -41,7 +44,8 @@ __device__ inline void pair_features(const float (&a)[4][3], float hbar, bool in
             hmax2 = fmaxf(hmax2, l2);
             hmin2 = fminf(hmin2, l2);
         }
-    const float hT = sqrtf(hmax2), hmin = sqrtf(hmin2);
+    const float ihT = __builtin_amdgcn_rsqf(hmax2), hT = hmax2 * ihT;
+    const float ihmin = __builtin_amdgcn_rsqf(hmin2);
     // face volumes [a_p, a_q, a_r] (face f opposite vertex f, ascending p < q < r)
     float vol[4];
 #pragma unroll
@@ -53,9 +57,9 @@ __device__ inline void pair_features(const float (&a)[4][3], float hbar, bool in
         vol[f] = a[p][0] * nx + a[p][1] * ny + a[p][2] * nz;
     }
     const float D = (vol[0] - vol[1]) + (vol[2] - vol[3]); // signed 6V
-    const float lam[4] = {vol[0] / D, -vol[1] / D, vol[2] / D, -vol[3] / D};
-    const float s = hT / d;
-    float l0 = lam[0] * s, l1 = lam[1] * s, l2 = lam[2] * s, l3 = lam[3] * s;
+    const float iD = __builtin_amdgcn_rcpf(D);
+    const float s = hT * id;
+    float l0 = vol[0] * iD * s, l1 = -vol[1] * iD * s, l2 = vol[2] * iD * s, l3 = -vol[3] * iD * s;
     sort4_desc(l0, l1, l2, l3);
     // outward unit normals, cosines with -c/d, distances to the face planes
     float cs[4], dmin = 3e38f;
@@ -67,19 +71,19 @@ __device__ inline void pair_features(const float (&a)[4][3], float hbar, bool in
         float nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
         // orient away from the opposite vertex f
         const float o = nx * (a[f][0] - a[p][0]) + ny * (a[f][1] - a[p][1]) + nz * (a[f][2] - a[p][2]);
-        const float inv = (o > 0.f ? -1.f : 1.f) / sqrtf(nx * nx + ny * ny + nz * nz);
+        const float inv = (o > 0.f ? -1.f : 1.f) * __builtin_amdgcn_rsqf(nx * nx + ny * ny + nz * nz);
         nx *= inv;
         ny *= inv;
         nz *= inv;
-        cs[f] = -(nx * c[0] + ny * c[1] + nz * c[2]) / d;
+        cs[f] = -(nx * c[0] + ny * c[1] + nz * c[2]) * id;
         // plane through a_p; x is the origin
         dmin = fminf(dmin, fabsf(nx * a[p][0] + ny * a[p][1] + nz * a[p][2]));
     }
     sort4_desc(cs[0], cs[1], cs[2], cs[3]);
-    f[0] = d / hT;
-    f[1] = d / hbar;
-    f[2] = hT / hmin;
-    f[3] = hbar / d;
+    f[0] = d * ihT;
+    f[1] = d * __builtin_amdgcn_rcpf(hbar);
+    f[2] = hT * ihmin;
+    f[3] = hbar * id;
     f[4] = l0;
     f[5] = l1;
     f[6] = l2;
@@ -89,8 +93,8 @@ __device__ inline void pair_features(const float (&a)[4][3], float hbar, bool in
     f[10] = cs[2];
     f[11] = cs[3];
     f[12] = inc ? 1.f : 0.f;
-    f[13] = fabsf(D) / (hT * hT * hT);
-    f[14] = dmin / hT;
+    f[13] = fabsf(D) * (ihT * ihT * ihT);
+    f[14] = dmin * ihT;
     f[15] = 1.f;
 }
 
