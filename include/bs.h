@@ -63,6 +63,11 @@ extern "C" {
  * streams beside the far field (same results; per-kernel times then
  * measure each kernel alone). */
 #define BS_EVAL_SERIAL 0x20u
+/* bs_advect_heun only: advance the nodal vorticity too, by vortex
+ * stretching dw/dt = (w . grad) v with the nodal velocity gradient of
+ * bs_velocity_gradient (the paper's Lagrangian application, Sections 1 and
+ * 3; the stretching model is this library's, the paper does not give one). */
+#define BS_ADVECT_STRETCH 0x40u
 
 /* Rules a (node, tetrahedron) pair can be evaluated with. */
 #define BS_RULE_G1 0  /* 1-point Gauss rule (centroid), degree 1              */
@@ -191,18 +196,46 @@ int bs_eval_points(bs_mesh *m, int64_t n_pts, const double *pts, double *vel, ui
  * control points move with the flow and the velocity is re-evaluated every
  * step): `steps` Heun (RK2) steps of size dt,
  *     v1 = v(x); x* = x + dt v1; v2 = v(x*); x <- x + dt/2 (v1 + v2),
- * with the current policy, connectivity and nodal vorticity kept.  The
- * position updates are FP64 on the host; each stage re-runs the per-element
- * precompute and one evaluation.  The mesh ends at the new positions;
+ * with the current policy and connectivity kept.  The nodal vorticity is
+ * kept too, unless flags has BS_ADVECT_STRETCH: then it takes the same Heun
+ * steps with dw/dt = G w, G the nodal velocity gradient (bs_velocity_gradient)
+ * of each stage's velocities,
+ *     s1 = G(v1) w; w* = w + dt s1; s2 = G(v2) w*; w <- w + dt/2 (s1 + s2),
+ * and stage two is evaluated with w*.  The position and vorticity updates
+ * are FP64 on the host; each stage re-runs the per-element precompute and
+ * one evaluation.  The mesh ends at the new state (bs_mesh_read returns it);
  * xyz_out ([n_nodes][3], host or device per flags; may be NULL) receives
- * them; step_seconds (host, `steps` doubles; may be NULL) the wall time of
- * every step; st (may be NULL) the counters of the last evaluation, with
- * t_eval_s the summed device time of all evaluations.  Errors: BS_E_STATE
- * (NULL mesh), BS_E_ARG (steps < 0, non-finite dt), BS_E_DEGENERATE (a
- * tetrahedron flattens or inverts relative to its uploaded orientation;
- * the mesh is left at the start of that step), BS_E_DEVICE. */
+ * the positions; step_seconds (host, `steps` doubles; may be NULL) the wall
+ * time of every step; st (may be NULL) the counters of the last evaluation,
+ * with t_eval_s the summed device time of all evaluations.  Errors:
+ * BS_E_STATE (NULL mesh), BS_E_ARG (steps < 0, non-finite dt, unknown
+ * flag), BS_E_DEGENERATE (a tetrahedron flattens or inverts relative to its
+ * uploaded orientation), BS_E_NONFINITE (the vorticity overflows); on an
+ * error the mesh is left at the start of that step; BS_E_DEVICE. */
 int bs_advect_heun(bs_mesh *m, double dt, int steps, double *xyz_out, uint32_t flags, void *stream,
                    double *step_seconds, bs_stats *st);
+
+/* Nodal velocity gradient grad ([n_nodes][3][3] FP64, grad[i][a][b] =
+ * dv_a/dx_b at node i, input order) of the piecewise-linear interpolant of
+ * nodal velocities vel ([n_nodes][3] FP64), which the vortex-stretching
+ * term (w . grad) v of a Lagrangian vortex method needs (the application of
+ * Sections 1 and 3; the paper does not define a discretisation, this is the
+ * library's): on each tetrahedron the interpolant's constant gradient
+ * D E^-1 (E: edge vectors from vertex 0, D: the velocity differences along
+ * them), at each node the mean of the gradients of its tetrahedra weighted
+ * by their volumes (0 for a node of no tetrahedron).  vel = NULL takes the
+ * velocities of the last bs_eval_velocity (at the current positions and
+ * vorticity).  vel and grad are device memory when flags has BS_PTR_DEVICE,
+ * else host.  FP64 throughout, deterministic.  Errors: BS_E_STATE (NULL mesh;
+ * vel NULL with no current evaluation), BS_E_ARG (NULL grad, unknown flag),
+ * BS_E_NONFINITE (a host velocity), BS_E_DEVICE. */
+int bs_velocity_gradient(bs_mesh *m, const double *vel, double *grad, uint32_t flags, void *stream);
+
+/* The mesh's current FP64 node positions and nodal vorticity ([n_nodes][3]
+ * each, input order; either pointer may be NULL), e.g. after
+ * bs_advect_heun; device memory when flags has BS_PTR_DEVICE, else host.
+ * Errors: BS_E_STATE (NULL mesh), BS_E_ARG (unknown flag), BS_E_DEVICE. */
+int bs_mesh_read(bs_mesh *m, double *xyz, double *omega, uint32_t flags, void *stream);
 
 /* ------------------------------------------------------------ rule selector
  * A 16-64-64-4 network (ReLU, BF16 weights and activations, FP32

@@ -39,6 +39,7 @@ BS_PTR_HOST = 0
 BS_PTR_DEVICE = 1
 BS_EVAL_VALU_FAR = 0x10
 BS_EVAL_SERIAL = 0x20
+BS_ADVECT_STRETCH = 0x40
 
 BS_RULE_G1, BS_RULE_G4, BS_RULE_G11, BS_RULE_RT = 0, 1, 2, 3
 BS_POLICY_FIXED, BS_POLICY_PURE_RT, BS_POLICY_GAUSS_ONLY, BS_POLICY_LEARNED = 0, 1, 2, 3
@@ -95,7 +96,8 @@ class Stats(ctypes.Structure):
 
 # every symbol include/bs.h declares
 EXPORTS = ["bs_mesh_upload", "bs_mesh_update", "bs_mesh_free", "bs_policy_default", "bs_set_policy",
-           "bs_eval_velocity", "bs_eval_points", "bs_advect_heun", "bs_learn_sample_pairs", "bs_learn_pairs", "bs_mlp_train",
+           "bs_eval_velocity", "bs_eval_points", "bs_advect_heun", "bs_velocity_gradient", "bs_mesh_read",
+           "bs_learn_sample_pairs", "bs_learn_pairs", "bs_mlp_train",
            "bs_mlp_grad", "bs_mlp_logits", "bs_status_string", "bs_last_error"]
 
 BS_MLP_BLOB_LEN = 5540
@@ -154,6 +156,10 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     L.bs_advect_heun.argtypes = [vp, ctypes.c_double, ctypes.c_int, vp, ctypes.c_uint32, vp, vp,
                                  ctypes.POINTER(Stats)]
     L.bs_advect_heun.restype = ctypes.c_int
+    L.bs_velocity_gradient.argtypes = [vp, vp, vp, ctypes.c_uint32, vp]
+    L.bs_velocity_gradient.restype = ctypes.c_int
+    L.bs_mesh_read.argtypes = [vp, vp, vp, ctypes.c_uint32, vp]
+    L.bs_mesh_read.restype = ctypes.c_int
     L.bs_learn_sample_pairs.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64, vp, ctypes.POINTER(ctypes.c_int64)]
     L.bs_learn_sample_pairs.restype = ctypes.c_int
     L.bs_learn_pairs.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, vp, vp, vp, vp]
@@ -339,10 +345,12 @@ def bs_eval_points(mesh: BsMesh, pts, out=None, stream=None, stats: bool = False
     return (vel, st.as_dict()) if stats else vel
 
 
-def bs_advect_heun(mesh: BsMesh, dt: float, steps: int, out=None, stream=None, stats: bool = False):
+def bs_advect_heun(mesh: BsMesh, dt: float, steps: int, out=None, stream=None, stats: bool = False,
+                   stretch: bool = False):
     """Advance the mesh nodes `steps` Heun steps of size dt (positions kept in
-    the mesh).  Returns (positions [n,3] numpy or the device tensor `out`,
-    per-step seconds [steps] numpy[, stats dict])."""
+    the mesh; with stretch the nodal vorticity too, by (w . grad) v).
+    Returns (positions [n,3] numpy or the device tensor `out`, per-step
+    seconds [steps] numpy[, stats dict])."""
     L = load_library()
     st = Stats() if stats else None
     secs = np.zeros(max(int(steps), 1), dtype=np.float64)
@@ -353,11 +361,46 @@ def bs_advect_heun(mesh: BsMesh, dt: float, steps: int, out=None, stream=None, s
         if not (_is_torch(out) and out.is_cuda and str(out.dtype) == "torch.float64" and out.is_contiguous()):
             raise ValueError("out must be a contiguous float64 device tensor")
         pos, ptr, flags = out, ctypes.c_void_p(out.data_ptr()), BS_PTR_DEVICE
+    flags |= BS_ADVECT_STRETCH if stretch else 0
     _check(L.bs_advect_heun(mesh.handle, float(dt), int(steps), ptr, flags, _stream_handle(stream),
                             ctypes.c_void_p(secs.ctypes.data), ctypes.byref(st) if st is not None else None),
            "bs_advect_heun")
     secs = secs[: int(steps)]
     return (pos, secs, st.as_dict()) if stats else (pos, secs)
+
+
+def bs_velocity_gradient(mesh: BsMesh, vel=None, out=None, stream=None):
+    """Nodal velocity gradient [n,3,3] (g[i,a,b] = dv_a/dx_b) of the
+    piecewise-linear interpolant of vel ([n,3] float64 numpy array or device
+    tensor; None: the last bs_eval_velocity).  Returns numpy, or the device
+    tensor `out` (contiguous float64 [n,3,3])."""
+    L = load_library()
+    pv, dv, kv = _ptr(vel, np.float64)
+    if vel is not None and tuple(vel.shape) != (mesh.n_nodes, 3):
+        raise ValueError("vel must be [n_nodes, 3]")
+    if out is None:
+        g = np.empty((mesh.n_nodes, 3, 3), dtype=np.float64)
+        pg, dev = ctypes.c_void_p(g.ctypes.data), False
+    else:
+        if not (_is_torch(out) and out.is_cuda and str(out.dtype) == "torch.float64" and out.is_contiguous()
+                and tuple(out.shape) == (mesh.n_nodes, 3, 3)):
+            raise ValueError("out must be a contiguous float64 device tensor [n_nodes, 3, 3]")
+        g, pg, dev = out, ctypes.c_void_p(out.data_ptr()), True
+    if vel is not None and dv != dev:
+        raise ValueError("vel and out must both be host arrays or both device tensors")
+    _check(L.bs_velocity_gradient(mesh.handle, pv, pg, BS_PTR_DEVICE if dev else BS_PTR_HOST,
+                                  _stream_handle(stream)), "bs_velocity_gradient")
+    return g
+
+
+def bs_mesh_read(mesh: BsMesh):
+    """The mesh's current FP64 positions and nodal vorticity (numpy [n,3] each)."""
+    L = load_library()
+    x = np.empty((mesh.n_nodes, 3), dtype=np.float64)
+    w = np.empty((mesh.n_nodes, 3), dtype=np.float64)
+    _check(L.bs_mesh_read(mesh.handle, ctypes.c_void_p(x.ctypes.data), ctypes.c_void_p(w.ctypes.data), BS_PTR_HOST,
+                          None), "bs_mesh_read")
+    return x, w
 
 
 def _dev(t, dtype_name):

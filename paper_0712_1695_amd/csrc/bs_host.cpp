@@ -226,6 +226,8 @@ struct bs_mesh {
     int t0 = 0, tblk0 = 0, tnblk = 0;
     DBuf torig, tlist, tvel;
     bool last_targets = false; // the last evaluation was of the points
+    bool vel_valid = false;    // vel holds the nodes' velocities at the current positions and vorticity
+    DBuf gvel, tgrad, ngrad;   // velocity gradient: input velocities, per-tet |T| G and |T|, nodal G
     int rt_mode = 0; // 0: walk where the boundary is convex, 1: always the candidate kernel
     int far_mode = 0; // 0: matrix-core far field (fixed-rule policies, FP32 modes), 1: vector-ALU kernel
     int serial = 0;   // 1: every kernel on the caller's stream
@@ -522,6 +524,7 @@ void block_spheres(const std::vector<float> &xh, int npad, int64_t p0, int64_t c
 
 int build_device_mesh(bs_mesh *m, hipStream_t s)
 {
+    m->vel_valid = false;
     const int64_t n = m->n, T = m->T;
     const double *X = m->xyz.data(), *W = m->omega.data();
     m->hbar = T > 0 ? mean_edge(n, X, T, m->tets.data()) : 0.0;
@@ -1061,7 +1064,8 @@ void bs_mesh_free(bs_mesh *m)
     DBuf *bufs[] = {&m->xh, &m->xl, &m->om, &m->nrec, &m->blk, &m->node_orig, &m->g1, &m->g4, &m->g11, &m->tid,
                     &m->nbr, &m->inc_start, &m->inc_list, &m->fallback,
                     &m->cell_start, &m->part, &m->band, &m->rtv, &m->vel, &m->cnt, &m->nonfinite, &m->dir,
-                    &m->dir64, &m->cphi, &m->dia, &m->mlp, &m->sel, &m->torig, &m->tlist, &m->tvel};
+                    &m->dir64, &m->cphi, &m->dia, &m->mlp, &m->sel, &m->torig, &m->tlist, &m->tvel,
+                    &m->gvel, &m->tgrad, &m->ngrad};
     for (DBuf *b : bufs) dfree(*b);
     for (auto &a : m->aux)
         if (a) (void)hipStreamSynchronize(a);
@@ -1238,6 +1242,7 @@ int eval_device(bs_mesh *m, hipStream_t s, bool targets)
                                  band, rtv, (double *)(targets ? m->tvel.p : m->vel.p), (int *)m->nonfinite.p, s)))
         return hip_fail(e, "combine kernel");
     (void)hipEventRecord(m->ev[7], s);
+    if (!targets) m->vel_valid = true;
     return BS_OK;
 }
 
@@ -1281,9 +1286,80 @@ int read_stats(bs_mesh *m, bs_stats *st)
     return BS_OK;
 }
 
+// Nodal velocity gradient into m->ngrad ([n][3][3] FP64, input order) from
+// device velocities vel ([n][3], input order).
+int velocity_gradient_device(bs_mesh *m, const double *vel, hipStream_t s)
+{
+    int rc;
+    if ((rc = dalloc(m->tgrad, 8 * 10 * (size_t)std::max<int64_t>(m->T, 1))) ||
+        (rc = dalloc(m->ngrad, 8 * 9 * (size_t)std::max<int64_t>(m->n, 1))))
+        return rc;
+    const bsk::DevMesh dm = dev_view(m);
+    hipError_t e = bsk::launch_velocity_gradient(dm, (const int *)m->node_orig.p, vel, (double *)m->tgrad.p,
+                                                 (double *)m->ngrad.p, s);
+    if (e != hipSuccess) return hip_fail(e, "velocity gradient kernels");
+    return BS_OK;
+}
+
 } // namespace
 
 extern "C" {
+
+int bs_velocity_gradient(bs_mesh *m, const double *vel, double *grad, uint32_t flags, void *stream)
+{
+    g_err.clear();
+    if (!m) return fail(BS_E_STATE, "null mesh");
+    if (!grad) return fail(BS_E_ARG, "null output");
+    if (flags & ~BS_PTR_DEVICE) return fail(BS_E_ARG, "unknown flags 0x%x", flags);
+    if (!vel && !m->vel_valid) return fail(BS_E_STATE, "no velocities: evaluate the nodes first or pass vel");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    const size_t n3 = 3 * (size_t)m->n;
+    const double *dvel = (const double *)m->vel.p;
+    if (vel) {
+        if (flags & BS_PTR_DEVICE) {
+            dvel = vel;
+        } else {
+            for (size_t i = 0; i < n3; ++i)
+                if (!std::isfinite(vel[i])) return fail(BS_E_NONFINITE, "non-finite velocity");
+            int rc = dalloc(m->gvel, 8 * std::max<size_t>(n3, 1));
+            if (rc) return rc;
+            if ((e = hipMemcpyAsync(m->gvel.p, vel, 8 * n3, hipMemcpyHostToDevice, s)) ||
+                (e = hipStreamSynchronize(s)))
+                return hip_fail(e, "upload velocities");
+            dvel = (const double *)m->gvel.p;
+        }
+    }
+    if (m->n == 0) return BS_OK;
+    int rc = velocity_gradient_device(m, dvel, s);
+    if (rc) return rc;
+    if ((e = hipMemcpyAsync(grad, m->ngrad.p, 8 * 9 * (size_t)m->n,
+                            (flags & BS_PTR_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s)) ||
+        (e = hipStreamSynchronize(s)))
+        return hip_fail(e, "velocity gradient");
+    return BS_OK;
+}
+
+int bs_mesh_read(bs_mesh *m, double *xyz, double *omega, uint32_t flags, void *stream)
+{
+    g_err.clear();
+    if (!m) return fail(BS_E_STATE, "null mesh");
+    if (flags & ~BS_PTR_DEVICE) return fail(BS_E_ARG, "unknown flags 0x%x", flags);
+    const size_t bytes = 8 * 3 * (size_t)m->n;
+    if (flags & BS_PTR_DEVICE) {
+        hipStream_t s = (hipStream_t)stream;
+        hipError_t e = hipSuccess;
+        if (xyz && bytes) e = hipMemcpyAsync(xyz, m->xyz.data(), bytes, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && omega && bytes)
+            e = hipMemcpyAsync(omega, m->omega.data(), bytes, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "copy mesh state");
+    } else {
+        if (xyz && bytes) std::memcpy(xyz, m->xyz.data(), bytes);
+        if (omega && bytes) std::memcpy(omega, m->omega.data(), bytes);
+    }
+    return BS_OK;
+}
 
 int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, bs_stats *st)
 {
@@ -1366,10 +1442,18 @@ int bs_advect_heun(bs_mesh *m, double dt, int steps, double *xyz_out, uint32_t f
     g_err.clear();
     if (!m) return fail(BS_E_STATE, "null mesh");
     if (steps < 0 || !std::isfinite(dt)) return fail(BS_E_ARG, "steps must be >= 0 and dt finite");
-    if (flags & ~BS_PTR_DEVICE) return fail(BS_E_ARG, "unknown flags 0x%x", flags);
+    if (flags & ~(BS_PTR_DEVICE | BS_ADVECT_STRETCH)) return fail(BS_E_ARG, "unknown flags 0x%x", flags);
+    const bool stretch = (flags & BS_ADVECT_STRETCH) != 0;
     hipStream_t s = (hipStream_t)stream;
     const size_t n3 = 3 * (size_t)m->n;
     std::vector<double> x = m->xyz, v1(n3), v2(n3), xs(n3);
+    std::vector<double> w = m->omega, s1, s2, ws, g;
+    if (stretch) {
+        s1.resize(n3);
+        s2.resize(n3);
+        ws.resize(n3);
+        g.resize(3 * n3);
+    }
     double t_dev = 0.0;
     int rc = BS_OK;
     hipError_t e;
@@ -1384,25 +1468,49 @@ int bs_advect_heun(bs_mesh *m, double dt, int steps, double *xyz_out, uint32_t f
         t_dev += ms * 1e-3;
         return BS_OK;
     };
-    auto move_to = [&](const std::vector<double> &pos) -> int {
+    // vortex stretching (w . grad) v at every node, from the velocities just
+    // evaluated (the gradient of their piecewise-linear interpolant)
+    auto stretch_to = [&](const std::vector<double> &om, std::vector<double> &out) -> int {
+        int r = velocity_gradient_device(m, (const double *)m->vel.p, s);
+        if (r) return r;
+        if ((e = hipMemcpyAsync(g.data(), m->ngrad.p, 8 * g.size(), hipMemcpyDeviceToHost, s)) ||
+            (e = hipStreamSynchronize(s)))
+            return hip_fail(e, "read velocity gradient");
+        for (size_t i = 0; i < (size_t)m->n; ++i)
+            for (int a = 0; a < 3; ++a)
+                out[3 * i + a] = (g[9 * i + 3 * a] * om[3 * i] + g[9 * i + 3 * a + 1] * om[3 * i + 1]) +
+                                 g[9 * i + 3 * a + 2] * om[3 * i + 2];
+        return BS_OK;
+    };
+    auto move_to = [&](const std::vector<double> &pos, const std::vector<double> &om) -> int {
         m->xyz = pos;
+        m->omega = om;
+        for (double o : om)
+            if (!std::isfinite(o)) return fail(BS_E_NONFINITE, "non-finite vorticity");
         int r = validate_geometry(m);
         if (r) return r;
         return build_device_mesh(m, s);
     };
     for (int k = 0; k < steps && rc == BS_OK; ++k) {
         const auto t0 = std::chrono::steady_clock::now();
-        const std::vector<double> x0 = x;
-        if ((rc = eval_to(v1))) break;
-        for (size_t i = 0; i < n3; ++i) xs[i] = x[i] + dt * v1[i];
-        if ((rc = move_to(xs)) == BS_OK && (rc = eval_to(v2)) == BS_OK) {
-            for (size_t i = 0; i < n3; ++i) x[i] = x[i] + 0.5 * dt * (v1[i] + v2[i]);
-            rc = move_to(x);
+        const std::vector<double> x0 = x, w0 = w;
+        if ((rc = eval_to(v1)) == BS_OK && (!stretch || (rc = stretch_to(w, s1)) == BS_OK)) {
+            for (size_t i = 0; i < n3; ++i) xs[i] = x[i] + dt * v1[i];
+            if (stretch)
+                for (size_t i = 0; i < n3; ++i) ws[i] = w[i] + dt * s1[i];
+            if ((rc = move_to(xs, stretch ? ws : w)) == BS_OK && (rc = eval_to(v2)) == BS_OK &&
+                (!stretch || (rc = stretch_to(ws, s2)) == BS_OK)) {
+                for (size_t i = 0; i < n3; ++i) x[i] = x[i] + 0.5 * dt * (v1[i] + v2[i]);
+                if (stretch)
+                    for (size_t i = 0; i < n3; ++i) w[i] = w[i] + 0.5 * dt * (s1[i] + s2[i]);
+                rc = move_to(x, w);
+            }
         }
         if (rc) {
             // leave the mesh at the start of the failing step
             const std::string why = g_err;
             m->xyz = x0;
+            m->omega = w0;
             if (validate_geometry(m) == BS_OK) build_device_mesh(m, s);
             g_err = why;
             return rc;

@@ -120,6 +120,11 @@ hipError_t launch_select(const DevMesh &m, const Thresholds &th, const LearnPara
 hipError_t launch_rt_walk(const DevMesh &m, const Thresholds &th, const AngTab &ang, int all_pairs, float r_stop,
                           int precision, double *rtv, unsigned long long *cnt, int *fallback, int *n_fallback,
                           const int *sel_list, const int *sel_n, const float *sel_dmax, hipStream_t s);
+// Nodal velocity gradient (grad[input node][3][3], FP64) of the linear
+// interpolant of vel ([input node][3]) on each tet, volume-weighted over the
+// node's tets; tg: scratch of 10 doubles per tet.
+hipError_t launch_velocity_gradient(const DevMesh &m, const int *node_orig, const double *vel, double *tg,
+                                    double *grad, hipStream_t s);
 hipError_t launch_combine(const DevMesh &m, const int *node_orig, const double *part, int splits,
                           const double *band, const double *rtv, double *vel, int *nonfinite, hipStream_t s);
 

@@ -2057,4 +2057,83 @@ hipError_t launch_combine(const DevMesh &m, const int *node_orig, const double *
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Velocity gradient of the piecewise-linear interpolant of nodal velocities
+// (FP64).  Per tet: with E = [x1-x0, x2-x0, x3-x0] and D = [v1-v0, v2-v0,
+// v3-v0] (columns), the interpolant's gradient is G = D E^-1, whose rows of
+// E^-1 are the cross products of pairs of edges over det E; tg[t] holds
+// |T| G (9 values, G[a][b] = dv_a/dx_b) and |T|.  Per node: the mean of G
+// over its incident tets weighted by their volumes, in the incident list's
+// order, written in input numbering (0 for a node without tets).
+__global__ void __launch_bounds__(256) k_tet_grad(DevMesh m, const int *__restrict__ node_orig,
+                                                  const double *__restrict__ vel, double *__restrict__ tg)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= m.T) return;
+    const int4 id4 = m.tid[t];
+    const int id[4] = {id4.x, id4.y, id4.z, id4.w};
+    double x[4][3], v[4][3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const size_t o = 3 * (size_t)node_orig[id[j]];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            x[j][c] = (double)m.xh[c * m.npad + id[j]] + (double)m.xl[c * m.npad + id[j]];
+            v[j][c] = vel[o + c];
+        }
+    }
+    double e[3][3], dv[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            e[k][c] = x[k + 1][c] - x[0][c];
+            dv[k][c] = v[k + 1][c] - v[0][c];
+        }
+    double r[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double *p = e[(k + 1) % 3], *q = e[(k + 2) % 3];
+        r[k][0] = p[1] * q[2] - p[2] * q[1];
+        r[k][1] = p[2] * q[0] - p[0] * q[2];
+        r[k][2] = p[0] * q[1] - p[1] * q[0];
+    }
+    const double det = e[0][0] * r[0][0] + e[0][1] * r[0][1] + e[0][2] * r[0][2];
+    // |T| G = (|det| / 6) D E^-1 = (sign(det) / 6) sum_k dv_k r_k^T
+    const double w = (det < 0.0 ? -1.0 : 1.0) / 6.0;
+    double *o = tg + 10 * (size_t)t;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            o[3 * a + b] = w * ((dv[0][a] * r[0][b] + dv[1][a] * r[1][b]) + dv[2][a] * r[2][b]);
+    o[9] = fabs(det) / 6.0;
+}
+
+__global__ void __launch_bounds__(256) k_node_grad(DevMesh m, const int *__restrict__ node_orig,
+                                                   const double *__restrict__ tg, double *__restrict__ grad)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= m.n) return;
+    double g[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, vs = 0.0;
+    for (int p = m.inc_start[k]; p < m.inc_start[k + 1]; ++p) {
+        const double *o = tg + 10 * (size_t)m.inc_list[p];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) g[q] += o[q];
+        vs += o[9];
+    }
+    const double inv = vs > 0.0 ? 1.0 / vs : 0.0;
+    double *out = grad + 9 * (size_t)node_orig[k];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) out[q] = g[q] * inv;
+}
+
+hipError_t launch_velocity_gradient(const DevMesh &m, const int *node_orig, const double *vel, double *tg,
+                                    double *grad, hipStream_t s)
+{
+    if (m.T > 0) hipLaunchKernelGGL(k_tet_grad, dim3((m.T + 255) / 256), dim3(256), 0, s, m, node_orig, vel, tg);
+    if (m.n > 0) hipLaunchKernelGGL(k_node_grad, dim3((m.n + 255) / 256), dim3(256), 0, s, m, node_orig, tg, grad);
+    return hipGetLastError();
+}
+
 } // namespace bsk

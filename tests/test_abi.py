@@ -83,6 +83,8 @@ def test_calls_on_null_mesh():
     assert L.bs_mesh_update(None, None, None, 0, None) == bs.BS_E_STATE
     assert L.bs_advect_heun(None, 0.1, 1, None, 0, None, None, None) == bs.BS_E_STATE
     assert L.bs_eval_points(None, 1, None, None, 0, None, None) == bs.BS_E_STATE
+    assert L.bs_velocity_gradient(None, None, None, 0, None) == bs.BS_E_STATE
+    assert L.bs_mesh_read(None, None, None, 0, None) == bs.BS_E_STATE
     L.bs_mesh_free(None)
 
 

@@ -1,0 +1,113 @@
+"""The Lagrangian kinematics on the GPU against the oracle: the nodal
+velocity gradient (bs_velocity_gradient) on seeded velocities, and Heun
+steps that stretch the vorticity (bs_advect_heun with stretch) against the
+same steps driven by the oracle in FP64."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.kinematics as K
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def bs():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_0712_1695_amd as bs
+
+    return bs
+
+
+@pytest.mark.parametrize("name,scale", [("C1", (6, 6, 6)), ("C5", (9, 8, 10))])
+def test_velocity_gradient_matches_oracle(bs, name, scale):
+    m = W.make_config(name, scale=scale)
+    _say(f"velocity gradient: {name} at {scale}, {m.n_nodes} nodes, {m.n_tets} tets")
+    rng = np.random.default_rng(11)
+    vel = rng.standard_normal((m.n_nodes, 3))
+    h = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
+    try:
+        g = bs.bs_velocity_gradient(h, vel=vel)
+        ref = K.nodal_velocity_gradient(m.xyz, m.tets, vel)
+        err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+        _say(f"max |G - G_oracle| / max |G_oracle| = {err:.3e}")
+        assert err <= 1e-9
+        # a globally linear field comes back exactly (to rounding)
+        A = rng.standard_normal((3, 3))
+        gl = bs.bs_velocity_gradient(h, vel=m.xyz @ A.T + 0.3)
+        assert np.max(np.abs(gl - A)) <= 1e-8 * np.max(np.abs(A))
+    finally:
+        bs.bs_mesh_free(h)
+
+
+def test_gradient_of_the_last_evaluation(bs):
+    m = W.make_config("C1", scale=(5, 5, 5))
+    h = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
+    try:
+        with pytest.raises(bs.BsError) as ei:
+            bs.bs_velocity_gradient(h)
+        assert ei.value.status == bs.BS_E_STATE
+        v = bs.bs_eval_velocity(h)
+        assert np.array_equal(bs.bs_velocity_gradient(h), bs.bs_velocity_gradient(h, vel=v))
+        bs.bs_mesh_update(h, xyz=m.xyz)  # new positions: no current velocities
+        with pytest.raises(bs.BsError):
+            bs.bs_velocity_gradient(h)
+    finally:
+        bs.bs_mesh_free(h)
+
+
+def test_heun_with_stretching_matches_oracle(bs):
+    """Two Heun steps of the two-ring workload (12^3 cells) moving the nodes
+    and stretching their vorticity, against the oracle's steps (its own
+    velocities, gradient and updates in FP64)."""
+    m = W.make_config("C5", scale=(12, 12, 12))
+    dt, steps = 0.02, 2
+    _say(f"Lagrangian with stretching: {m.n_nodes} nodes, {steps} Heun steps")
+    h = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
+    try:
+        pos, secs = bs.bs_advect_heun(h, dt, steps, stretch=True)
+        x_gpu, w_gpu = bs.bs_mesh_read(h)
+    finally:
+        bs.bs_mesh_free(h)
+    assert np.array_equal(pos, x_gpu)
+    x, w = m.xyz.copy(), m.omega.copy()
+    for _ in range(steps):
+        x, w = K.lagrangian_step(x, w, m.tets, dt, lambda xx, ww: oracle.evaluate(xx, ww, m.tets))
+    ex = np.linalg.norm((x_gpu - m.xyz) - (x - m.xyz)) / np.linalg.norm(x - m.xyz)
+    ew = np.linalg.norm((w_gpu - m.omega) - (w - m.omega)) / np.linalg.norm(w - m.omega)
+    _say(f"rel-L2 of displacement {ex:.3e}, of vorticity change {ew:.3e}")
+    assert np.linalg.norm(w - m.omega) > 1e-3 * np.linalg.norm(m.omega)  # the vorticity did change
+    assert ex <= 1e-5 and ew <= 1e-5
+
+
+def test_remeshed_run_and_parity_on_the_new_mesh(bs):
+    """A run that stretches and re-tetrahedralises the points before every
+    evaluation, then the velocity on a Delaunay mesh of its final nodes
+    against the oracle on that mesh (the flat tets Qhull leaves on lattices
+    are dropped, so the mesh has zero-volume cracks and takes the candidate
+    ray kernel)."""
+    from paper_0712_1695_amd.lagrangian import retetrahedralise, run
+
+    m = W.make_config("C5", scale=(8, 8, 8))
+    x, w, secs, _, last = run(m.xyz, m.omega, m.tets, 3, 0.02, stretch=True, remesh=True)
+    _say(f"remeshed run: {len(secs)} steps, last mesh {last.shape[0]} tets")
+    assert len(secs) == 3
+    assert np.all(np.isfinite(x)) and np.all(np.isfinite(w))
+    assert np.linalg.norm(w - m.omega) > 1e-3 * np.linalg.norm(m.omega)
+    tets = retetrahedralise(x)
+    h = bs.bs_mesh_upload(x, w, tets)
+    try:
+        v = bs.bs_eval_velocity(h)
+    finally:
+        bs.bs_mesh_free(h)
+    ref = oracle.evaluate(x, w, tets)
+    err = np.linalg.norm(v - ref) / np.linalg.norm(ref)
+    _say(f"Delaunay mesh of the moved nodes ({tets.shape[0]} tets): rel-L2 vs oracle {err:.3e}")
+    assert err <= 1e-6
