@@ -35,6 +35,7 @@
 #include "bs_mlp_dev.h"
 
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 namespace bsk {
 
@@ -1456,6 +1457,16 @@ struct WalkLds {
     float4 icone[kIncCap]; // cone around the face seen from the node: unit axis, cos(half angle) (-2: none)
 };
 
+// The learned policy's walk also holds a bounding sphere (radius: the
+// largest vertex-centroid distance) of every listed tet that does not
+// contain the node: centroid relative to the node and its squared norm.  A
+// ray can meet such a tet only inside its sphere, so each ray walks only to
+// the far side of the last sphere it passes through (not at all past its
+// start if it passes through none).
+struct WalkLdsListed : WalkLds {
+    float4 lc[kSelListCap];
+};
+
 
 // value [d, A, B] for the canonical ordering (smaller node id first); FP64
 // sign when tiny.  Returns the value for (A, B) in the given order.
@@ -1629,7 +1640,7 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
                                                 const int *__restrict__ sel_list, const int *__restrict__ sel_n,
                                                 const float *__restrict__ sel_dmax)
 {
-    __shared__ WalkLds W;
+    __shared__ typename std::conditional<LISTED, WalkLdsListed, WalkLds>::type W;
     const int lane = threadIdx.x;
     const int self = blockIdx.x;
     float xhv[3], xlv[3], omx[3];
@@ -1647,7 +1658,7 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
 
     // ---- A. ray-traced tets of the node (not needed when every pair is):
     // their count and the farthest centroid; the learned policy's list
-    int nlist = 0;
+    int nlist = 0, n_lc = 0;
     float stop = r_stop;
     if (!all_pairs) {
         float dmax = 0.f;
@@ -1657,7 +1668,25 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
                 if (lane == 0) fallback[atomicAdd(n_fallback, 1)] = self;
                 return;
             }
-            for (int k = lane; k < nlist; k += 64) W.list[k] = sel_list[(size_t)self * kSelCap + k];
+            for (int k0 = 0; k0 < nlist; k0 += 64) {
+                const int k = k0 + lane;
+                bool take = false;
+                float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (k < nlist) {
+                    const int t = sel_list[(size_t)self * kSelCap + k];
+                    W.list[k] = t;
+                    const int4 id = m.tid[t];
+                    const float *g = m.g1 + (size_t)t * kRecG;
+                    c.x = (g[0] - xhv[0]) - xlv[0];
+                    c.y = (g[1] - xhv[1]) - xlv[1];
+                    c.z = (g[2] - xhv[2]) - xlv[2];
+                    c.w = (c.x * c.x + c.y * c.y) + c.z * c.z;
+                    take = !((id.x == self) | (id.y == self) | (id.z == self) | (id.w == self));
+                }
+                const unsigned long long mk = __ballot(take);
+                if (take) W.lc[n_lc + __popcll(mk & ((1ull << lane) - 1ull))] = c;
+                n_lc += __popcll(mk);
+            }
             dmax = sel_dmax[self];
             // sort the list (bitonic, padded with INT_MAX)
             int np2 = 1;
@@ -1837,6 +1866,18 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
                           h * fmaf(d.x, sy, -(d.y * sx)));
             ++A.hits;
         }
+        // the learned policy: this ray's last listed sphere
+        float stop_r = stop;
+        if constexpr (LISTED) {
+            const float vcm = th.vc * (1.f + 1e-4f) + 1e-6f, vc2 = vcm * vcm;
+            float sr = 0.f;
+            for (int k = 0; k < n_lc; ++k) {
+                const float4 c = W.lc[k];
+                const float t = fmaf(c.x, d.x, fmaf(c.y, d.y, c.z * d.z));
+                if (c.w - t * t <= vc2 && t + vcm > sr) sr = t + vcm;
+            }
+            stop_r = fminf(stop, sr * (1.f + 1e-4f) + 1e-6f);
+        }
         // the entry face (P0, P1, P2) and its values [d,P0,P1], [d,P1,P2],
         // [d,P2,P0] (all of sign sg)
         int T = W.inb[start];
@@ -1852,7 +1893,7 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
             }
         }
         int steps = 0;
-        while (T >= 0 && rho < stop && steps < kMaxSteps) {
+        while (T >= 0 && rho < stop_r && steps < kMaxSteps) {
             ++steps;
             const int4 id4 = m.tid[T];
             const int4 nb4 = m.nbr[T];
