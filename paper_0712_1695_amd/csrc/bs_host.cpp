@@ -217,6 +217,7 @@ struct bs_mesh {
     bool convex = false;          // boundary is one closed, locally convex surface (rays never re-enter)
     bsk::Bins bins{};
     // device buffers
+    DBuf tsph; // bounding spheres of 16-tet tiles
     DBuf xh, xl, om, nrec, blk, node_orig, g1, g4, g11, tid, cell_start, nbr, inc_start, inc_list;
     DBuf part, band, rtv, vel, cnt, nonfinite, fallback;
     // evaluation points (bs_eval_points): FP64 copy, count, first node index
@@ -693,6 +694,31 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
         }
     });
 
+    // ---- bounding sphere of the binary32 centroids of every tile of 16
+    // consecutive (sorted) tets, for the far kernel's band flags
+    const int64_t ntile = (T + 15) / 16;
+    std::vector<float4> tsph((size_t)std::max<int64_t>(ntile, 1));
+    for (int64_t k = 0; k < ntile; ++k) {
+        const int64_t a = 16 * k, b = std::min<int64_t>(T, a + 16);
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int64_t t = a; t < b; ++t)
+            for (int c = 0; c < 3; ++c) {
+                lo[c] = std::min(lo[c], (double)g1[(size_t)t * 8 + c]);
+                hi[c] = std::max(hi[c], (double)g1[(size_t)t * 8 + c]);
+            }
+        const float cc[3] = {(float)(0.5 * (lo[0] + hi[0])), (float)(0.5 * (lo[1] + hi[1])), (float)(0.5 * (lo[2] + hi[2]))};
+        double r2 = 0.0;
+        for (int64_t t = a; t < b; ++t) {
+            double d2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                const double d = (double)g1[(size_t)t * 8 + c] - (double)cc[c];
+                d2 += d * d;
+            }
+            r2 = std::max(r2, d2);
+        }
+        tsph[(size_t)k] = make_float4(cc[0], cc[1], cc[2], (float)(std::sqrt(r2) * (1.0 + 1e-5) + 1e-6));
+    }
+
     // ---- face neighbours (sorted numbering) and incident tets per node
     std::vector<int32_t> slot((size_t)T);
     for (int64_t k = 0; k < T; ++k) slot[(size_t)order[(size_t)k]] = (int32_t)k;
@@ -732,7 +758,8 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
         (rc = dalloc(m->cell_start, 4 * cell_start.size())) || (rc = dalloc(m->band, 8 * 3 * (size_t)npad)) ||
         (rc = dalloc(m->rtv, 8 * 3 * (size_t)npad)) || (rc = dalloc(m->vel, 8 * 3 * (size_t)n)) ||
         (rc = dalloc(m->cnt, 8 * bsk::kNumCounters)) || (rc = dalloc(m->nonfinite, 4)) ||
-        (rc = dalloc(m->nbr, sizeof(int4) * (size_t)T)) || (rc = dalloc(m->inc_start, 4 * inc_start.size())) ||
+        (rc = dalloc(m->nbr, sizeof(int4) * (size_t)T)) ||
+        (rc = dalloc(m->tsph, sizeof(float4) * tsph.size())) || (rc = dalloc(m->inc_start, 4 * inc_start.size())) ||
         (rc = dalloc(m->inc_list, 4 * inc_list.size())))
         return rc;
     hipError_t e;
@@ -755,6 +782,7 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
     BS_UP(tid, tid)
     BS_UP(cell_start, cell_start)
     BS_UP(nbr, nbr)
+    BS_UP(tsph, tsph)
     BS_UP(inc_start, inc_start)
     BS_UP(inc_list, inc_list)
 #undef BS_UP
@@ -848,6 +876,7 @@ bsk::DevMesh dev_view(const bs_mesh *m)
     d.tid = (const int4 *)m->tid.p;
     d.cell_start = (const int *)m->cell_start.p;
     d.nbr = (const int4 *)m->nbr.p;
+    d.tsph = (const float4 *)m->tsph.p;
     d.inc_start = (const int *)m->inc_start.p;
     d.inc_list = (const int *)m->inc_list.p;
     d.bins = m->bins;
@@ -1061,7 +1090,7 @@ int bs_mesh_update(bs_mesh *m, const double *xyz, const double *omega, uint32_t 
 void bs_mesh_free(bs_mesh *m)
 {
     if (!m) return;
-    DBuf *bufs[] = {&m->xh, &m->xl, &m->om, &m->nrec, &m->blk, &m->node_orig, &m->g1, &m->g4, &m->g11, &m->tid,
+    DBuf *bufs[] = {&m->xh, &m->xl, &m->om, &m->nrec, &m->tsph, &m->blk, &m->node_orig, &m->g1, &m->g4, &m->g11, &m->tid,
                     &m->nbr, &m->inc_start, &m->inc_list, &m->fallback,
                     &m->cell_start, &m->part, &m->band, &m->rtv, &m->vel, &m->cnt, &m->nonfinite, &m->dir,
                     &m->dir64, &m->cphi, &m->dia, &m->mlp, &m->sel, &m->torig, &m->tlist, &m->tvel,

@@ -86,6 +86,7 @@ struct DevMesh {
     const int4 *tid;
     const int *cell_start;
     const int4 *nbr;       // [T] face neighbours (sorted numbering; face f opposite vertex f; -1 boundary)
+    const float4 *tsph;    // [ceil(T/16)] bounding sphere of the centroids of each tile of 16 sorted tets
     const int *inc_start;  // [n+1] CSR of the tets incident to each node
     const int *inc_list;
     Bins bins;

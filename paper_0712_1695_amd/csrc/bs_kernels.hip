@@ -285,9 +285,10 @@ hipError_t launch_gauss_all(const DevMesh &m, int rule_pts, int precision, int s
 // lanes of the second line up with the output lanes of the first (block b =
 // lanes 4b..4b+3 = one tet and four nodes), so the reciprocal cubes pass from
 // one to the other in registers.
-// Pairs whose rule is not G1 are masked out: for a tile of 16 tets any of
-// whose centroids lies within r_band of a node tile's bounding sphere, every
-// pair of that node tile is classified with the comparisons of fixed_rule
+// Pairs whose rule is not G1 are masked out: for a tile of 16 tets whose
+// centroids' bounding sphere (precomputed per tile) comes within r_band of
+// a node tile's bounding sphere, every pair of that node tile is classified
+// with the comparisons of fixed_rule
 // (the band and ray-tracing kernels take the others); outside the band
 // every pair is G1.  The cut distances are ordered (checked on the host),
 // so a pair is G1 exactly when it is not incident and !(d^2 < g4^2); the
@@ -383,13 +384,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     }
     __syncthreads();
     float4 nts[4];
-    float rb2[4];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        nts[nt] = S.nts[nt];
-        const float rb = nts[nt].w + th.r_band;
-        rb2[nt] = nts[nt].w < 0.f ? -1.f : rb * rb;
-    }
+    for (int nt = 0; nt < 4; ++nt) nts[nt] = S.nts[nt];
 
     f32x4 D0[4], D1[4];
 #pragma unroll
@@ -435,18 +431,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
             for (int h = 0; h < 2; ++h) S.c.a2[buf][tile][c][qq][2 * j + h] = comp[4 * h + c];
         S.c.pc[buf][tid] = make_float4(pr[0], pr[1], pr[2], 0.f);
         S.c.ids[buf][tid] = pok ? pid : make_int4(-1, -1, -1, -1);
-        unsigned long long bal[4];
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const float dx = pr[0] - nts[nt].x, dy = pr[1] - nts[nt].y, dz = pr[2] - nts[nt].z;
-            bal[nt] = __ballot(pok && (dx * dx + dy * dy) + dz * dz < rb2[nt]);
+        // the wave's 64 tets are tiles 4 wave + tl of the chunk; lane 4 tl + nt
+        // tests the bounding sphere of tile tl against node tile nt
+        bool near = false;
+        if (lane < 16) {
+            const int g = ((pt - lane) >> 4) + (lane >> 2);
+            const float4 ns = S.nts[lane & 3];
+            if (16 * g < t1 && ns.w >= 0.f) {
+                const float4 ts = m.tsph[g];
+                const float dx = ts.x - ns.x, dy = ts.y - ns.y, dz = ts.z - ns.z;
+                const float rr = (ts.w + ns.w + th.r_band) * (1.f + 1e-5f);
+                near = (dx * dx + dy * dy) + dz * dz < rr * rr;
+            }
         }
-        // the wave's 64 tets are tiles 4 wave + tl
+        const unsigned long long bal = __ballot(near);
 #pragma unroll
         for (int tl = 0; tl < 4; ++tl) {
             unsigned long long pk = 0;
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) pk |= ((bal[nt] >> (16 * tl)) & 0xffffull) << (16 * nt);
+            for (int nt = 0; nt < 4; ++nt) pk |= ((bal >> (4 * tl + nt)) & 1ull) ? 0xffffull << (16 * nt) : 0ull;
             if (lane == 0) S.c.band[buf][4 * wave + tl] = pk;
         }
     };
@@ -1267,7 +1270,9 @@ __device__ __forceinline__ int learned_batch(const DevMesh &m, const LearnParams
                              : rule == RULE_G4 ? m.g4 + (size_t)t * 4 * kRecG : m.g11 + (size_t)t * 11 * kRecG;
             for (int q = 0; q < np; ++q) gauss_point(xhv[0], xhv[1], xhv[2], g + q * kRecG, a0, a1, a2);
             acc_add<PREC>(A, a0, a1, a2);
-            ++n_by_rule[rule];
+            n_by_rule[0] += rule == RULE_G1;
+            n_by_rule[1] += rule == RULE_G4;
+            n_by_rule[2] += rule == RULE_G11;
         }
     }
     __syncthreads();
