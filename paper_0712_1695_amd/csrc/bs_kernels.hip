@@ -1473,24 +1473,27 @@ struct WalkLdsListed : WalkLds {
 };
 
 
-// value [d, A, B] for the canonical ordering (smaller node id first); FP64
-// sign when tiny.  Returns the value for (A, B) in the given order.
+// value [d, A, B] in the given order; when it is too small for its binary32
+// sign to be certain (|value| below 1e-5 of the normal's 1-norm; the
+// rounding error of either order is near 1e-7 of it), the sign comes from
+// FP64 in the canonical order (smaller node id first), so every test of an
+// edge takes the same decision whichever tet or order it is evaluated in.
 __device__ __forceinline__ float edge_val(const float4 &d, const float *A, int ia, const float *B, int ib,
                                           const DevMesh &m, const double *d64, const float *xhv, const float *xlv,
                                           int &sgn, int &retests)
 {
     float N[3];
-    const bool flip = ia > ib;
-    if (!flip) cross_canon(A, B, N);
-    else cross_canon(B, A, N);
+    cross_canon(A, B, N);
     const float c = fmaf(d.x, N[0], fmaf(d.y, N[1], d.z * N[2]));
     int sg = c >= 0.f ? 1 : -1;
     if (fabsf(c) <= 1e-5f * (fabsf(N[0]) + fabsf(N[1]) + fabsf(N[2]))) {
-        sg = edge_sign_f64(m, d64, flip ? ib : ia, flip ? ia : ib, xhv, xlv);
+        const bool flip = ia > ib;
+        const int s64 = edge_sign_f64(m, d64, flip ? ib : ia, flip ? ia : ib, xhv, xlv);
+        sg = flip ? -s64 : s64;
         ++retests;
     }
-    sgn = flip ? -sg : sg;
-    return flip ? -c : c;
+    sgn = sg;
+    return c;
 }
 
 __device__ __forceinline__ bool in_sorted(const int *a, int n, int v)
@@ -1897,6 +1900,9 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
                 Wv[q][c] = W.iw[start][3 * q + c];
             }
         }
+        // compensated mode: the chords of one ray summed in FP32, the ray's
+        // sum added to the node's compensated sum
+        float ray[3] = {0.f, 0.f, 0.f};
         int steps = 0;
         while (T >= 0 && rho < stop_r && steps < kMaxSteps) {
             ++steps;
@@ -1946,17 +1952,29 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
 #pragma unroll
             for (int c = 0; c < 3; ++c) wout[c] = fmaf(lv, wv[c], fmaf(la, wa[c], lb * wb[c]));
             const float r_out = fmaxf(rout, rho);
-            // the selector's list holds only pairs the fixed rule ray-traces
+            // the fixed rule's test: past its first segment a ray meets no tet
+            // incident to the node (such a tet lies in its own cone from the
+            // node), so only the distance comparison remains; the selector's
+            // list holds only pairs the fixed rule ray-traces
             bool take = true;
             if (!all_pairs) {
-                take = fixed_rule(xhv[0], xhv[1], xhv[2], cen.x, cen.y, cen.z, id4, self, th) == RULE_RT;
+                const float ex = xhv[0] - cen.x, ey = xhv[1] - cen.y, ez = xhv[2] - cen.z;
+                const float qx = ex * ex, qy = ey * ey, qz = ez * ez;
+                take = (qx + qy) + qz < th.rt2;
                 if constexpr (LISTED) take = take && in_sorted(W.list, nlist, T);
             }
             if (take) {
                 const float h = 0.5f * d.w * (r_out - rho);
                 const float sx = w_in[0] + wout[0], sy = w_in[1] + wout[1], sz = w_in[2] + wout[2];
-                acc_add<PREC>(A, h * fmaf(d.y, sz, -(d.z * sy)), h * fmaf(d.z, sx, -(d.x * sz)),
-                              h * fmaf(d.x, sy, -(d.y * sx)));
+                const float a0 = h * fmaf(d.y, sz, -(d.z * sy)), a1 = h * fmaf(d.z, sx, -(d.x * sz)),
+                            a2 = h * fmaf(d.x, sy, -(d.y * sx));
+                if (PREC == 1) {
+                    ray[0] += a0;
+                    ray[1] += a1;
+                    ray[2] += a2;
+                } else {
+                    acc_add<PREC>(A, a0, a1, a2);
+                }
                 ++A.hits;
             }
             // across the exit face: the face of T opposite O
@@ -1979,6 +1997,7 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
                 w_in[c] = wout[c];
             }
         }
+        if (PREC == 1) acc_add<1>(A, ray[0], ray[1], ray[2]);
     }
     A.pairs = all_pairs ? (unsigned long long)m.T : (unsigned long long)nlist;
 
