@@ -1209,6 +1209,28 @@ __device__ __forceinline__ void rt_batch(const DevMesh &m, const AngTab &ang, Rt
     __syncthreads();
 }
 
+// The first np (<= NQ) points of a Gauss record g at x, all NQ records
+// loaded before any is used (point min(q, np - 1) for q >= np, its term
+// dropped; np = 0 adds nothing).
+template <int NQ>
+__device__ __forceinline__ void gauss_terms(const float *x, const float *g, int np, float &a0, float &a1, float &a2)
+{
+    float4 ra[NQ];
+    float2 rb[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int qq = min(q, max(np - 1, 0));
+        ra[q] = *reinterpret_cast<const float4 *>(g + qq * kRecG);
+        rb[q] = *reinterpret_cast<const float2 *>(g + qq * kRecG + 4);
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        if (q >= np) continue;
+        const float rec[6] = {ra[q].x, ra[q].y, ra[q].z, ra[q].w, rb[q].x, rb[q].y};
+        gauss_point(x[0], x[1], x[2], rec, a0, a1, a2);
+    }
+}
+
 // Learned rule choice for a batch of n <= 64 candidate pairs (lane p: tet
 // cand[p], p < n): pairs the fixed rule ray-traces whose tet does not
 // contain the node.  The pair takes the cheapest Gauss rule whose predicted
@@ -1263,17 +1285,22 @@ __device__ __forceinline__ int learned_batch(const DevMesh &m, const LearnParams
         rule = c2 >= need ? RULE_G11 : RULE_RT;
         rule = c1 >= need ? RULE_G4 : rule;
         rule = c0 >= need ? RULE_G1 : rule;
-        if (rule != RULE_RT) {
-            float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-            const int np = rule == RULE_G1 ? 1 : rule == RULE_G4 ? 4 : 11;
-            const float *g = rule == RULE_G1 ? m.g1 + (size_t)t * kRecG
-                             : rule == RULE_G4 ? m.g4 + (size_t)t * 4 * kRecG : m.g11 + (size_t)t * 11 * kRecG;
-            for (int q = 0; q < np; ++q) gauss_point(xhv[0], xhv[1], xhv[2], g + q * kRecG, a0, a1, a2);
-            acc_add<PREC>(A, a0, a1, a2);
-            n_by_rule[0] += rule == RULE_G1;
-            n_by_rule[1] += rule == RULE_G4;
-            n_by_rule[2] += rule == RULE_G11;
-        }
+    }
+    // the Gauss terms of the moved pairs: every lane runs the wave's largest
+    // rule, unrolled so that the record loads issue together (a lane with a
+    // smaller rule reloads its last point and drops the extra terms)
+    const int np = !act || rule == RULE_RT ? 0 : rule == RULE_G1 ? 1 : rule == RULE_G4 ? 4 : 11;
+    const float *g = np == 11 ? m.g11 + (size_t)t * 11 * kRecG
+                     : np == 4 ? m.g4 + (size_t)t * 4 * kRecG : m.g1 + (size_t)t * kRecG;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    if (__ballot(np == 11)) gauss_terms<11>(xhv, g, np, a0, a1, a2);
+    else if (__ballot(np == 4)) gauss_terms<4>(xhv, g, np, a0, a1, a2);
+    else if (__ballot(np == 1)) gauss_terms<1>(xhv, g, np, a0, a1, a2);
+    if (np > 0) {
+        acc_add<PREC>(A, a0, a1, a2);
+        n_by_rule[0] += rule == RULE_G1;
+        n_by_rule[1] += rule == RULE_G4;
+        n_by_rule[2] += rule == RULE_G11;
     }
     __syncthreads();
     return rule;
