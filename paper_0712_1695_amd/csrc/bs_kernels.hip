@@ -314,12 +314,10 @@ struct FarLds {
         struct {
             float a1[2][16][kA1Stride];       // [buf][tile][k*16 + i]: -2p'_k (k < 3), |p'|^2 (k = 3) of tet i
             float a2[2][16][4][4][8];         // [buf][tile][c][q][2j + h]: component 4h + c of [W, W x p'] of tet 4q + j
-            float4 pc[2][kFarChunk];          // binary32 centroid (the rule's) of each tet of the chunk
-            int4 ids[2][kFarChunk];           // vertex ids (sorted numbering)
             unsigned long long band[2][16];   // [buf][tile]: bit 16 nt + i = centroid of tet i within the band of node tile nt
         } c;
-        double red[4][4][6][16];              // [wave][node tile][component][node]
     };
+    double acc[4][6][64];                     // [wave][component][lane]: FP64 sums of node 16 (lane / 16) + lane % 16
     float4 xn[64];                            // binary32 node coordinates (the rule's), by node of the block
     float4 nts[4];                            // bounding sphere of each node tile (radius < 0: no node)
 };
@@ -327,7 +325,7 @@ struct FarLds {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int PREC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_far_mfma(DevMesh m, Thresholds th, int splits,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_far_mfma(DevMesh m, Thresholds th, int splits,
                                                   int per_split, double *__restrict__ part)
 {
     __shared__ FarLds S;
@@ -390,14 +388,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     f32x4 D0[4], D1[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) D0[nt] = D1[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}; // node 16q + i16 of the block after each fold
+#pragma unroll
+    for (int r = 0; r < 6; ++r) S.acc[wave][r][lane] = 0.0; // node 16q + i16 of the block after each fold
 
     // the record of tet c0 + tid, in flight in registers until stored (the
     // index is clamped so that the loads need no branch; tets past the end
     // of the split are replaced at the store)
     float4 pg;
     float2 pw;
-    int4 pid;
     int pt;
     auto load = [&](int c0) {
         pt = c0 + tid;
@@ -405,7 +403,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         const float *g = m.g1 + (size_t)t * kRecG;
         pg = *(const float4 *)g;
         pw = *(const float2 *)(g + 4);
-        pid = th.inc_far ? m.tid[t] : make_int4(-1, -1, -1, -1);
     };
     auto store = [&](int buf) {
         const int tile = tid >> 4, i = tid & 15, qq = i >> 2, j = i & 3;
@@ -429,8 +426,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int h = 0; h < 2; ++h) S.c.a2[buf][tile][c][qq][2 * j + h] = comp[4 * h + c];
-        S.c.pc[buf][tid] = make_float4(pr[0], pr[1], pr[2], 0.f);
-        S.c.ids[buf][tid] = pok ? pid : make_int4(-1, -1, -1, -1);
         // the wave's 64 tets are tiles 4 wave + tl of the chunk; lane 4 tl + nt
         // tests the bounding sphere of tile tl against node tile nt
         bool near = false;
@@ -472,7 +467,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         for (int r = 0; r < 6; ++r) {
             const auto sw =
                 __builtin_amdgcn_permlane16_swap(__float_as_uint(y[0][r]), __float_as_uint(y[1][r]), false, false);
-            acc[r] += (double)(__uint_as_float(sw[0]) + __uint_as_float(sw[1]));
+            S.acc[wave][r][lane] += (double)(__uint_as_float(sw[0]) + __uint_as_float(sw[1]));
         }
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) D0[nt] = D1[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
@@ -532,13 +527,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                     const int self = b * kBlockNodes + 16 * nt + i16;
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        const int e = tile * 16 + 4 * q + j;
-                        const float4 pc = S.c.pc[buf][e];
+                        // the rule's centroid and ids from the tet records (a
+                        // padding slot past the split reads the last tet: its
+                        // strength is zero in the operands, any decision holds)
+                        const int tg = min(c0 + tile * 16 + 4 * q + j, t1 - 1);
+                        const float4 pc = *reinterpret_cast<const float4 *>(m.g1 + (size_t)tg * kRecG);
                         const float dx = xn.x - pc.x, dy = xn.y - pc.y, dz = xn.z - pc.z;
                         const float sx = dx * dx, sy = dy * dy, sz = dz * dz;
                         g1[j] = !((sx + sy) + sz < th.g4_2);
                         if (th.inc_far) {
-                            const int4 id = S.c.ids[buf][e];
+                            const int4 id = m.tid[tg];
                             g1[j] = g1[j] && !((id.x == self) | (id.y == self) | (id.z == self) | (id.w == self));
                         }
                     }
@@ -559,15 +557,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     }
     fold();
     // combine the waves (each took a quarter of every chunk)
-#pragma unroll
-    for (int r = 0; r < 6; ++r) S.red[wave][q][r][i16] = acc[r];
     __syncthreads();
     if (tid < 64) {
-        const int nt = tid >> 4, n16 = tid & 15;
         double sw[6];
 #pragma unroll
         for (int r = 0; r < 6; ++r)
-            sw[r] = ((S.red[0][nt][r][n16] + S.red[1][nt][r][n16]) + S.red[2][nt][r][n16]) + S.red[3][nt][r][n16];
+            sw[r] = ((S.acc[0][r][tid] + S.acc[1][r][tid]) + S.acc[2][r][tid]) + S.acc[3][r][tid];
         const int i = b * kBlockNodes + tid;
         double xp[3] = {0.0, 0.0, 0.0};
         if (i < m.nv) {
