@@ -11,7 +11,8 @@ Prints one JSON line (see the keys below).  The timed steps run the band
 and ray-tracing kernels beside the far field (library streams); a second
 pass of the same steps with every kernel on one stream gives each kernel's
 own duration (HIP events recorded on its launch stream inside the library),
-from which the roofline object for the far-field kernel is computed.  cpu_baseline
+from which the roofline objects of the three kernels are computed
+("roofline" is the longest of them, "roofline_kernels" lists all).  cpu_baseline
 times the FP64 oracle on a bounded sample of nodes (all tetrahedra) on the
 host's cores.
 """
@@ -206,23 +207,28 @@ def main():
                                         "sum": kl[3] * 1e3},
                    "selector": {**info, "trained_on": [t.name for t in train_meshes]}}
     flops = algorithmic_flops(stats, nm)
-    g1_pairs = stats["pairs_by_rule"][0]
-    far_flops = FLOPS_PER_POINT * g1_pairs  # the method's flops of the G1 pairs
-    far_t = kern[0]
+    g1, g4, g11, rtp = stats["pairs_by_rule"]
     far_name = "k_gauss_all" if (args.valu_far or args.precision == 2) else "k_far_mfma"
-    roof = {
-        "kernel": far_name + (" (far field, 1-point rule on every pair, vector ALUs)" if far_name == "k_gauss_all"
-                              else " (far field, the G1 pairs, FP32 matrix-core contractions)"),
-        "bound": "alu" if far_name == "k_gauss_all" else "mfma",
-        "achieved": far_flops / far_t / 1e12,
-        "peak": FP32_PEAK_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": far_flops / far_t / 1e12 / FP32_PEAK_TFLOPS,
-        "traffic": measured_traffic(far_name, args.workload, args.precision),
-        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-        "avg_duration_ms": far_t * 1e3,
-        "measured": "kernel alone: the serial pass (every kernel on one stream), HIP events on its stream",
-    }
+    measured = "kernel alone: the serial pass (every kernel on one stream), HIP events on its stream"
+
+    def roof_entry(name, what, bound, kflops, t):
+        return {"kernel": f"{name} ({what})", "bound": bound, "achieved": kflops / t / 1e12,
+                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": kflops / t / 1e12 / FP32_PEAK_TFLOPS,
+                "traffic": measured_traffic(name, args.workload, args.precision),
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "avg_duration_ms": t * 1e3, "measured": measured}
+
+    kernels = [
+        roof_entry(far_name, "far field, 1-point rule on every pair, vector ALUs" if far_name == "k_gauss_all"
+                   else "far field, the G1 pairs, FP32 matrix-core contractions",
+                   "alu" if far_name == "k_gauss_all" else "mfma", FLOPS_PER_POINT * g1, kern[0]),
+        roof_entry("k_band", "the G4 and G11 pairs, vector ALUs, lane = node", "alu",
+                   FLOPS_PER_POINT * (4 * g4 + 11 * g11), kern[1]),
+        roof_entry("k_rt_walk", "ray tracing by walking face neighbours; the method's flops of its pairs", "alu",
+                   rtp * (9.0 + 7.0 * nm) + 156.0 * stats["rt_hit_lines"], kern[2]),
+    ]
+    # the dominant kernel: the longest one alone
+    roof = dict(max(kernels, key=lambda r: r["avg_duration_ms"]))
     line = {
         "metric": "node-tet pair evals/s (+ % FP32 peak)",
         "value": value,
@@ -250,6 +256,7 @@ def main():
                                  "sum": kern[3] * 1e3},
         },
         "roofline": roof,
+        "roofline_kernels": kernels,
     }
     if learned is not None:
         line["learned"] = learned
