@@ -111,3 +111,20 @@ def test_remeshed_run_and_parity_on_the_new_mesh(bs):
     err = np.linalg.norm(v - ref) / np.linalg.norm(ref)
     _say(f"Delaunay mesh of the moved nodes ({tets.shape[0]} tets): rel-L2 vs oracle {err:.3e}")
     assert err <= 1e-6
+
+
+def test_velocity_gradient_device_pointers(bs):
+    """Device velocities and a device output give the host call's bits."""
+    import torch
+
+    m = W.make_config("C1", scale=(5, 6, 7))
+    vel = np.random.default_rng(3).standard_normal((m.n_nodes, 3))
+    h = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
+    try:
+        g_host = bs.bs_velocity_gradient(h, vel=vel)
+        out = torch.empty((m.n_nodes, 3, 3), dtype=torch.float64, device="cuda")
+        bs.bs_velocity_gradient(h, vel=torch.tensor(vel, device="cuda"), out=out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), g_host)
+    finally:
+        bs.bs_mesh_free(h)
