@@ -209,6 +209,7 @@ def main():
     flops = algorithmic_flops(stats, nm)
     g1, g4, g11, rtp = stats["pairs_by_rule"]
     far_name = "k_gauss_all" if (args.valu_far or args.precision == 2) else "k_far_mfma"
+    band_name = "k_band" if far_name == "k_gauss_all" else "k_band_piece"
     measured = "kernel alone: the serial pass (every kernel on one stream), HIP events on its stream"
 
     def roof_entry(name, what, bound, kflops, t):
@@ -222,7 +223,8 @@ def main():
         roof_entry(far_name, "far field, 1-point rule on every pair, vector ALUs" if far_name == "k_gauss_all"
                    else "far field, the G1 pairs, FP32 matrix-core contractions",
                    "alu" if far_name == "k_gauss_all" else "mfma", FLOPS_PER_POINT * g1, kern[0]),
-        roof_entry("k_band", "the G4 and G11 pairs, vector ALUs, lane = node", "alu",
+        roof_entry(band_name, "the G4 and G11 pairs, vector ALUs, lane = node" +
+                   ("" if band_name == "k_band" else ", row pieces staged in LDS"), "alu",
                    FLOPS_PER_POINT * (4 * g4 + 11 * g11), kern[1]),
         roof_entry("k_rt_walk", "ray tracing by walking face neighbours; the method's flops of its pairs", "alu",
                    rtp * (9.0 + 7.0 * nm) + 156.0 * stats["rt_hit_lines"], kern[2]),

@@ -27,8 +27,9 @@
 //                the far field of all pairs), tet records wave-uniform;
 //   k_far_mfma   the G1 pairs of the fixed rule on the matrix cores (FP32
 //                MFMA; pairs with another rule masked out);
-//   k_band       per 64-node block: pairs whose fixed rule is G4 / G11
-//                (after k_gauss_all: also remove their G1 term);
+//   k_band_piece per 64-node block: pairs whose fixed rule is G4 / G11,
+//                after k_far_mfma (row pieces staged in LDS);
+//   k_band       the same after k_gauss_all, also removing their G1 term;
 //   k_rt         one wave per node: ray tracing of its near tetrahedra;
 //   k_combine    FP64 sum of the partials, back to input node order.
 #include "bs_internal.h"
@@ -641,18 +642,18 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 }
 
 // ---------------------------------------------------------------------------
-// Band corrections.  One workgroup of kBandWaves waves per 64 consecutive
-// (Morton-ordered) nodes; lane = node, the waves take the bin rows of the
-// block's neighbourhood in turn.  For every tet whose centroid lies within
-// r_band of the block's bounding sphere: with SUB (the far field came from
-// k_gauss_all, which took every pair by G1) lanes whose pair rule is not G1
-// subtract that G1 term; then lanes with G4 / G11 add that rule (ray-traced
-// pairs are added by k_rt).  Without SUB the far field (k_far_mfma) already
-// left out every pair that is not G1.  The waves' partial sums
-// are combined in FP64 through LDS.
+// Band corrections after k_gauss_all (which took every pair by G1).  One
+// workgroup of kBandWaves waves per 64 consecutive (k-d ordered) nodes; lane
+// = node, the waves take the bin rows of the block's neighbourhood in turn.
+// For every tet whose centroid lies within r_band of the block's bounding
+// sphere, lanes whose pair rule is not G1 subtract that G1 term, then lanes
+// with G4 / G11 add that rule (ray-traced pairs are added by the ray-tracing
+// kernels).  The waves' partial sums are combined in FP64 through LDS.
+// (After k_far_mfma, which leaves out every pair that is not G1, the band
+// runs in k_band_piece.)
 constexpr int kBandWaves = 4;
 
-template <int PREC, bool SUB>
+template <int PREC>
 __global__ void __launch_bounds__(64 * kBandWaves) k_band(DevMesh m, Thresholds th, double *__restrict__ band,
                                                           unsigned long long *__restrict__ cnt)
 {
@@ -692,7 +693,7 @@ __global__ void __launch_bounds__(64 * kBandWaves) k_band(DevMesh m, Thresholds 
             }
             const bool in11 = valid && !near && d2 < th.g11_2;
             const bool in4 = valid && !near && d2 < th.g4_2 && !(d2 < th.g11_2);
-            if (SUB && valid && (near || d2 < th.g4_2)) {
+            if (valid && (near || d2 < th.g4_2)) {
                 float a = 0.f, b = 0.f, c = 0.f;
                 gauss_point(x, y, z, g, a, b, c);
                 ax -= a;
@@ -752,6 +753,165 @@ __global__ void __launch_bounds__(64 * kBandWaves) k_band(DevMesh m, Thresholds 
     }
 }
 
+// Band pairs after k_far_mfma (no G1 terms to remove): k_band's blocks,
+// waves, rows and rule masks, but each wave streams its rows in pieces of 32
+// tets staged in its own LDS.  The centroids and G4 points of the next piece
+// are loaded into registers while the current piece is evaluated, so a tet
+// costs LDS broadcast reads instead of dependent scalar loads from L2 (the
+// G11 points, needed for few tets, stay scalar loads).  The FP32 sums of a
+// piece are folded into the compensated sums.
+constexpr int kBandPiece = 32;
+
+struct BandPieceLds {
+    float4 cen[kBandPiece];     // centroid (x, y, z, 0)
+    float4 pa[kBandPiece][4];   // G4 point q: position, W.x
+    float2 pb[kBandPiece][4];   // G4 point q: W.y, W.z
+};
+
+template <int PREC>
+__global__ void __launch_bounds__(64 * kBandWaves) k_band_piece(DevMesh m, Thresholds th, double *__restrict__ band,
+                                                                unsigned long long *__restrict__ cnt)
+{
+    __shared__ double red[kBandWaves][3][64];
+    __shared__ BandPieceLds P[kBandWaves];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int per_xcd = (m.nblk + 7) >> 3;
+    const int lb = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (lb >= m.nblk) return;
+    const int blk = m.blk0 + lb;
+    const int i = blk * kBlockNodes + lane;
+    const bool valid = i < m.nv;
+    const float x = m.xh[i], y = m.xh[m.npad + i], z = m.xh[2 * m.npad + i];
+    const float4 bc = m.blk[blk];
+    float sx = 0.f, sy = 0.f, sz = 0.f, ccx = 0.f, ccy = 0.f, ccz = 0.f;
+    double dx = 0.0, dy = 0.0, dz = 0.0;
+    unsigned long long n4 = 0, n11 = 0;
+    RowIter rows(m, bc.x, bc.y, bc.z, th.r_band + bc.w);
+    int row = 0, c0 = 0, c1 = 0, t0, t1;
+    // lane l: tet c0 + l % 32 (clamped to the piece), G4 points 2h, 2h + 1
+    // with h = l / 32; lanes below 32 also the centroid
+    const int k = lane & (kBandPiece - 1), h = lane >> 5;
+    float4 rc, ra0, ra1;
+    float2 rb0, rb1;
+#define BAND_FETCH()                                                                                   \
+    do {                                                                                               \
+        const int t_ = min(c0 + k, c1 - 1);                                                            \
+        rc = *reinterpret_cast<const float4 *>(m.g1 + (size_t)t_ * kRecG);                            \
+        const float *g_ = m.g4 + (size_t)t_ * 4 * kRecG + 2 * h * kRecG;                               \
+        ra0 = *reinterpret_cast<const float4 *>(g_);                                                   \
+        rb0 = *reinterpret_cast<const float2 *>(g_ + 4);                                               \
+        ra1 = *reinterpret_cast<const float4 *>(g_ + kRecG);                                           \
+        rb1 = *reinterpret_cast<const float2 *>(g_ + kRecG + 4);                                       \
+    } while (0)
+    // the first piece of this wave's rows
+    bool have = false;
+    while (rows.next(t0, t1)) {
+        if ((row++ % kBandWaves) != wave) continue;
+        c0 = t0;
+        c1 = t1;
+        have = true;
+        break;
+    }
+    if (have) BAND_FETCH();
+    while (have) {
+        const int p0 = c0, pn = min(kBandPiece, c1 - c0);
+        if (h == 0) P[wave].cen[k] = make_float4(rc.x, rc.y, rc.z, 0.f);
+        P[wave].pa[k][2 * h] = ra0;
+        P[wave].pb[k][2 * h] = rb0;
+        P[wave].pa[k][2 * h + 1] = ra1;
+        P[wave].pb[k][2 * h + 1] = rb1;
+        // the next piece: the rest of this row, else this wave's next row
+        if (c0 + kBandPiece < c1) {
+            c0 += kBandPiece;
+        } else {
+            have = false;
+            while (rows.next(t0, t1)) {
+                if ((row++ % kBandWaves) != wave) continue;
+                c0 = t0;
+                c1 = t1;
+                have = true;
+                break;
+            }
+        }
+        if (have) BAND_FETCH();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        float ax = 0.f, ay = 0.f, az = 0.f;
+        for (int j = 0; j < pn; ++j) {
+            const int t = p0 + j;
+            const float4 c = P[wave].cen[j];
+            const float ex = x - c.x, ey = y - c.y, ez = z - c.z;
+            const float qx = ex * ex, qy = ey * ey, qz = ez * ez;
+            const float d2 = (qx + qy) + qz;
+            bool near = d2 < th.rt2;
+            if (th.inc_band) {
+                const int4 id = m.tid[t];
+                near = near || (id.x == i) | (id.y == i) | (id.z == i) | (id.w == i);
+            }
+            const bool in11 = valid && !near && d2 < th.g11_2;
+            const bool in4 = valid && !near && d2 < th.g4_2 && !(d2 < th.g11_2);
+            if (in4) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float4 a = P[wave].pa[j][q];
+                    const float2 b = P[wave].pb[j][q];
+                    const float g[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
+                    gauss_point(x, y, z, g, ax, ay, az);
+                }
+                ++n4;
+            }
+            if (in11) {
+                const float *g11 = m.g11 + (size_t)t * 11 * kRecG;
+#pragma unroll
+                for (int q = 0; q < 11; ++q) gauss_point(x, y, z, g11 + q * kRecG, ax, ay, az);
+                ++n11;
+            }
+        }
+        if (PREC == 1) {
+            two_sum(sx, ccx, ax);
+            two_sum(sy, ccy, ay);
+            two_sum(sz, ccz, az);
+        } else if (PREC == 2) {
+            dx += (double)ax;
+            dy += (double)ay;
+            dz += (double)az;
+        } else {
+            sx += ax;
+            sy += ay;
+            sz += az;
+        }
+        // the next piece's stores must follow this piece's reads
+        __builtin_amdgcn_wave_barrier();
+    }
+#undef BAND_FETCH
+    if (PREC != 2) {
+        dx = (double)sx + (double)ccx;
+        dy = (double)sy + (double)ccy;
+        dz = (double)sz + (double)ccz;
+    }
+    red[wave][0][lane] = dx;
+    red[wave][1][lane] = dy;
+    red[wave][2][lane] = dz;
+    n4 = wave_sum_u64(n4);
+    n11 = wave_sum_u64(n11);
+    if (lane == 0 && cnt) {
+        atomicAdd(&cnt[0], n4);
+        atomicAdd(&cnt[1], n11);
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double v = red[0][c][lane];
+#pragma unroll
+            for (int w = 1; w < kBandWaves; ++w) v += red[w][c][lane];
+            band[(size_t)c * m.npad + i] = v;
+        }
+    }
+}
+
 hipError_t launch_band(const DevMesh &m, const Thresholds &th, int precision, int sub_g1, double *band,
                        unsigned long long *cnt, hipStream_t s)
 {
@@ -759,18 +919,18 @@ hipError_t launch_band(const DevMesh &m, const Thresholds &th, int precision, in
     const dim3 grid(8 * ((m.nblk + 7) / 8));
     if (sub_g1) {
         if (precision == 0)
-            hipLaunchKernelGGL((k_band<0, true>), grid, blk, 0, s, m, th, band, cnt);
+            hipLaunchKernelGGL(k_band<0>, grid, blk, 0, s, m, th, band, cnt);
         else if (precision == 1)
-            hipLaunchKernelGGL((k_band<1, true>), grid, blk, 0, s, m, th, band, cnt);
+            hipLaunchKernelGGL(k_band<1>, grid, blk, 0, s, m, th, band, cnt);
         else
-            hipLaunchKernelGGL((k_band<2, true>), grid, blk, 0, s, m, th, band, cnt);
+            hipLaunchKernelGGL(k_band<2>, grid, blk, 0, s, m, th, band, cnt);
     } else {
         if (precision == 0)
-            hipLaunchKernelGGL((k_band<0, false>), grid, blk, 0, s, m, th, band, cnt);
+            hipLaunchKernelGGL(k_band_piece<0>, grid, blk, 0, s, m, th, band, cnt);
         else if (precision == 1)
-            hipLaunchKernelGGL((k_band<1, false>), grid, blk, 0, s, m, th, band, cnt);
+            hipLaunchKernelGGL(k_band_piece<1>, grid, blk, 0, s, m, th, band, cnt);
         else
-            hipLaunchKernelGGL((k_band<2, false>), grid, blk, 0, s, m, th, band, cnt);
+            hipLaunchKernelGGL(k_band_piece<2>, grid, blk, 0, s, m, th, band, cnt);
     }
     return hipGetLastError();
 }
