@@ -712,16 +712,25 @@ __global__ void __launch_bounds__(64 * kBandWaves) k_band(DevMesh m, Thresholds 
                 for (int q = 0; q < 11; ++q) gauss_point(x, y, z, g11 + q * kRecG, ax, ay, az);
                 ++n11;
             }
+            // FP64 mode: every pair's terms added in FP64; compensated mode:
+            // the FP32 sum of every 32 tets folded by TwoSum
+            if (PREC == 2) {
+                dx += (double)ax;
+                dy += (double)ay;
+                dz += (double)az;
+                ax = ay = az = 0.f;
+            } else if (PREC == 1 && ((t - t0) & 31) == 31) {
+                two_sum(sx, ccx, ax);
+                two_sum(sy, ccy, ay);
+                two_sum(sz, ccz, az);
+                ax = ay = az = 0.f;
+            }
         }
         if (PREC == 1) {
             two_sum(sx, ccx, ax);
             two_sum(sy, ccy, ay);
             two_sum(sz, ccz, az);
-        } else if (PREC == 2) {
-            dx += (double)ax;
-            dy += (double)ay;
-            dz += (double)az;
-        } else {
+        } else if (PREC == 0) {
             sx += ax;
             sy += ay;
             sz += az;
@@ -868,16 +877,18 @@ __global__ void __launch_bounds__(64 * kBandWaves) k_band_piece(DevMesh m, Thres
                 for (int q = 0; q < 11; ++q) gauss_point(x, y, z, g11 + q * kRecG, ax, ay, az);
                 ++n11;
             }
+            if (PREC == 2) { // FP64 mode: every pair's terms added in FP64
+                dx += (double)ax;
+                dy += (double)ay;
+                dz += (double)az;
+                ax = ay = az = 0.f;
+            }
         }
         if (PREC == 1) {
             two_sum(sx, ccx, ax);
             two_sum(sy, ccy, ay);
             two_sum(sz, ccz, az);
-        } else if (PREC == 2) {
-            dx += (double)ax;
-            dy += (double)ay;
-            dz += (double)az;
-        } else {
+        } else if (PREC == 0) {
             sx += ax;
             sy += ay;
             sz += az;
