@@ -239,6 +239,36 @@ def test_reoriented_tets():
     assert rel_l2(v, oracle.evaluate(m.xyz, m.omega, tets)) <= TOL
 
 
+@pytest.mark.parametrize("name,scale,valu", [("C1", None, False), ("C1", None, True),
+                                             ("C2", (24, 24, 8), False)])
+def test_incident_pairs_beyond_the_cuts(name, scale, valu):
+    """Cuts below the largest vertex-centroid distance (ray tracing below
+    0.5, G11 below 0.65, G4 below 0.8 mean edge lengths; the largest
+    vertex-centroid distance is 0.86 of it on C1): a tet having the node as
+    a vertex can lie beyond every cut, so the far-field and band kernels take
+    their incidence tests (the rule ray-traces every incident pair), on the
+    matrix-core and on the vector-ALU far field."""
+    m = W.make_config(name) if scale is None else W.make_config(name, scale=scale)
+    cuts = dict(near_cut=0.5, d_g11=0.65, d_g4=0.8)
+    hb = oracle.mean_edge(m.xyz, m.tets)
+    X = m.xyz[m.tets]
+    vc = np.linalg.norm(X - X.mean(axis=1)[:, None, :], axis=2)
+    assert (vc > cuts["d_g4"] * hb).sum() > 0  # incident pairs beyond the G4 cut exist
+    _say(f"{name} {m.n_nodes} nodes, cuts {cuts}, {'vector ALUs' if valu else 'matrix cores'}; "
+         f"{(vc > cuts['d_g4'] * hb).sum()} vertex-tet pairs beyond the G4 cut")
+    h = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
+    try:
+        bs.bs_set_policy(h, kind=bs.BS_POLICY_FIXED, **cuts)
+        v, st = bs.bs_eval_velocity(h, stats=True, valu_far=valu)
+    finally:
+        bs.bs_mesh_free(h)
+    ref, cnt = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("fixed", **cuts),
+                               return_counters=True)
+    _say(f"  rules {st['pairs_by_rule']} (oracle {cnt['pairs_by_rule']}), rel-L2 {rel_l2(v, ref):.3e}")
+    assert st["pairs_by_rule"] == cnt["pairs_by_rule"]
+    assert rel_l2(v, ref) <= TOL
+
+
 def test_device_pointers_update_stream_and_determinism():
     import torch
 
