@@ -1700,14 +1700,13 @@ __device__ __forceinline__ bool in_sorted(const int *a, int n, int v)
     return lo < n && a[lo] == v;
 }
 
-// Count the ray-traced tets the wave found and track the farthest centroid.
-__device__ __forceinline__ void walk_reach_add(const DevMesh &m, int &n, bool take, int t, const float *xhv,
-                                               float &dmax)
+// Count the ray-traced tets the wave found and track the farthest centroid
+// (g: the tet's centroid).
+__device__ __forceinline__ void walk_reach_add(int &n, bool take, const float4 &g, const float *xhv, float &dmax)
 {
     n += __popcll(__ballot(take));
     if (take) {
-        const float *g = m.g1 + (size_t)t * kRecG;
-        const float dx = xhv[0] - g[0], dy = xhv[1] - g[1], dz = xhv[2] - g[2];
+        const float dx = xhv[0] - g.x, dy = xhv[1] - g.y, dz = xhv[2] - g.z;
         dmax = fmaxf(dmax, sqrtf((dx * dx + dy * dy) + dz * dz));
     }
 }
@@ -1909,19 +1908,34 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
                     __syncthreads();
                 }
         } else {
+            // chunks of 64 tets of a bin row, the next chunk's ids and
+            // centroids loaded while the current one is tested
             RowIter rows(m, xhv[0], xhv[1], xhv[2], th.r_rt);
-            int t0, t1;
-            while (rows.next(t0, t1)) {
-                for (int b0 = t0; b0 < t1; b0 += 64) {
-                    const int t = b0 + lane;
-                    bool is_rt = false;
-                    if (t < t1) {
-                        const int4 id = m.tid[t];
-                        const float *g = m.g1 + (size_t)t * kRecG;
-                        is_rt = fixed_rule(xhv[0], xhv[1], xhv[2], g[0], g[1], g[2], id, self, th) == RULE_RT;
-                    }
-                    walk_reach_add(m, nlist, is_rt, t, xhv, dmax);
+            int t0 = 0, t1 = 0;
+            bool have = rows.next(t0, t1);
+            int b0 = t0;
+            int4 id_n = make_int4(-1, -1, -1, -1);
+            float4 g_n = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (have && b0 + lane < t1) {
+                id_n = m.tid[b0 + lane];
+                g_n = *reinterpret_cast<const float4 *>(m.g1 + (size_t)(b0 + lane) * kRecG);
+            }
+            while (have) {
+                const bool tv = b0 + lane < t1;
+                const int4 id = id_n;
+                const float4 g = g_n;
+                if (b0 + 64 < t1) {
+                    b0 += 64;
+                } else {
+                    have = rows.next(t0, t1);
+                    b0 = t0;
                 }
+                if (have && b0 + lane < t1) {
+                    id_n = m.tid[b0 + lane];
+                    g_n = *reinterpret_cast<const float4 *>(m.g1 + (size_t)(b0 + lane) * kRecG);
+                }
+                const bool is_rt = tv && fixed_rule(xhv[0], xhv[1], xhv[2], g.x, g.y, g.z, id, self, th) == RULE_RT;
+                walk_reach_add(nlist, is_rt, g, xhv, dmax);
             }
             for (int o = 32; o > 0; o >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, o, 64));
         }
