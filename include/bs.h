@@ -242,7 +242,8 @@ int bs_mesh_read(bs_mesh *m, double *xyz, double *omega, uint32_t flags, void *s
  * accumulation on the matrix cores) picks, for pairs the fixed rule sends
  * to ray tracing and whose tet does not contain the node, the cheapest
  * rule (BS_RULE_*) expected to meet an error budget; the fixed rule is the
- * fallback below a softmax confidence and the judge of the labels.  The
+ * fallback below a softmax confidence, and the method's own errors decide
+ * the labels.  The
  * training pairs are labelled by the method itself (bs_learn_pairs).
  *
  * Packed blob (BS_MLP_BLOB_LEN uint16 BF16 values, in this order):
