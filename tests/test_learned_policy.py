@@ -147,3 +147,21 @@ def test_learned_policy_gains_over_fixed(bs, selector):
           flush=True)
     assert err_l <= err_f
     assert st_l["pairs_by_rule"][3] < 0.25 * st_f["pairs_by_rule"][3]
+
+
+def test_learned_policy_concurrent_and_serial_agree(bs, selector):
+    """The learned policy's selection and walk on the mesh's ray-tracing
+    stream, beside the far field and the band, give the same bits as every
+    kernel on one stream, and the same bits on a second evaluation."""
+    bits, _, conf_min = selector
+    m = W.make_config("C1", scale=(12, 12, 12))
+    h = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
+    try:
+        bs.bs_set_policy(h, kind=bs.BS_POLICY_LEARNED, mlp_bf16=bits, conf_min=conf_min)
+        a, st = bs.bs_eval_velocity(h, stats=True)
+        b = bs.bs_eval_velocity(h, serial=True)
+        c = bs.bs_eval_velocity(h)
+    finally:
+        bs.bs_mesh_free(h)
+    assert sum(st["pairs_by_rule"][:3]) > 0 and np.all(np.isfinite(a))
+    assert np.array_equal(a, b) and np.array_equal(a, c)
