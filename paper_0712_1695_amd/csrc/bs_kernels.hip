@@ -1495,6 +1495,10 @@ __device__ __forceinline__ void list_shift(int *list, int &n, int used, int lane
     n = rest;
 }
 
+// workgroups of k_rt over a node list: enough to fill the chip, few enough
+// that an empty list costs nothing beside the kernels that run concurrently
+constexpr int kRtListGrid = 2048;
+
 template <int PREC, bool LEARNED>
 __global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang, LearnParams lp, int all_pairs,
                                            double *__restrict__ rtv, unsigned long long *__restrict__ cnt,
@@ -1502,116 +1506,122 @@ __global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang,
 {
     __shared__ RtShared<LEARNED> S;
     const int lane = threadIdx.x;
-    if (node_list && (int)blockIdx.x >= *node_count) return;
-    const int self = node_list ? node_list[blockIdx.x] : (int)blockIdx.x;
-    float xhv[3], xlv[3], omx[3];
+    // with a node list (whose length only the device knows) a grid of at
+    // most kRtListGrid workgroups strides over it; without one, one
+    // workgroup per node
+    const int count = node_list ? *node_count : m.n;
+    for (int nk = blockIdx.x; nk < count; nk += gridDim.x) {
+        const int self = node_list ? node_list[nk] : nk;
+        float xhv[3], xlv[3], omx[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        xhv[c] = m.xh[c * m.npad + self];
-        xlv[c] = m.xl[c * m.npad + self];
-        omx[c] = m.om[c * m.npad + self];
-    }
-    RtAcc A;
-    A.ax = A.ay = A.az = A.sx = A.sy = A.sz = A.cx = A.cy = A.cz = 0.f;
-    A.dx = A.dy = A.dz = 0.0;
-    A.pairs = A.hits = 0;
-    A.retests = 0;
-    unsigned long long n_by_rule[3] = {0, 0, 0};
-    int nlist = 0, ncand = 0; // uniform
+        for (int c = 0; c < 3; ++c) {
+            xhv[c] = m.xh[c * m.npad + self];
+            xlv[c] = m.xl[c * m.npad + self];
+            omx[c] = m.om[c * m.npad + self];
+        }
+        RtAcc A;
+        A.ax = A.ay = A.az = A.sx = A.sy = A.sz = A.cx = A.cy = A.cz = 0.f;
+        A.dx = A.dy = A.dz = 0.0;
+        A.pairs = A.hits = 0;
+        A.retests = 0;
+        unsigned long long n_by_rule[3] = {0, 0, 0};
+        int nlist = 0, ncand = 0; // uniform
 
-    RowIter rows(m, xhv[0], xhv[1], xhv[2], th.r_rt);
-    int t0 = 0, t1 = all_pairs ? m.T : 0;
-    bool have = all_pairs ? (m.T > 0) : rows.next(t0, t1);
-    while (have) {
-        for (int b0 = t0; b0 < t1; b0 += 64) {
-            const int t = b0 + lane;
-            bool is_rt = false, inc = false;
-            if (t < t1) {
-                const int4 id = m.tid[t];
-                inc = (id.x == self) | (id.y == self) | (id.z == self) | (id.w == self);
-                if (all_pairs) is_rt = true;
-                else {
-                    const float *g = m.g1 + (size_t)t * kRecG;
-                    is_rt = fixed_rule(xhv[0], xhv[1], xhv[2], g[0], g[1], g[2], id, self, th) == RULE_RT;
+        RowIter rows(m, xhv[0], xhv[1], xhv[2], th.r_rt);
+        int t0 = 0, t1 = all_pairs ? m.T : 0;
+        bool have = all_pairs ? (m.T > 0) : rows.next(t0, t1);
+        while (have) {
+            for (int b0 = t0; b0 < t1; b0 += 64) {
+                const int t = b0 + lane;
+                bool is_rt = false, inc = false;
+                if (t < t1) {
+                    const int4 id = m.tid[t];
+                    inc = (id.x == self) | (id.y == self) | (id.z == self) | (id.w == self);
+                    if (all_pairs) is_rt = true;
+                    else {
+                        const float *g = m.g1 + (size_t)t * kRecG;
+                        is_rt = fixed_rule(xhv[0], xhv[1], xhv[2], g[0], g[1], g[2], id, self, th) == RULE_RT;
+                    }
                 }
-            }
-            if constexpr (LEARNED) {
-                // the selector's pairs wait for a full batch; the rest are listed now
-                const bool cand = is_rt && !inc;
-                list_append(S.cand, ncand, cand, t, lane);
-                is_rt = is_rt && !cand;
-            }
-            list_append(S.list, nlist, is_rt, t, lane);
-            __syncthreads();
-            if (nlist >= 64) {
-                rt_batch<PREC>(m, ang, S.u.b, S.list, 64, lane, self, xhv, xlv, omx, A);
-                list_shift(S.list, nlist, 64, lane);
-            }
-            if constexpr (LEARNED) {
-                if (ncand >= 64) {
-                    int tt;
-                    const bool keep = learned_batch<PREC>(m, lp, S.u.n, S.cand, 64, lane, xhv, xlv, A, n_by_rule,
-                                                          &tt) == RULE_RT;
-                    list_shift(S.cand, ncand, 64, lane);
-                    list_append(S.list, nlist, keep, tt, lane);
-                    __syncthreads();
-                    if (nlist >= 64) {
-                        rt_batch<PREC>(m, ang, S.u.b, S.list, 64, lane, self, xhv, xlv, omx, A);
-                        list_shift(S.list, nlist, 64, lane);
+                if constexpr (LEARNED) {
+                    // the selector's pairs wait for a full batch; the rest are listed now
+                    const bool cand = is_rt && !inc;
+                    list_append(S.cand, ncand, cand, t, lane);
+                    is_rt = is_rt && !cand;
+                }
+                list_append(S.list, nlist, is_rt, t, lane);
+                __syncthreads();
+                if (nlist >= 64) {
+                    rt_batch<PREC>(m, ang, S.u.b, S.list, 64, lane, self, xhv, xlv, omx, A);
+                    list_shift(S.list, nlist, 64, lane);
+                }
+                if constexpr (LEARNED) {
+                    if (ncand >= 64) {
+                        int tt;
+                        const bool keep = learned_batch<PREC>(m, lp, S.u.n, S.cand, 64, lane, xhv, xlv, A, n_by_rule,
+                                                              &tt) == RULE_RT;
+                        list_shift(S.cand, ncand, 64, lane);
+                        list_append(S.list, nlist, keep, tt, lane);
+                        __syncthreads();
+                        if (nlist >= 64) {
+                            rt_batch<PREC>(m, ang, S.u.b, S.list, 64, lane, self, xhv, xlv, omx, A);
+                            list_shift(S.list, nlist, 64, lane);
+                        }
                     }
                 }
             }
+            have = all_pairs ? false : rows.next(t0, t1);
         }
-        have = all_pairs ? false : rows.next(t0, t1);
-    }
-    if constexpr (LEARNED) {
-        if (ncand > 0) {
-            int tt;
-            const bool keep = learned_batch<PREC>(m, lp, S.u.n, S.cand, ncand, lane, xhv, xlv, A, n_by_rule, &tt) ==
-                                  RULE_RT && lane < ncand;
-            list_append(S.list, nlist, keep, tt, lane);
-            __syncthreads();
-            if (nlist >= 64) {
-                rt_batch<PREC>(m, ang, S.u.b, S.list, 64, lane, self, xhv, xlv, omx, A);
-                list_shift(S.list, nlist, 64, lane);
+        if constexpr (LEARNED) {
+            if (ncand > 0) {
+                int tt;
+                const bool keep = learned_batch<PREC>(m, lp, S.u.n, S.cand, ncand, lane, xhv, xlv, A, n_by_rule, &tt) ==
+                                      RULE_RT && lane < ncand;
+                list_append(S.list, nlist, keep, tt, lane);
+                __syncthreads();
+                if (nlist >= 64) {
+                    rt_batch<PREC>(m, ang, S.u.b, S.list, 64, lane, self, xhv, xlv, omx, A);
+                    list_shift(S.list, nlist, 64, lane);
+                }
             }
         }
-    }
-    if (nlist > 0) rt_batch<PREC>(m, ang, S.u.b, S.list, nlist, lane, self, xhv, xlv, omx, A);
+        if (nlist > 0) rt_batch<PREC>(m, ang, S.u.b, S.list, nlist, lane, self, xhv, xlv, omx, A);
 
-    double vx, vy, vz;
-    if (PREC == 0) {
-        vx = A.ax;
-        vy = A.ay;
-        vz = A.az;
-    } else if (PREC == 1) {
-        vx = (double)A.sx + (double)A.cx;
-        vy = (double)A.sy + (double)A.cy;
-        vz = (double)A.sz + (double)A.cz;
-    } else {
-        vx = A.dx;
-        vy = A.dy;
-        vz = A.dz;
-    }
-    vx = wave_sum_f64(vx);
-    vy = wave_sum_f64(vy);
-    vz = wave_sum_f64(vz);
-    const unsigned long long hits = wave_sum_u64(A.hits);
-    const unsigned long long rts = wave_sum_u64((unsigned long long)A.retests);
-    unsigned long long lr[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) lr[k] = LEARNED ? wave_sum_u64(n_by_rule[k]) : 0;
-    if (lane == 0) {
-        rtv[self] = vx;
-        rtv[m.npad + self] = vy;
-        rtv[2 * m.npad + self] = vz;
-        if (cnt) {
-            atomicAdd(&cnt[2], A.pairs);
-            atomicAdd(&cnt[3], hits);
-            atomicAdd(&cnt[4], rts);
-            if (LEARNED)
-                for (int k = 0; k < 3; ++k) atomicAdd(&cnt[5 + k], lr[k]);
+        double vx, vy, vz;
+        if (PREC == 0) {
+            vx = A.ax;
+            vy = A.ay;
+            vz = A.az;
+        } else if (PREC == 1) {
+            vx = (double)A.sx + (double)A.cx;
+            vy = (double)A.sy + (double)A.cy;
+            vz = (double)A.sz + (double)A.cz;
+        } else {
+            vx = A.dx;
+            vy = A.dy;
+            vz = A.dz;
         }
+        vx = wave_sum_f64(vx);
+        vy = wave_sum_f64(vy);
+        vz = wave_sum_f64(vz);
+        const unsigned long long hits = wave_sum_u64(A.hits);
+        const unsigned long long rts = wave_sum_u64((unsigned long long)A.retests);
+        unsigned long long lr[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) lr[k] = LEARNED ? wave_sum_u64(n_by_rule[k]) : 0;
+        if (lane == 0) {
+            rtv[self] = vx;
+            rtv[m.npad + self] = vy;
+            rtv[2 * m.npad + self] = vz;
+            if (cnt) {
+                atomicAdd(&cnt[2], A.pairs);
+                atomicAdd(&cnt[3], hits);
+                atomicAdd(&cnt[4], rts);
+                if (LEARNED)
+                    for (int k = 0; k < 3; ++k) atomicAdd(&cnt[5 + k], lr[k]);
+            }
+        }
+        __syncthreads(); // the next node reuses the shared arrays
     }
 }
 
@@ -2250,8 +2260,9 @@ hipError_t launch_rt(const DevMesh &m, const Thresholds &th, const AngTab &ang, 
 {
     if (m.n == 0) return hipSuccess;
     const bool L = lp.net != nullptr;
+    const int grid = node_list ? std::min(m.n, kRtListGrid) : m.n;
 #define BS_RT(P, LL)                                                                                               \
-    hipLaunchKernelGGL((k_rt<P, LL>), dim3(m.n), dim3(64), 0, s, m, th, ang, lp, all_pairs, rtv, cnt, node_list,  \
+    hipLaunchKernelGGL((k_rt<P, LL>), dim3(grid), dim3(64), 0, s, m, th, ang, lp, all_pairs, rtv, cnt, node_list, \
                        node_count)
     if (precision == 0) {
         if (L) BS_RT(0, true); else BS_RT(0, false);
