@@ -774,7 +774,7 @@ constexpr int kBandPiece = 32;
 struct BandPieceLds {
     float4 cen[kBandPiece];     // centroid (x, y, z, 0)
     float4 pa[kBandPiece][4];   // G4 point q: position, W.x
-    float2 pb[kBandPiece][4];   // G4 point q: W.y, W.z
+    float4 pb[kBandPiece][2];   // G4 points 2e, 2e + 1: W.y, W.z of each
 };
 
 template <int PREC>
@@ -827,9 +827,8 @@ __global__ void __launch_bounds__(64 * kBandWaves) k_band_piece(DevMesh m, Thres
         const int p0 = c0, pn = min(kBandPiece, c1 - c0);
         if (h == 0) P[wave].cen[k] = make_float4(rc.x, rc.y, rc.z, 0.f);
         P[wave].pa[k][2 * h] = ra0;
-        P[wave].pb[k][2 * h] = rb0;
         P[wave].pa[k][2 * h + 1] = ra1;
-        P[wave].pb[k][2 * h + 1] = rb1;
+        P[wave].pb[k][h] = make_float4(rb0.x, rb0.y, rb1.x, rb1.y);
         // the next piece: the rest of this row, else this wave's next row
         if (c0 + kBandPiece < c1) {
             c0 += kBandPiece;
@@ -863,11 +862,13 @@ __global__ void __launch_bounds__(64 * kBandWaves) k_band_piece(DevMesh m, Thres
             const bool in4 = valid && !near && d2 < th.g4_2 && !(d2 < th.g11_2);
             if (in4) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float4 a = P[wave].pa[j][q];
-                    const float2 b = P[wave].pb[j][q];
-                    const float g[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
-                    gauss_point(x, y, z, g, ax, ay, az);
+                for (int e = 0; e < 2; ++e) {
+                    const float4 b = P[wave].pb[j][e];
+                    const float4 a0 = P[wave].pa[j][2 * e], a1 = P[wave].pa[j][2 * e + 1];
+                    const float g0[6] = {a0.x, a0.y, a0.z, a0.w, b.x, b.y};
+                    const float g1[6] = {a1.x, a1.y, a1.z, a1.w, b.z, b.w};
+                    gauss_point(x, y, z, g0, ax, ay, az);
+                    gauss_point(x, y, z, g1, ax, ay, az);
                 }
                 ++n4;
             }
