@@ -213,6 +213,9 @@ struct bs_mesh {
     std::vector<float> h_cen32;                         // binary32 centroids, input tet order
     std::vector<float> h_xh;                            // binary32 node coordinates, input node order
     std::vector<int32_t> nbr_in;  // [T][4] face neighbours (input tet numbering, -1 boundary)
+    std::vector<int64_t> edge_keys; // unique edges, sorted (lo * (n + 1) + hi); built on first use
+    std::vector<float> h_g1, h_g4, h_g11; // host staging of the Gauss records (reused between builds)
+    std::vector<int4> h_tid;
     bool manifold = true;         // every face shared by at most two tets
     bool convex = false;          // boundary is one closed, locally convex surface (rays never re-enter)
     bsk::Bins bins{};
@@ -267,27 +270,50 @@ int check_device(int *dev)
 
 // Mean edge length over unique edges: keys (min id, max id) of the input
 // numbering, lengths summed in increasing key order.
-double mean_edge(int64_t n, const double *xyz, int64_t T, const int32_t *tets)
+// Mean length of the unique edges, summed in the order of their sorted keys.
+// The edge set depends on the connectivity alone, fixed for the mesh's
+// lifetime, so it is sorted once and kept (moving the nodes, as every
+// stage of the Lagrangian step does, only re-measures the lengths).
+double mean_edge(bs_mesh *m)
 {
-    static const int ea[6] = {0, 0, 0, 1, 1, 2}, eb[6] = {1, 2, 3, 2, 3, 3};
-    std::vector<int64_t> keys((size_t)(6 * T));
-    for (int64_t t = 0; t < T; ++t)
-        for (int e = 0; e < 6; ++e) {
-            const int64_t a = tets[4 * t + ea[e]], b = tets[4 * t + eb[e]];
-            keys[(size_t)(6 * t + e)] = std::min(a, b) * (n + 1) + std::max(a, b);
+    const int64_t n = m->n, T = m->T;
+    const int32_t *tets = m->tets.data();
+    const double *xyz = m->xyz.data();
+    if (m->edge_keys.empty() && T > 0) {
+        // sorted by the smaller node (a counting sort), then by the larger
+        // within each node's few edges: the order of a full sort of the keys
+        static const int ea[6] = {0, 0, 0, 1, 1, 2}, eb[6] = {1, 2, 3, 2, 3, 3};
+        std::vector<int64_t> start((size_t)n + 1, 0);
+        for (int64_t t = 0; t < T; ++t)
+            for (int e = 0; e < 6; ++e) start[(size_t)std::min(tets[4 * t + ea[e]], tets[4 * t + eb[e]]) + 1]++;
+        for (int64_t i = 0; i < n; ++i) start[(size_t)i + 1] += start[(size_t)i];
+        std::vector<int32_t> hi((size_t)(6 * T));
+        {
+            std::vector<int64_t> fill(start.begin(), start.end() - 1);
+            for (int64_t t = 0; t < T; ++t)
+                for (int e = 0; e < 6; ++e) {
+                    const int32_t a = tets[4 * t + ea[e]], b = tets[4 * t + eb[e]];
+                    hi[(size_t)fill[(size_t)std::min(a, b)]++] = std::max(a, b);
+                }
         }
-    std::sort(keys.begin(), keys.end());
+        std::vector<int64_t> keys;
+        keys.reserve((size_t)(6 * T) / 2);
+        for (int64_t i = 0; i < n; ++i) {
+            int32_t *b0 = hi.data() + start[(size_t)i], *b1 = hi.data() + start[(size_t)i + 1];
+            std::sort(b0, b1);
+            for (int32_t *p = b0; p < b1; ++p)
+                if (p == b0 || *p != p[-1]) keys.push_back(i * (n + 1) + *p);
+        }
+        m->edge_keys.swap(keys);
+    }
     double sum = 0.0;
-    int64_t cnt = 0;
-    for (size_t i = 0; i < keys.size(); ++i) {
-        if (i > 0 && keys[i] == keys[i - 1]) continue;
-        const int64_t lo = keys[i] / (n + 1), hi = keys[i] % (n + 1);
+    for (const int64_t key : m->edge_keys) {
+        const int64_t lo = key / (n + 1), hi = key % (n + 1);
         const double dx = xyz[3 * hi] - xyz[3 * lo], dy = xyz[3 * hi + 1] - xyz[3 * lo + 1],
                      dz = xyz[3 * hi + 2] - xyz[3 * lo + 2];
         sum += std::sqrt(dx * dx + dy * dy + dz * dz);
-        ++cnt;
     }
-    return cnt ? sum / (double)cnt : 0.0;
+    return m->edge_keys.empty() ? 0.0 : sum / (double)m->edge_keys.size();
 }
 
 int validate_geometry(bs_mesh *m)
@@ -350,18 +376,34 @@ void build_neighbours(bs_mesh *m)
         int32_t a, b, c;
         int64_t tf;
     };
-    std::vector<FK> fk((size_t)(4 * T));
+    // faces in the order of (a, b, c, tf): a counting sort by the smallest
+    // node a, then a sort of each node's few faces
+    const int64_t n = m->n;
+    std::vector<int64_t> start((size_t)n + 1, 0);
     for (int64_t t = 0; t < T; ++t)
         for (int f = 0; f < 4; ++f) {
-            int32_t v[3], k = 0;
+            int32_t a = INT32_MAX;
             for (int j = 0; j < 4; ++j)
-                if (j != f) v[k++] = m->tets[(size_t)(4 * t + j)];
-            std::sort(v, v + 3);
-            fk[(size_t)(4 * t + f)] = {v[0], v[1], v[2], 4 * t + f};
+                if (j != f) a = std::min(a, m->tets[(size_t)(4 * t + j)]);
+            start[(size_t)a + 1]++;
         }
-    std::sort(fk.begin(), fk.end(), [](const FK &x, const FK &y) {
-        return x.a != y.a ? x.a < y.a : x.b != y.b ? x.b < y.b : x.c != y.c ? x.c < y.c : x.tf < y.tf;
-    });
+    for (int64_t i = 0; i < n; ++i) start[(size_t)i + 1] += start[(size_t)i];
+    std::vector<FK> fk((size_t)(4 * T));
+    {
+        std::vector<int64_t> fill(start.begin(), start.end() - 1);
+        for (int64_t t = 0; t < T; ++t)
+            for (int f = 0; f < 4; ++f) {
+                int32_t v[3], k = 0;
+                for (int j = 0; j < 4; ++j)
+                    if (j != f) v[k++] = m->tets[(size_t)(4 * t + j)];
+                std::sort(v, v + 3);
+                fk[(size_t)fill[(size_t)v[0]]++] = {v[0], v[1], v[2], 4 * t + f};
+            }
+    }
+    for (int64_t i = 0; i < n; ++i)
+        std::sort(fk.begin() + start[(size_t)i], fk.begin() + start[(size_t)i + 1], [](const FK &x, const FK &y) {
+            return x.b != y.b ? x.b < y.b : x.c != y.c ? x.c < y.c : x.tf < y.tf;
+        });
     for (size_t i = 0; i < fk.size();) {
         size_t j = i + 1;
         while (j < fk.size() && fk[j].a == fk[i].a && fk[j].b == fk[i].b && fk[j].c == fk[i].c) ++j;
@@ -528,7 +570,7 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
     m->vel_valid = false;
     const int64_t n = m->n, T = m->T;
     const double *X = m->xyz.data(), *W = m->omega.data();
-    m->hbar = T > 0 ? mean_edge(n, X, T, m->tets.data()) : 0.0;
+    m->hbar = T > 0 ? mean_edge(m) : 0.0;
 
     // ---- nodes ordered by a k-d split into leaves of 64 (one band-kernel
     // block per leaf); evaluation points (bs_eval_points) follow the nodes
@@ -647,8 +689,16 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
     for (int64_t i = 0; i < 3 * n; ++i) m->h_xh[(size_t)i] = (float)X[i];
 
     // ---- per-tet records in bin order
-    std::vector<float> g1((size_t)T * 8), g4((size_t)T * 32), g11((size_t)T * 88);
-    std::vector<int4> tid((size_t)T);
+    // host staging of the records, kept between builds (every element is
+    // rewritten below): moving the nodes rebuilds them at each Lagrangian
+    // stage, and fresh multi-GB vectors cost more to zero and fault in than
+    // to fill
+    std::vector<float> &g1 = m->h_g1, &g4 = m->h_g4, &g11 = m->h_g11;
+    std::vector<int4> &tid = m->h_tid;
+    g1.resize((size_t)T * 8);
+    g4.resize((size_t)T * 32);
+    g11.resize((size_t)T * 88);
+    tid.resize((size_t)T);
     const TetRule R1 = tet_rule(1), R4 = tet_rule(4), R11 = tet_rule(11);
     parallel_for(T, [&](int64_t a, int64_t b) {
         for (int64_t k = a; k < b; ++k) {
