@@ -825,6 +825,15 @@ __global__ void __launch_bounds__(64 * kBandWaves) k_band_piece(DevMesh m, Thres
     if (have) BAND_FETCH();
     while (have) {
         const int p0 = c0, pn = min(kBandPiece, c1 - c0);
+        // the piece's tets within the scan radius of the block sphere (the
+        // bin rows overreach it by about a quarter): no node of the block can
+        // take any other by G4 or G11
+        unsigned live;
+        {
+            const float qx = rc.x - bc.x, qy = rc.y - bc.y, qz = rc.z - bc.z;
+            const float rs = (th.r_band + bc.w) * (1.f + 1e-5f);
+            live = (unsigned)__ballot(h == 0 && k < pn && (qx * qx + qy * qy) + qz * qz < rs * rs);
+        }
         if (h == 0) P[wave].cen[k] = make_float4(rc.x, rc.y, rc.z, 0.f);
         P[wave].pa[k][2 * h] = ra0;
         P[wave].pa[k][2 * h + 1] = ra1;
@@ -847,7 +856,8 @@ __global__ void __launch_bounds__(64 * kBandWaves) k_band_piece(DevMesh m, Thres
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         float ax = 0.f, ay = 0.f, az = 0.f;
-        for (int j = 0; j < pn; ++j) {
+        for (; live; live &= live - 1u) {
+            const int j = __builtin_ctz(live);
             const int t = p0 + j;
             const float4 c = P[wave].cen[j];
             const float ex = x - c.x, ey = y - c.y, ez = z - c.z;
