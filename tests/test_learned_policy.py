@@ -73,10 +73,19 @@ def gpu_learned(bs, m, bits, conf_min):
     return v, st
 
 
-def test_learned_policy_matches_oracle(bs, selector):
+def _ball():
+    """A non-convex mesh (the cube's cells clipped to a ball): no walk, the
+    candidate kernel with the selector inside it takes every node."""
+    b = W.ball_mesh(cells=8)
+    b.omega = W.field_gaussian_swirl(b.xyz)
+    return b
+
+
+@pytest.mark.parametrize("name", ["C1", "ball"])
+def test_learned_policy_matches_oracle(bs, selector, name):
     bits, p, conf_min = selector
-    m = W.make_config("C1")
-    print(f"learned policy on C1, conf_min {conf_min}", flush=True)
+    m = W.make_config("C1") if name == "C1" else _ball()
+    print(f"learned policy on {name} ({m.xyz.shape[0]} nodes), conf_min {conf_min}", flush=True)
     v_ora, pr, (aK, aT, arule, aalt), tg = oracle_learned(m, p, conf_min)
     v_gpu, st = gpu_learned(bs, m, bits, conf_min)
     counts = np.bincount(pr.ravel(), minlength=4)
