@@ -498,11 +498,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
             const float4 v0 = *(const float4 *)&S.c.a2[buf][tile][c4][q][0];
             const float4 v1 = *(const float4 *)&S.c.a2[buf][tile][c4][q][4];
             const float A2[4][2] = {{v0.x, v0.y}, {v0.z, v0.w}, {v1.x, v1.y}, {v1.z, v1.w}};
+            // the matrix core and the vector ALUs of a SIMD do not overlap
+            // here (each MFMA group costs its full pipe time), so a wave at
+            // its MFMAs is given issue priority over the waves at vector work
+            // and the matrix pipe runs its groups back to back
             f32x4 r2[4];
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt)
                 r2[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A1, B1[nt], (f32x4){Cin[nt], Cin[nt], Cin[nt], Cin[nt]},
                                                              0, 0, 0);
+            __builtin_amdgcn_s_setprio(0);
             float sv[4][4];
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt)
@@ -545,6 +551,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 #pragma unroll
                 for (int j = 0; j < 4; ++j) sv[nt][j] = g1[j] ? sv[nt][j] : 0.f;
             }
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -552,6 +559,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                     D0[nt] = __builtin_amdgcn_mfma_f32_4x4x1f32(A2[j][0], sv[nt][j], D0[nt], 0, 0, 0);
                     D1[nt] = __builtin_amdgcn_mfma_f32_4x4x1f32(A2[j][1], sv[nt][j], D1[nt], 0, 0, 0);
                 }
+            __builtin_amdgcn_s_setprio(0);
         }
         if (PREC == 1 && (k & 1)) fold();
         __syncthreads();
