@@ -517,6 +517,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                     const float iv = __builtin_amdgcn_rsqf(r2[nt][j]);
                     sv[nt][j] = iv * iv * iv;
                 }
+            // (one branch skips the masks of a tet tile clear of every node tile's band)
+            if (blo | bhi)
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
                 if (!bmask[nt]) continue;
