@@ -407,14 +407,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     };
     auto store = [&](int buf) {
         const int tile = tid >> 4, i = tid & 15, qq = i >> 2, j = i & 3;
+        // a slot past the split keeps the clamped tet's position (finite
+        // operands) with zero strength and |p'|^2 = 1e30: its terms are 0
         const bool pok = pt < t1;
-        float pr[6] = {pg.x, pg.y, pg.z, pg.w, pw.x, pw.y};
-        if (!pok) {
-            pr[0] = bc.x;
-            pr[1] = bc.y;
-            pr[2] = bc.z;
-            pr[3] = pr[4] = pr[5] = 0.f;
-        }
+        const float pr[6] = {pg.x, pg.y, pg.z, pok ? pg.w : 0.f, pok ? pw.x : 0.f, pok ? pw.y : 0.f};
         const float px = pr[0] - bc.x, py = pr[1] - bc.y, pz = pr[2] - bc.z;
         const float n2 = (px * px + py * py) + pz * pz;
         S.c.a1[buf][tile][i] = -2.f * px;
