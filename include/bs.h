@@ -92,10 +92,10 @@ typedef struct bs_mesh bs_mesh; /* opaque; owns all device memory */
 /* Mesh description.  Nodes are both the vertices of the tetrahedra and the
  * points where the velocity is wanted (Section 2). */
 typedef struct {
-    int64_t n_nodes;      /* >= 1                                              */
+    int64_t n_nodes;      /* >= 1, at most 2^29                                */
     const double *xyz;    /* [n_nodes][3] coordinates                          */
     const double *omega;  /* [n_nodes][3] nodal vorticity                      */
-    int64_t n_tets;       /* >= 0                                              */
+    int64_t n_tets;       /* >= 0, at most 2^29                                */
     const int32_t *tets;  /* [n_tets][4] node indices                          */
     uint32_t flags;       /* BS_PTR_DEVICE: xyz, omega, tets are device memory */
     void *stream;         /* hipStream_t or NULL                               */
@@ -104,7 +104,8 @@ typedef struct {
 /* Validate and copy a mesh to the device, and run the O(n_tets) per-element
  * precompute (orientation, volume, centroid, rule points and strengths,
  * ray-tracing records, spatial bins).  Errors: BS_E_ARG (null pointers,
- * n_nodes < 1, n_tets < 0), BS_E_INDEX (index outside [0, n_nodes) or
+ * n_nodes outside [1, 2^29], n_tets outside [0, 2^29]: the kernels
+ * index the node arrays in 32 bits), BS_E_INDEX (index outside [0, n_nodes) or
  * repeated within a tet; bs_last_error names the tet), BS_E_NONFINITE,
  * BS_E_DEGENERATE (|6 V| <= 1e-12 h_T^3, h_T its longest edge), BS_E_DEVICE,
  * BS_E_NOMEM.  On success *out holds a new mesh with the default policy. */
@@ -187,7 +188,8 @@ int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, 
  * mesh sees only whole chords.  The points are kept with the mesh (a new
  * set re-runs the per-element precompute once; the nodes' own evaluation is
  * unaffected); n_pts = 0 clears them.  Errors: BS_E_STATE (NULL mesh),
- * BS_E_ARG (n_pts < 0 or above 2^28, NULL pointer, unknown flag),
+ * BS_E_ARG (n_pts < 0 or above 2^28, or n_nodes rounded up to a multiple
+ * of 1024 plus n_pts above 2^29; NULL pointer, unknown flag),
  * BS_E_NONFINITE (a coordinate), BS_E_DEVICE. */
 int bs_eval_points(bs_mesh *m, int64_t n_pts, const double *pts, double *vel, uint32_t flags, void *stream,
                    bs_stats *st);

@@ -167,6 +167,15 @@ void parallel_for(int64_t n, F &&f)
     for (auto &t : th) t.join();
 }
 
+// Node slots (nodes, then evaluation points from the next multiple of 1024,
+// padded to a multiple of 1024) are indexed in 32-bit int by the kernels as
+// c * npad + i for c < 3: 3 * 2^29 stays below 2^31.  The tet count is held
+// below 2^29 so that the CSR of incident tets (4 per tet) fits int32.
+constexpr int64_t kMaxNodeSlots = (int64_t)1 << 29;
+constexpr int64_t kMaxTets = (int64_t)1 << 29;
+
+inline int64_t round_up_1024(int64_t v) { return ((v + 1023) / 1024) * 1024; }
+
 struct DBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -1049,8 +1058,10 @@ int bs_mesh_upload(const bs_mesh_desc *d, bs_mesh **out)
     if (d->n_nodes < 1 || d->n_tets < 0) return fail(BS_E_ARG, "n_nodes must be >= 1 and n_tets >= 0");
     if (!d->xyz || !d->omega || (d->n_tets > 0 && !d->tets)) return fail(BS_E_ARG, "null input array");
     if (d->flags & ~BS_PTR_DEVICE) return fail(BS_E_ARG, "unknown flags 0x%x", d->flags);
-    if (d->n_nodes > (int64_t)1 << 30 || d->n_tets > (int64_t)1 << 30)
-        return fail(BS_E_ARG, "mesh too large for 32-bit indexing");
+    if (round_up_1024(d->n_nodes) > kMaxNodeSlots || d->n_tets > kMaxTets)
+        return fail(BS_E_ARG, "mesh too large for 32-bit indexing (n_nodes %lld, n_tets %lld; limits %lld, %lld)",
+                    (long long)d->n_nodes, (long long)d->n_tets, (long long)kMaxNodeSlots,
+                    (long long)kMaxTets);
     // device inputs need the device before anything can be validated
     int dev = -1, rc;
     if ((d->flags & BS_PTR_DEVICE) && (rc = check_device(&dev))) return rc;
@@ -1472,7 +1483,8 @@ int bs_eval_points(bs_mesh *m, int64_t n_pts, const double *pts, double *vel, ui
     g_err.clear();
     if (!m) return fail(BS_E_STATE, "null mesh");
     if (n_pts < 0 || (n_pts > 0 && (!pts || !vel))) return fail(BS_E_ARG, "n_pts < 0 or null pointer");
-    if (n_pts > (int64_t)1 << 28) return fail(BS_E_ARG, "too many points (%lld)", (long long)n_pts);
+    if (n_pts > (int64_t)1 << 28 || round_up_1024(m->n) + n_pts > kMaxNodeSlots)
+        return fail(BS_E_ARG, "too many points (%lld beside %lld nodes)", (long long)n_pts, (long long)m->n);
     if (flags & ~(BS_PTR_DEVICE | BS_EVAL_VALU_FAR | BS_EVAL_SERIAL)) return fail(BS_E_ARG, "unknown flags 0x%x", flags);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;

@@ -102,3 +102,18 @@ def test_valid_mesh_without_device_reports_device_error():
     m = W.make_config("C1", scale=(2, 2, 2))
     rc, msg = _upload_status(m.xyz, m.omega, m.tets)
     assert rc == bs.BS_E_DEVICE, msg
+
+
+def test_upload_rejects_meshes_beyond_32_bit_node_indexing():
+    """The kernels index the node arrays as c * npad + i in 32 bits, so the
+    library refuses more than 2^29 node slots and 2^29 tets before reading
+    any array (the pointers here cover one node only)."""
+    L = bs.load_library()
+    xyz = np.zeros((1, 3))
+    tets = np.zeros((1, 4), dtype=np.int32)
+    for n_nodes, n_tets in (((1 << 29) + 1, 1), (1 << 30, 1), (4, (1 << 29) + 1)):
+        d = bs.MeshDesc(n_nodes, xyz.ctypes.data, xyz.ctypes.data, n_tets, tets.ctypes.data, 0, None)
+        h = ctypes.c_void_p()
+        assert L.bs_mesh_upload(ctypes.byref(d), ctypes.byref(h)) == bs.BS_E_ARG
+        assert "32-bit" in L.bs_last_error().decode()
+        assert not h.value
