@@ -1,20 +1,33 @@
 """Benchmark: node-tet pair evaluations per second on one MI355X.
 
-One step = one bs_eval_velocity on the vortex-ring workload (a
-[-1.5,1.5]^2 x [-0.5,0.5] box, 64 x 64 x 22 Kuhn-split cells: 97,175 nodes,
-540,672 tetrahedra, jitter 0.15 h; Gaussian-core ring, radius 1, sigma 0.1;
-fixed distance rule with ray tracing below 2 mean edge lengths, 16 x 16
-angular rule, FP32 with compensated accumulation).  Inputs are resident in
-HBM before the timed region; the output goes to device memory.
+One step = one bs_eval_velocity on the two-ring workload (a [-1.5,1.5]^3
+box, 80^3 Kuhn-split cells: 531,441 nodes, 3,072,000 tetrahedra, jitter
+0.2 h; two coaxial Gaussian-core rings, radii 1.0 and 0.8, sigma 0.08) with
+the learned rule selector (trained first on the GPU by the library's own
+kernels, outside the timed region), 16 x 16 angular rule, FP32 with
+compensated accumulation.  Inputs are resident in HBM before the timed
+region; the output goes to device memory.
 
-Prints one JSON line (see the keys below).  The timed steps run the band
-and ray-tracing kernels beside the far field (library streams); a second
-pass of the same steps with every kernel on one stream gives each kernel's
-own duration (HIP events recorded on its launch stream inside the library),
-from which the roofline objects of the three kernels are computed
-("roofline" is the longest of them, "roofline_kernels" lists all).  cpu_baseline
-times the FP64 oracle on a bounded sample of nodes (all tetrahedra) on the
-host's cores.
+Besides the headline, the same JSON line carries:
+  fixed       the fixed distance rule (RT < 2 hbar, G11 < 4, G4 < 8, else G1)
+              on the same mesh;
+  accuracy    rel-L2 error of each policy at stored probe nodes against the
+              exact velocity of the piecewise-linear vorticity
+              (tests/golden/probe_exact_<workload>.json, written by a script
+              that runs the FP64 oracle's references), and a ladder of fixed
+              settings (cuts, lines) timed beside the learned policy: the
+              speed ratio to the fastest fixed setting whose error is not
+              above the learned policy's is "vs_fixed_equal_accuracy";
+  valu_far    the fixed rule with the far field on the vector ALUs
+              (k_gauss_all, the design without matrix cores) and its roofline;
+  c2          the vortex-ring workload (97,175 nodes x 540,672 tets): fixed
+              and learned timings and errors;
+  lagrangian  Heun steps of the two-ring run with the learned policy
+              (bs_advect_heun: mesh rebuild, two evaluations per step);
+  roofline    the longest kernel of the headline step alone (HIP events on
+              its launch stream in a pass with every kernel on one stream),
+              "roofline_kernels" lists far field, band and ray tracing;
+  cpu_baseline  the FP64 oracle on a bounded sample of nodes x all tets.
 """
 from __future__ import annotations
 
@@ -32,6 +45,11 @@ import numpy as np  # noqa: E402
 
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector: 256 CUs x 2.4 GHz x 256 flop/clk
 FLOPS_PER_POINT = 26.0     # one Gauss point: 3 sub, |r|^2 (5), rsqrt (1), r^-3 (2), W x r / r^3 + acc (15)
+DEFAULT_CUTS = (2.0, 4.0, 8.0)
+# fixed settings (near cut, G11 cut, G4 cut, lines per angle) timed for the
+# equal-accuracy comparison: narrower ray-traced zones and more lines are
+# more accurate at 16 x 16 and above
+LADDER = ((1.5, 4.0, 8.0, 24), (1.5, 4.0, 8.0, 32), (1.0, 4.0, 8.0, 24), (2.0, 4.0, 8.0, 32), (2.0, 4.0, 8.0, 48))
 
 
 def algorithmic_flops(st, nm):
@@ -49,16 +67,16 @@ WORKLOAD_TEXT = {
 }
 
 
-def measured_traffic(kernel, workload, precision):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None when the kernel source has changed since the counters were
-    taken (the summary records the sha256 of that source) or the run is not
-    the profiled configuration."""
+def measured_traffic(kernel, workload, policy, precision):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    of this workload and policy, or None when the kernel source has changed
+    since the counters were taken (the summary records the sha256 of that
+    source) or the run is not a profiled configuration."""
     import hashlib
 
-    if workload != "C2" or precision != 1:
+    if precision != 1:
         return None
-    path = os.path.join(ROOT, "profiles", "bs_eval_velocity_C2_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"bs_eval_velocity_{workload}_hbm_traffic.md")
     src = os.path.join(ROOT, "paper_0712_1695_amd", "csrc", "bs_kernels.hip")
     try:
         lines = open(path).read().split("\n")
@@ -67,8 +85,8 @@ def measured_traffic(kernel, workload, precision):
         return None
     for ln in lines:
         f = ln.split()
-        if len(f) == 4 and f[0] == "traffic" and f[1] == kernel and f[3] == sha:
-            return float(f[2])
+        if len(f) == 5 and f[0] == "traffic" and f[1] == policy and f[2] == kernel and f[4] == sha:
+            return float(f[3])
     return None
 
 
@@ -106,19 +124,128 @@ def cpu_baseline(mesh, target_seconds=15.0):
                       f"{dt:.1f} s"}
 
 
+def load_probes(workload):
+    """Probe nodes and their exact velocities (stored reference), or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"probe_exact_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    doc = json.load(open(path))
+    return np.array(doc["nodes"], dtype=np.int64), np.array(doc["velocity"], dtype=np.float64)
+
+
+class Bench:
+    """One uploaded workload with helpers that time evaluations on it."""
+
+    def __init__(self, bs, torch, mesh, precision):
+        self.bs, self.torch, self.mesh, self.precision = bs, torch, mesh, precision
+        dev = torch.device("cuda", 0)
+        self.h = bs.bs_mesh_upload(torch.tensor(mesh.xyz, device=dev), torch.tensor(mesh.omega, device=dev),
+                                   torch.tensor(mesh.tets, device=dev))
+        self.out = torch.empty((mesh.n_nodes, 3), dtype=torch.float64, device=dev)
+        self.pairs = mesh.n_nodes * mesh.n_tets
+        self.probes = None
+
+    def set_policy(self, **kw):
+        self.bs.bs_set_policy(self.h, precision=self.precision, **kw)
+
+    def time(self, steps, warmup, **flags):
+        """Wall time per evaluation over `steps` after `warmup` (seconds)."""
+        bs, torch = self.bs, self.torch
+        for _ in range(warmup):
+            bs.bs_eval_velocity(self.h, out=self.out, **flags)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            bs.bs_eval_velocity(self.h, out=self.out, **flags)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / max(steps, 1)
+
+    def kernels(self, steps, **flags):
+        """Mean per-kernel seconds [far, band, ray tracing, sum] with every
+        kernel on one stream, the stats of the last pass and its wall time
+        per evaluation."""
+        bs, torch = self.bs, self.torch
+        kern = np.zeros(4)
+        st = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(max(steps, 1)):
+            _, st = bs.bs_eval_velocity(self.h, out=self.out, stats=True, serial=True, **flags)
+            kern += np.array(st["t_kernel_s"])
+        torch.cuda.synchronize()
+        return kern / max(steps, 1), st, (time.perf_counter() - t0) / max(steps, 1)
+
+    def stats(self, **flags):
+        return self.bs.bs_eval_velocity(self.h, out=self.out, stats=True, **flags)[1]
+
+    def error(self):
+        """rel-L2 error of the last evaluation at the probe nodes."""
+        if self.probes is None:
+            return None
+        nodes, exact = self.probes
+        v = self.out[self.torch.as_tensor(nodes, device=self.out.device)].cpu().numpy()
+        return float(np.linalg.norm(v - exact) / np.linalg.norm(exact))
+
+    def free(self):
+        self.bs.bs_mesh_free(self.h)
+
+
+def roof_entry(name, what, bound, kflops, t, workload, policy, precision):
+    return {"kernel": f"{name} ({what})", "bound": bound, "achieved": kflops / t / 1e12,
+            "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": kflops / t / 1e12 / FP32_PEAK_TFLOPS,
+            "traffic": measured_traffic(name, workload, policy, precision),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "avg_duration_ms": t * 1e3,
+            "measured": "kernel alone: the serial pass (every kernel on one stream), HIP events on its stream"}
+
+
+def kernel_rooflines(st, kern, nm, workload, policy, precision, valu_far=False):
+    g1, g4, g11, rtp = st["pairs_by_rule"]
+    far_name = "k_gauss_all" if (valu_far or precision == 2) else "k_far_mfma"
+    band_name = "k_band" if far_name == "k_gauss_all" else "k_band_piece"
+    rt_what = ("learned selection pass and ray tracing by walking face neighbours; the method's flops of "
+               "the ray-traced pairs" if policy == "learned"
+               else "ray tracing by walking face neighbours; the method's flops of its pairs")
+    rt_name = "k_select+k_rt_walk" if policy == "learned" else "k_rt_walk"
+    return [
+        roof_entry(far_name, "far field, 1-point rule on every pair, vector ALUs" if far_name == "k_gauss_all"
+                   else "far field, the G1 pairs, FP32 matrix-core contractions",
+                   "alu" if far_name == "k_gauss_all" else "mfma", FLOPS_PER_POINT * g1, kern[0],
+                   workload, policy, precision),
+        roof_entry(band_name, "the G4 and G11 pairs, vector ALUs", "alu", FLOPS_PER_POINT * (4 * g4 + 11 * g11),
+                   kern[1], workload, policy, precision),
+        roof_entry(rt_name, rt_what, "alu", rtp * (9.0 + 7.0 * nm) + 156.0 * st["rt_hit_lines"], kern[2],
+                   workload, policy, precision),
+    ]
+
+
+def train_selector(W):
+    """The learned policy's network, trained on the GPU (outside any timed
+    region) on pairs of the swirl box and the ring box at half resolution."""
+    from paper_0712_1695_amd import selector
+
+    train_meshes = [W.make_config("C1"), W.make_config("C2", scale=(32, 32, 11))]
+    blob, info = selector.train([(t.xyz, t.omega, t.tets) for t in train_meshes])
+    info["trained_on"] = [t.name for t in train_meshes]
+    return blob, info
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="C2")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="C5")
+    ap.add_argument("--policy", default="learned", choices=["learned", "fixed"],
+                    help="policy of the headline step")
     ap.add_argument("--precision", type=int, default=1)
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned-policy leg")
-    ap.add_argument("--serial", action="store_true",
-                    help="time the steps with every kernel on one stream too (for per-kernel profiles)")
+    ap.add_argument("--quick", action="store_true",
+                    help="headline step, its per-kernel pass and the fixed leg only (profiling runs)")
+    ap.add_argument("--serial", action="store_true", help="time the headline steps with every kernel on one stream")
     ap.add_argument("--valu-far", action="store_true",
-                    help="far field on the vector ALUs instead of the matrix cores (comparison)")
+                    help="headline far field on the vector ALUs instead of the matrix cores")
+    ap.add_argument("--heun-steps", type=int, default=10, help="Heun steps of the Lagrangian leg (0: skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (profiler byte-counter calibration)")
     args = ap.parse_args()
@@ -137,100 +264,32 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
-    dev = torch.device("cuda", 0)
-    mesh = W.make_config(args.workload)
-    xyz = torch.tensor(mesh.xyz, device=dev)
-    om = torch.tensor(mesh.omega, device=dev)
-    tets = torch.tensor(mesh.tets, device=dev)
-    h = bs.bs_mesh_upload(xyz, om, tets)
     nm = 16 * 16
-    bs.bs_set_policy(h, kind=bs.BS_POLICY_FIXED, n_phi=16, n_theta=16, precision=args.precision)
-    out = torch.empty((mesh.n_nodes, 3), dtype=torch.float64, device=dev)
-    stream = torch.cuda.current_stream()
+    t_start = time.perf_counter()
+    blob, sel_info = (train_selector(W) if (args.policy == "learned" or not args.quick) else (None, None))
+    learned_pol = dict(kind=bs.BS_POLICY_LEARNED, n_phi=16, n_theta=16, mlp_bf16=blob, conf_min=0.9)
+    fixed_pol = dict(kind=bs.BS_POLICY_FIXED, n_phi=16, n_theta=16)
+    head_pol = learned_pol if args.policy == "learned" else fixed_pol
+    flags = dict(valu_far=args.valu_far)
 
-    for _ in range(args.warmup):
-        bs.bs_eval_velocity(h, out=out, valu_far=args.valu_far)
-    torch.cuda.synchronize()
+    mesh = W.make_config(args.workload)
+    B = Bench(bs, torch, mesh, args.precision)
+    B.probes = load_probes(args.workload)
+    print(f"bench: {args.workload} {mesh.n_nodes} nodes x {mesh.n_tets} tets, {args.policy} policy", flush=True)
 
-    # the timed steps: band and ray tracing run beside the far field
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        bs.bs_eval_velocity(h, out=out, valu_far=args.valu_far, serial=args.serial)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    _, stats = bs.bs_eval_velocity(h, out=out, stats=True, valu_far=args.valu_far, serial=args.serial)
-    # the same steps with every kernel on one stream: each kernel's own
-    # duration (HIP events on its launch stream) for the roofline
-    kern = np.zeros(4)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, st_s = bs.bs_eval_velocity(h, out=out, stats=True, valu_far=args.valu_far, serial=True)
-        kern += np.array(st_s["t_kernel_s"])
-    torch.cuda.synchronize()
-    wall_serial = time.perf_counter() - t0
-    kern /= max(args.steps, 1)
+    # ---- the timed steps (the headline)
+    B.set_policy(**head_pol)
+    t_head = B.time(args.steps, args.warmup, serial=args.serial, **flags)
+    err_head = B.error()
+    st_head = B.stats(**flags)
+    kern, st_k, t_serial = B.kernels(args.steps, **flags)
+    value = B.pairs / t_head
+    print(f"bench: headline {t_head * 1e3:.2f} ms per evaluation", flush=True)
 
-    pairs = mesh.n_nodes * mesh.n_tets
-    ms = wall / args.steps * 1e3
-    value = pairs / (wall / args.steps)
-
-    learned = None
-    if not args.no_learned:
-        # the selector is trained on the GPU by the library's own kernels
-        # (outside the timed region), on pairs of two smaller meshes, then
-        # the same evaluation is timed with the learned policy
-        from paper_0712_1695_amd import selector
-
-        train_meshes = [W.make_config("C1"), W.make_config("C2", scale=(32, 32, 11))]
-        blob, info = selector.train([(t.xyz, t.omega, t.tets) for t in train_meshes])
-        conf_min = 0.9
-        bs.bs_set_policy(h, kind=bs.BS_POLICY_LEARNED, n_phi=16, n_theta=16, precision=args.precision,
-                         mlp_bf16=blob, conf_min=conf_min)
-        for _ in range(args.warmup):
-            bs.bs_eval_velocity(h, out=out, valu_far=args.valu_far)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            bs.bs_eval_velocity(h, out=out, valu_far=args.valu_far)
-        torch.cuda.synchronize()
-        wall_l = time.perf_counter() - t0
-        kl = np.zeros(4)
-        for _ in range(args.steps):
-            _, st_l = bs.bs_eval_velocity(h, out=out, stats=True, valu_far=args.valu_far, serial=True)
-            kl += np.array(st_l["t_kernel_s"])
-        kl /= max(args.steps, 1)
-        value_l = pairs / (wall_l / args.steps)
-        learned = {"value": value_l, "unit": "pairs/s", "ms_per_step": wall_l / args.steps * 1e3,
-                   "vs_fixed": value_l / value, "conf_min": conf_min, "pairs_by_rule": st_l["pairs_by_rule"],
-                   "rt_hit_lines": st_l["rt_hit_lines"],
-                   "kernel_ms_serial": {"far": kl[0] * 1e3, "band": kl[1] * 1e3, "rt": kl[2] * 1e3,
-                                        "sum": kl[3] * 1e3},
-                   "selector": {**info, "trained_on": [t.name for t in train_meshes]}}
-    flops = algorithmic_flops(stats, nm)
-    g1, g4, g11, rtp = stats["pairs_by_rule"]
-    far_name = "k_gauss_all" if (args.valu_far or args.precision == 2) else "k_far_mfma"
-    band_name = "k_band" if far_name == "k_gauss_all" else "k_band_piece"
-    measured = "kernel alone: the serial pass (every kernel on one stream), HIP events on its stream"
-
-    def roof_entry(name, what, bound, kflops, t):
-        return {"kernel": f"{name} ({what})", "bound": bound, "achieved": kflops / t / 1e12,
-                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": kflops / t / 1e12 / FP32_PEAK_TFLOPS,
-                "traffic": measured_traffic(name, args.workload, args.precision),
-                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "avg_duration_ms": t * 1e3, "measured": measured}
-
-    kernels = [
-        roof_entry(far_name, "far field, 1-point rule on every pair, vector ALUs" if far_name == "k_gauss_all"
-                   else "far field, the G1 pairs, FP32 matrix-core contractions",
-                   "alu" if far_name == "k_gauss_all" else "mfma", FLOPS_PER_POINT * g1, kern[0]),
-        roof_entry(band_name, "the G4 and G11 pairs, vector ALUs, lane = node" +
-                   ("" if band_name == "k_band" else ", row pieces staged in LDS"), "alu",
-                   FLOPS_PER_POINT * (4 * g4 + 11 * g11), kern[1]),
-        roof_entry("k_rt_walk", "ray tracing by walking face neighbours; the method's flops of its pairs", "alu",
-                   rtp * (9.0 + 7.0 * nm) + 156.0 * stats["rt_hit_lines"], kern[2]),
-    ]
-    # the dominant kernel: the longest one alone
+    flops = algorithmic_flops(st_head, nm)
+    kernels = kernel_rooflines(st_head, kern, nm, args.workload, args.policy, args.precision, args.valu_far)
     roof = dict(max(kernels, key=lambda r: r["avg_duration_ms"]))
+    cuts = "RT < 2 hbar, G11 < 4, G4 < 8, else G1"
     line = {
         "metric": "node-tet pair evals/s (+ % FP32 peak)",
         "value": value,
@@ -238,7 +297,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": t_head * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -246,25 +305,106 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: {WORKLOAD_TEXT.get(args.workload, mesh.name)}, {mesh.n_nodes} nodes x "
-                        f"{mesh.n_tets} tets, fixed rule (RT < 2 hbar, G11 < 4, G4 < 8, else G1), 16x16 lines, "
+                        f"{mesh.n_tets} tets, {args.policy} policy "
+                        f"({'selector on the pairs the fixed rule ray-traces, ' if args.policy == 'learned' else ''}"
+                        f"{cuts}), 16x16 lines, "
                         f"{['fp32 naive', 'fp32 compensated', 'fp64 accumulation'][args.precision]}",
-            "pairs_per_step": pairs,
-            "pairs_by_rule": stats["pairs_by_rule"],
-            "rt_hit_lines": stats["rt_hit_lines"],
+            "pairs_per_step": B.pairs,
+            "pairs_by_rule": st_head["pairs_by_rule"],
+            "rt_hit_lines": st_head["rt_hit_lines"],
             "algorithmic_tflop_per_step": flops / 1e12,
-            "path_fp32_peak_frac": flops / (wall / args.steps) / 1e12 / FP32_PEAK_TFLOPS,
-            "ms_per_step_serial": wall_serial / args.steps * 1e3,
+            "path_fp32_peak_frac": flops / t_head / 1e12 / FP32_PEAK_TFLOPS,
+            "ms_per_step_serial": t_serial * 1e3,
             "kernel_ms_serial": {"far": kern[0] * 1e3, "band": kern[1] * 1e3, "rt": kern[2] * 1e3,
                                  "sum": kern[3] * 1e3},
+            "probe_error": err_head,
         },
         "roofline": roof,
         "roofline_kernels": kernels,
     }
-    if learned is not None:
-        line["learned"] = learned
-    if not args.no_cpu_baseline:
+    if sel_info is not None:
+        line["config"]["selector"] = sel_info
+
+    # ---- the fixed rule on the same mesh
+    steps2 = max(2, args.steps // 2 + 1)
+    if args.policy == "learned":
+        B.set_policy(**fixed_pol)
+        t_fix = B.time(args.steps, args.warmup, **flags)
+        err_fix = B.error()
+        st_fix = B.stats(**flags)
+        kf, _, _ = B.kernels(steps2, **flags)
+        line["fixed"] = {"ms_per_step": t_fix * 1e3, "value": B.pairs / t_fix, "probe_error": err_fix,
+                         "pairs_by_rule": st_fix["pairs_by_rule"], "rt_hit_lines": st_fix["rt_hit_lines"],
+                         "kernel_ms_serial": {"far": kf[0] * 1e3, "band": kf[1] * 1e3, "rt": kf[2] * 1e3},
+                         "learned_vs_fixed_speed": t_fix / t_head,
+                         "roofline_kernels": kernel_rooflines(st_fix, kf, nm, args.workload, "fixed",
+                                                              args.precision, args.valu_far)}
+        print(f"bench: fixed {t_fix * 1e3:.2f} ms", flush=True)
+
+    if not args.quick:
+        # ---- equal accuracy: a ladder of fixed settings against the learned policy
+        if args.policy == "learned" and B.probes is not None:
+            ladder = [{"near_cut": DEFAULT_CUTS[0], "d_g11": DEFAULT_CUTS[1], "d_g4": DEFAULT_CUTS[2], "lines": 16,
+                       "ms_per_step": t_fix * 1e3, "probe_error": err_fix}]
+            for a, b, c, nl in LADDER:
+                B.set_policy(kind=bs.BS_POLICY_FIXED, near_cut=a, d_g11=b, d_g4=c, n_phi=nl, n_theta=nl)
+                t = B.time(steps2, 1, **flags)
+                ladder.append({"near_cut": a, "d_g11": b, "d_g4": c, "lines": nl, "ms_per_step": t * 1e3,
+                               "probe_error": B.error()})
+                print(f"bench: fixed {a}/{b}/{c} {nl}x{nl}: {t * 1e3:.2f} ms, error {ladder[-1]['probe_error']:.3e}",
+                      flush=True)
+            ok = [r for r in ladder if r["probe_error"] <= err_head]
+            best = min(ok, key=lambda r: r["ms_per_step"]) if ok else min(ladder, key=lambda r: r["probe_error"])
+            line["accuracy"] = {
+                "reference": f"exact velocity at {len(B.probes[0])} probe nodes (tests/golden/probe_exact_"
+                             f"{args.workload}.json: cone decomposition within 4 hbar, 11-point rule beyond)",
+                "learned": {"ms_per_step": t_head * 1e3, "probe_error": err_head},
+                "fixed_ladder": ladder,
+                "equal_accuracy_fixed": best,
+                "fixed_reaches_learned_error": bool(ok),
+                "vs_fixed_equal_accuracy": best["ms_per_step"] / (t_head * 1e3),
+            }
+
+        # ---- the far field on the vector ALUs (the design without matrix cores)
+        B.set_policy(**fixed_pol)
+        t_valu = B.time(steps2, 1, valu_far=True)
+        err_valu = B.error()
+        kv, st_v, _ = B.kernels(steps2, valu_far=True)
+        line["valu_far"] = {"ms_per_step": t_valu * 1e3, "value": B.pairs / t_valu, "probe_error": err_valu,
+                            "policy": "fixed",
+                            "roofline_kernels": kernel_rooflines(st_v, kv, nm, args.workload, "fixed",
+                                                                 args.precision, valu_far=True)}
+        print(f"bench: vector-ALU far field {t_valu * 1e3:.2f} ms", flush=True)
+
+        # ---- the Lagrangian run (moves this mesh: last on it)
+        if args.heun_steps > 0:
+            B.set_policy(**head_pol)
+            _, secs = bs.bs_advect_heun(B.h, 0.005, args.heun_steps)
+            line["lagrangian"] = {"steps": args.heun_steps, "dt": 0.005, "policy": args.policy,
+                                  "seconds_per_step": [float(s) for s in secs],
+                                  "median_s_per_step": float(np.median(secs)),
+                                  "evaluations_per_step": 2,
+                                  "what": "bs_advect_heun: per step two device-mesh rebuilds on the host and two "
+                                          "evaluations, connectivity and nodal vorticity kept"}
+            print(f"bench: Heun {np.median(secs):.3f} s per step", flush=True)
+    B.free()
+
+    if not args.quick and args.workload != "C2":
+        # ---- the vortex-ring workload as a second leg
+        m2 = W.make_config("C2")
+        B2 = Bench(bs, torch, m2, args.precision)
+        B2.probes = load_probes("C2")
+        c2 = {"workload": f"C2: {WORKLOAD_TEXT['C2']}, {m2.n_nodes} nodes x {m2.n_tets} tets"}
+        for name, pol in (("fixed", fixed_pol), ("learned", learned_pol)):
+            B2.set_policy(**pol)
+            t = B2.time(args.steps * 2, args.warmup, **flags)
+            c2[name] = {"ms_per_step": t * 1e3, "value": B2.pairs / t, "probe_error": B2.error()}
+        B2.free()
+        line["c2"] = c2
+
+    if not args.no_cpu_baseline and not args.quick:
         line["cpu_baseline"] = cpu_baseline(mesh)
-    bs.bs_mesh_free(h)
+    line["config"]["bench_wall_s"] = time.perf_counter() - t_start
     print(json.dumps(line), flush=True)
 
 

@@ -5,6 +5,8 @@ import os
 import subprocess
 import sys
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -24,12 +26,20 @@ def test_bench_refuses_more_than_one_gpu():
 
 def test_traffic_reported_only_for_the_profiled_configuration():
     b = _bench()
-    # the counters were taken on the vortex-ring workload in compensated mode
+    # counters exist per workload and policy, in compensated mode only
     for kernel in ("k_far_mfma", "k_band_piece", "k_rt_walk"):
-        assert b.measured_traffic(kernel, "C1", 1) is None
-        assert b.measured_traffic(kernel, "C2", 0) is None
-        assert b.measured_traffic(kernel, "C2", 2) is None
-    assert b.measured_traffic("k_no_such_kernel", "C2", 1) is None
+        assert b.measured_traffic(kernel, "C1", "fixed", 1) is None
+        assert b.measured_traffic(kernel, "C5", "fixed", 0) is None
+        assert b.measured_traffic(kernel, "C5", "learned", 2) is None
+    assert b.measured_traffic("k_no_such_kernel", "C5", "learned", 1) is None
+
+
+def test_probe_references_are_stored_for_the_bench_workloads():
+    b = _bench()
+    for name, k in (("C2", 24), ("C5", 32)):
+        nodes, exact = b.load_probes(name)
+        assert nodes.shape == (k,) and exact.shape == (k, 3)
+        assert len(set(nodes.tolist())) == k and np.all(np.isfinite(exact))
 
 
 def test_algorithmic_flops_counts_gauss_points_and_ray_work():

@@ -77,14 +77,39 @@ def test_heun_with_stretching_matches_oracle(bs):
     finally:
         bs.bs_mesh_free(h)
     assert np.array_equal(pos, x_gpu)
-    x, w = m.xyz.copy(), m.omega.copy()
-    for _ in range(steps):
-        x, w = K.lagrangian_step(x, w, m.tets, dt, lambda xx, ww: oracle.evaluate(xx, ww, m.tets))
-    ex = np.linalg.norm((x_gpu - m.xyz) - (x - m.xyz)) / np.linalg.norm(x - m.xyz)
-    ew = np.linalg.norm((w_gpu - m.omega) - (w - m.omega)) / np.linalg.norm(w - m.omega)
-    _say(f"rel-L2 of displacement {ex:.3e}, of vorticity change {ew:.3e}")
+    def run(perturb):
+        rng = np.random.default_rng(21)
+
+        def vel(xx, ww):
+            v = oracle.evaluate(xx, ww, m.tets)
+            if perturb:
+                v = v + perturb * np.sqrt(np.mean(v * v)) * rng.standard_normal(v.shape)
+            return v
+
+        x, w = m.xyz.copy(), m.omega.copy()
+        for _ in range(steps):
+            x, w = K.lagrangian_step(x, w, m.tets, dt, vel)
+        return x, w
+
+    def errors(xa, wa, xb, wb):
+        ex = np.linalg.norm((xa - m.xyz) - (xb - m.xyz)) / np.linalg.norm(xb - m.xyz)
+        ew = np.linalg.norm((wa - m.omega) - (wb - m.omega)) / np.linalg.norm(wb - m.omega)
+        return ex, ew
+
+    x, w = run(0.0)
+    # Tolerance from the conditioning of the step: every evaluation may err
+    # by 1e-6 (rel-L2), and the nodal gradient turns velocity errors that vary
+    # from node to node into stretching errors of order error / h.  The
+    # oracle's own steps with i.i.d. velocity errors of rel-L2 1e-6 show how
+    # much of that reaches the displacement and the vorticity change; the
+    # library's steps may err by twice that.
+    xp, wp = run(1e-6)
+    ax, aw = errors(xp, wp, x, w)
+    ex, ew = errors(x_gpu, w_gpu, x, w)
+    _say(f"rel-L2 of displacement {ex:.3e}, of vorticity change {ew:.3e}; "
+         f"from 1e-6 velocity noise: {ax:.3e}, {aw:.3e}")
     assert np.linalg.norm(w - m.omega) > 1e-3 * np.linalg.norm(m.omega)  # the vorticity did change
-    assert ex <= 1e-5 and ew <= 1e-5
+    assert ex <= max(1e-6, 2 * ax) and ew <= max(1e-6, 2 * aw)
 
 
 def test_remeshed_run_and_parity_on_the_new_mesh(bs):

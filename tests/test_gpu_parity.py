@@ -2,8 +2,11 @@
 on the same seeded inputs.
 
 Tolerance: relative L2 error <= 1e-6 over all nodes and components for the
-FP32 path (the stated target), per policy.  Rule decisions (binary32 on both
-sides) must match exactly, pair counts included."""
+FP32 path (the stated target), per policy, and at every node an error at
+most 5e-6 of the larger of the node's own velocity and the root-mean-square
+node velocity (so that one bad node cannot hide in the aggregate; the floor
+keeps nodes whose velocity nearly cancels from dominating).  Rule decisions
+(binary32 on both sides) must match exactly, pair counts included."""
 import json
 import os
 
@@ -18,6 +21,7 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-6
+NODE_TOL = 5e-6
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -30,6 +34,22 @@ def _gpu():
 
 def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def node_errors(a, b):
+    """Per-node error relative to max(|b_i|, rms node magnitude of b)."""
+    scale = np.sqrt(np.mean(np.sum(b * b, axis=1)))
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), max(scale, 1e-300))
+
+
+def check(a, b, label="", tol=TOL, node_tol=NODE_TOL):
+    """Assert rel-L2 <= tol and the per-node bound; print both."""
+    e = rel_l2(a, b)
+    per = node_errors(a, b)
+    _say(f"  {label} rel-L2 {e:.3e}, worst node {per.max():.3e} (of {len(per)})")
+    assert e <= tol, (label, e)
+    assert per.max() <= node_tol, (label, per.max(), int(per.argmax()))
+    return e
 
 
 def gpu_eval(mesh_or_arrays, **pol):
@@ -54,7 +74,7 @@ def test_gauss_only_c1(rule, pts):
     _say(f"gauss-only G{pts} on C1")
     v, st = gpu_eval(m, kind=bs.BS_POLICY_GAUSS_ONLY, gauss_rule=rule)
     ref = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("gauss_only", gauss_rule=rule))
-    assert rel_l2(v, ref) <= TOL
+    check(v, ref, f"G{pts}")
     assert st["pairs_by_rule"][rule] == m.n_nodes * m.n_tets
 
 
@@ -68,7 +88,7 @@ def test_fixed_policy_c1(prec):
     assert st["pairs_by_rule"] == cnt["pairs_by_rule"]
     assert st["rt_hit_lines"] > 0
     assert st["nonfinite_out"] == 0
-    assert rel_l2(v, ref) <= TOL
+    check(v, ref, f"precision {prec}", node_tol=NODE_TOL if prec else 5e-5)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -87,10 +107,8 @@ def test_far_field_matrix_and_vector_kernels(prec, cells):
     v_m = bs.bs_eval_velocity(h)
     v_v = bs.bs_eval_velocity(h, valu_far=True)
     bs.bs_mesh_free(h)
-    e_m, e_v = rel_l2(v_m, ref), rel_l2(v_v, ref)
-    _say(f"  rel-L2 matrix cores {e_m:.3e}, vector ALUs {e_v:.3e}")
-    assert e_m <= (TOL if prec else 1e-5)
-    assert e_v <= (TOL if prec else 1e-5)
+    check(v_m, ref, "matrix cores", tol=TOL if prec else 1e-5, node_tol=NODE_TOL if prec else 5e-5)
+    check(v_v, ref, "vector ALUs", tol=TOL if prec else 1e-5, node_tol=NODE_TOL if prec else 5e-5)
 
 
 @pytest.mark.parametrize("nm", [(16, 16), (8, 12), (5, 7)])
@@ -109,9 +127,9 @@ def test_pure_ray_tracing_c1(nm):
     if nm[0] % 2 or nm[1] % 2:
         keep = ~m.boundary
         assert np.all(np.isfinite(v))
-        assert rel_l2(v[keep], ref[keep]) <= TOL
+        check(v[keep], ref[keep], "interior nodes")
     else:
-        assert rel_l2(v, ref) <= TOL
+        check(v, ref, "all nodes")
         # every (line, tet) hit of the oracle is one ray hit on the GPU (exact
         # decisions away from edges and vertices; allow a few near-edge flips)
         assert abs(st["rt_hit_lines"] - cnt["rt_hit_lines"]) <= 1e-5 * cnt["rt_hit_lines"] + 8
@@ -128,7 +146,7 @@ def test_pure_ray_tracing_general_position(nm):
     _say(f"pure ray tracing, general position, N x M = {nm}")
     v, _ = gpu_eval((xyz, om, tets), kind=bs.BS_POLICY_PURE_RT, n_phi=nm[0], n_theta=nm[1])
     ref = oracle.evaluate(xyz, om, tets, oracle.make_policy("pure_rt", n_phi=nm[0], n_theta=nm[1]))
-    assert rel_l2(v, ref) <= TOL
+    check(v, ref, f"{nm}")
 
 
 def test_ring_reduced_full_oracle():
@@ -137,7 +155,7 @@ def test_ring_reduced_full_oracle():
     v, st = gpu_eval(m)
     ref, cnt = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("fixed"), return_counters=True)
     assert st["pairs_by_rule"] == cnt["pairs_by_rule"]
-    assert rel_l2(v, ref) <= TOL
+    check(v, ref, "ring 24x24x8")
 
 
 def _sample_nodes(m, k, seed):
@@ -154,11 +172,10 @@ def test_full_size_sampled(name):
     m = W.make_config(name)
     _say(f"{name} full size ({m.n_nodes} nodes, {m.n_tets} tets), fixed policy")
     v, st = gpu_eval(m)
-    tg = _sample_nodes(m, 40, seed=11)
+    tg = _sample_nodes(m, 256, seed=11)
     ref = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("fixed"), targets=tg)
-    err = rel_l2(v[tg], ref)
-    _say(f"{name}: sampled rel-L2 {err:.3e}; rules {st['pairs_by_rule']}; t_eval {st['t_eval_s']*1e3:.2f} ms")
-    assert err <= TOL
+    _say(f"{name}: rules {st['pairs_by_rule']}; t_eval {st['t_eval_s']*1e3:.2f} ms")
+    check(v[tg], ref, f"{name} {len(tg)} sampled nodes")
     assert sum(st["pairs_by_rule"]) == m.n_nodes * m.n_tets
 
 
@@ -173,7 +190,7 @@ def test_precision_modes_c3_sampled():
     there); the matrix-core kernel adds FP32 sums of its eight splits in
     FP64 even then."""
     m = W.make_config("C3")
-    tg = _sample_nodes(m, 24, seed=3)
+    tg = _sample_nodes(m, 256, seed=3)
     ref = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("fixed"), targets=tg)
     h = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
     for valu in (False, True):
@@ -182,10 +199,12 @@ def test_precision_modes_c3_sampled():
             bs.bs_set_policy(h, kind=bs.BS_POLICY_FIXED, precision=prec)
             v, st = bs.bs_eval_velocity(h, stats=True, valu_far=valu)
             err = rel_l2(v[tg], ref)
-            per = np.linalg.norm(v[tg] - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-300)
+            per = node_errors(v[tg], ref)
             _say(f"C3 precision {prec}, {'vector ALUs' if valu else 'matrix cores'}: rel-L2 {err:.3e}, "
-                 f"max per-node {per.max():.3e}, t_eval {st['t_eval_s']*1e3:.1f} ms")
+                 f"worst node {per.max():.3e}, t_eval {st['t_eval_s']*1e3:.1f} ms")
             errs[prec] = err
+            if prec != bs.BS_PREC_FP32_NAIVE:
+                assert per.max() <= NODE_TOL, (prec, valu, per.max())
         assert errs[bs.BS_PREC_FP32_COMP] <= TOL and errs[bs.BS_PREC_FP64] <= TOL
         assert errs[bs.BS_PREC_FP32_COMP] <= 3e-7 and errs[bs.BS_PREC_FP64] <= 3e-7
         assert errs[bs.BS_PREC_FP32_NAIVE] <= 1e-4
@@ -202,10 +221,10 @@ def test_single_tet_and_tiny_meshes():
         v, _ = gpu_eval(t, kind=kind)
         ref = oracle.evaluate(t.xyz, t.omega, t.tets,
                               oracle.make_policy("fixed" if kind == bs.BS_POLICY_FIXED else "pure_rt"))
-        assert rel_l2(v, ref) <= TOL
+        check(v, ref, f"single tet, policy {kind}")
     m = W.make_config("C1", scale=(1, 1, 1))
     v, _ = gpu_eval(m)
-    assert rel_l2(v, oracle.evaluate(m.xyz, m.omega, m.tets)) <= TOL
+    check(v, oracle.evaluate(m.xyz, m.omega, m.tets), "one cell")
 
 
 def test_no_tets_gives_zero_velocity():
@@ -226,7 +245,7 @@ def test_ragged_counts_and_unreferenced_nodes():
     v, st = gpu_eval((xyz, om, m.tets))
     ref, cnt = oracle.evaluate(xyz, om, m.tets, return_counters=True)
     assert st["pairs_by_rule"] == cnt["pairs_by_rule"]
-    assert rel_l2(v, ref) <= TOL
+    check(v, ref, "ragged")
 
 
 def test_reoriented_tets():
@@ -236,7 +255,7 @@ def test_reoriented_tets():
     tets[flip, 1], tets[flip, 2] = m.tets[flip, 2], m.tets[flip, 1]
     v, st = gpu_eval((m.xyz, m.omega, tets))
     assert st["reoriented"] == flip.size
-    assert rel_l2(v, oracle.evaluate(m.xyz, m.omega, tets)) <= TOL
+    check(v, oracle.evaluate(m.xyz, m.omega, tets), "reoriented")
 
 
 @pytest.mark.parametrize("name,scale,valu", [("C1", None, False), ("C1", None, True),
@@ -264,9 +283,9 @@ def test_incident_pairs_beyond_the_cuts(name, scale, valu):
         bs.bs_mesh_free(h)
     ref, cnt = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("fixed", **cuts),
                                return_counters=True)
-    _say(f"  rules {st['pairs_by_rule']} (oracle {cnt['pairs_by_rule']}), rel-L2 {rel_l2(v, ref):.3e}")
+    _say(f"  rules {st['pairs_by_rule']} (oracle {cnt['pairs_by_rule']})")
     assert st["pairs_by_rule"] == cnt["pairs_by_rule"]
-    assert rel_l2(v, ref) <= TOL
+    check(v, ref, "incident beyond cuts")
 
 
 def test_device_pointers_update_stream_and_determinism():
@@ -316,7 +335,10 @@ def test_lagrangian_heun_matches_oracle_heun():
     err = float(np.linalg.norm((pos - m.xyz) - disp_ref) / np.linalg.norm(disp_ref))
     _say(f"Lagrangian drift: rel-L2 of displacement {err:.3e}; step seconds {secs}")
     assert len(secs) == steps and np.all(secs > 0)
-    assert err <= 1e-5
+    # the displacement is dt/2 (v1 + v2) summed over the steps: its relative
+    # error is bounded by the evaluations' (1e-6) up to the tiny change of
+    # v2 with the positions
+    assert err <= TOL
 
 
 def test_lagrangian_reports_inversion():
@@ -339,11 +361,11 @@ def test_walk_and_candidate_kernels_agree():
     m = W.make_config("C1")
     ref = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("pure_rt"))
     v, st = gpu_eval(m, kind=bs.BS_POLICY_PURE_RT)
-    assert rel_l2(v, ref) <= TOL
+    check(v, ref, "walk")
     b = W.ball_mesh(cells=8)
     b.omega = W.field_gaussian_swirl(b.xyz)
     vb, _ = gpu_eval(b)
-    assert rel_l2(vb, oracle.evaluate(b.xyz, b.omega, b.tets)) <= TOL
+    check(vb, oracle.evaluate(b.xyz, b.omega, b.tets), "candidate kernel on the ball")
 
 
 def test_concurrent_and_serial_streams_agree():
@@ -385,7 +407,7 @@ def test_pure_ray_tracing_convergence():
         if cells == 16:
             tg = np.random.default_rng(0).choice(sel, size=16, replace=False)
             ref = oracle.evaluate(xyz, om, tets, oracle.make_policy("pure_rt", n_phi=24, n_theta=24), targets=tg)
-            assert rel_l2(vg[tg], ref) <= TOL
+            check(vg[tg], ref, "16^3 sample")
     p = np.polyfit(np.log(hs), np.log(errs), 1)[0]
     _say(f"fitted order {p:.2f} (the paper's fit: {paper_p})")
     assert 1.5 < p < 2.8
@@ -421,6 +443,4 @@ def test_off_node_points(kind):
     om = np.concatenate([m.omega, np.zeros_like(pts)])
     tg = np.arange(m.n_nodes, m.n_nodes + len(pts))
     ref = oracle.evaluate(xyz, om, m.tets, oracle.make_policy(kind), targets=tg)
-    e = rel_l2(vp, ref)
-    _say(f"  rel-L2 {e:.3e}")
-    assert e <= TOL
+    check(vp, ref, "points")

@@ -81,30 +81,44 @@ def _ball():
     return b
 
 
-@pytest.mark.parametrize("name", ["C1", "ball"])
+@pytest.mark.parametrize("name", ["C1", "ball", "C2", "C5"])
 def test_learned_policy_matches_oracle(bs, selector, name):
+    """Whole small meshes (C1, the non-convex ball) and, at full size, seeded
+    samples of nodes of the ring (C2) and two-ring (C5) workloads: the GPU
+    evaluates every node, the oracle the sample with its own decisions."""
     bits, p, conf_min = selector
-    m = W.make_config("C1") if name == "C1" else _ball()
-    print(f"learned policy on {name} ({m.xyz.shape[0]} nodes), conf_min {conf_min}", flush=True)
-    v_ora, pr, (aK, aT, arule, aalt), tg = oracle_learned(m, p, conf_min)
+    m = W.make_config("C1") if name == "C1" else _ball() if name == "ball" else W.make_config(name)
+    sampled = name in ("C2", "C5")
+    targets = None
+    if sampled:
+        rng = np.random.default_rng(13)
+        targets = np.sort(rng.choice(m.n_nodes, 256 if name == "C2" else 128, replace=False))
+    print(f"learned policy on {name} ({m.xyz.shape[0]} nodes{', sampled' if sampled else ''}), "
+          f"conf_min {conf_min}", flush=True)
+    v_ora, pr, (aK, aT, arule, aalt), tg = oracle_learned(m, p, conf_min, targets=targets)
     v_gpu, st = gpu_learned(bs, m, bits, conf_min)
+    v_gpu = v_gpu[tg]
     counts = np.bincount(pr.ravel(), minlength=4)
     print(f"oracle rules {counts.tolist()}, gpu {st['pairs_by_rule']}, ambiguous pairs {len(aK)}", flush=True)
+    _, fixed_rules = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("fixed"), targets=tg,
+                                     return_rules=True)
     # the selector moved most ray-traced pairs
-    _, fixed_rules = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("fixed"), return_rules=True)
     assert counts[3] < 0.5 * np.count_nonzero(fixed_rules == 3)
-    # rule counts agree up to the ambiguous pairs
-    diff = np.abs(np.array(st["pairs_by_rule"]) - counts)
-    assert diff.sum() <= 2 * len(aK), (diff, len(aK))
     assert len(aK) <= 0.01 * max(1, counts[:3].sum() - np.count_nonzero(fixed_rules < 3))
-    # nodes without ambiguous pairs: element-wise parity
+    if not sampled:
+        # rule counts agree up to the ambiguous pairs
+        diff = np.abs(np.array(st["pairs_by_rule"]) - counts)
+        assert diff.sum() <= 2 * len(aK), (diff, len(aK))
+    # nodes without ambiguous pairs: element-wise parity, with a per-node bound
     amb_nodes = np.unique(aK)
-    clear = np.setdiff1d(np.arange(m.n_nodes), amb_nodes)
+    clear = np.setdiff1d(np.arange(len(tg)), amb_nodes)
     e = np.linalg.norm(v_gpu[clear] - v_ora[clear]) / np.linalg.norm(v_ora[clear])
-    print(f"rel-L2 over {len(clear)} nodes with unique decisions: {e:.3e}", flush=True)
-    assert e <= TOL
+    scale = np.linalg.norm(v_ora) / np.sqrt(len(tg))
+    per = np.linalg.norm(v_gpu[clear] - v_ora[clear], axis=1) / np.maximum(np.linalg.norm(v_ora[clear], axis=1),
+                                                                              scale)
+    print(f"rel-L2 over {len(clear)} nodes with unique decisions: {e:.3e}, worst node {per.max():.3e}", flush=True)
+    assert e <= TOL and per.max() <= 5 * TOL
     # nodes with ambiguous pairs: some choice of the alternatives explains the GPU
-    scale = np.linalg.norm(v_ora) / np.sqrt(m.n_nodes)
     for node in amb_nodes:
         sel = np.nonzero(aK == node)[0]
         assert len(sel) <= 12
