@@ -36,6 +36,7 @@
 #include "bs_mlp_dev.h"
 
 #include <hip/hip_runtime.h>
+
 #include <type_traits>
 
 namespace bsk {
@@ -305,7 +306,9 @@ hipError_t launch_gauss_all(const DevMesh &m, int rule_pts, int precision, int s
 // computed and stored to LDS in the next step, so the loads' latency hides
 // behind a whole chunk of work.
 // PREC 0: FP32 accumulation throughout; PREC 1: the FP32 sums of every two
-// chunks are added in FP64.
+// chunks are folded into a compensated FP32 pair (value, error) by TwoSum.
+// FP64 only assembles each node's result at the end: the four waves' pairs,
+// the cross product with the node's offset from the block centre.
 constexpr int kFarChunk = 256;
 
 constexpr int kA1Stride = 80; // floats per tile in a1 (64 used; the pad spreads the banks of the stores)
@@ -318,7 +321,8 @@ struct FarLds {
             unsigned long long band[2][16];   // [buf][tile]: bit 16 nt + i = centroid of tet i within the band of node tile nt
         } c;
     };
-    double acc[4][6][64];                     // [wave][component][lane]: FP64 sums of node 16 (lane / 16) + lane % 16
+    float accs[4][6][64];                     // [wave][component][lane]: compensated FP32 sums (value, error) of
+    float accc[4][6][64];                     //   node 16 (lane / 16) + lane % 16
     float4 xn[64];                            // binary32 node coordinates (the rule's), by node of the block
     float4 nts[4];                            // bounding sphere of each node tile (radius < 0: no node)
 };
@@ -390,7 +394,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) D0[nt] = D1[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int r = 0; r < 6; ++r) S.acc[wave][r][lane] = 0.0; // node 16q + i16 of the block after each fold
+    for (int r = 0; r < 6; ++r) S.accs[wave][r][lane] = S.accc[wave][r][lane] = 0.f; // node 16q + i16 after each fold
 
     // the record of tet c0 + tid, in flight in registers until stored (the
     // index is clamped so that the loads need no branch; tets past the end
@@ -448,7 +452,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     // sum the four tet streams of every node (lanes l, l^16, l^32, l^48) in
     // FP32, leaving node tile q's six sums in lane group q (a reduce-scatter
     // by lane swaps: lanes 0-31 keep node tiles 0, 1 and lanes 32-63 tiles
-    // 2, 3, then even and odd groups split those), and add them into acc in FP64
+    // 2, 3, then even and odd groups split those), and fold them into the
+    // compensated pairs by TwoSum (Knuth: t = s + x, the rounding error of
+    // the addition recovered exactly from t, s and x)
     auto fold = [&]() {
         float y[2][6];
 #pragma unroll
@@ -464,7 +470,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         for (int r = 0; r < 6; ++r) {
             const auto sw =
                 __builtin_amdgcn_permlane16_swap(__float_as_uint(y[0][r]), __float_as_uint(y[1][r]), false, false);
-            S.acc[wave][r][lane] += (double)(__uint_as_float(sw[0]) + __uint_as_float(sw[1]));
+            const float x = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+            const float a = S.accs[wave][r][lane];
+            const float t = a + x;
+            const float bp = t - a;
+            const float e = (a - (t - bp)) + (x - bp);
+            S.accs[wave][r][lane] = t;
+            S.accc[wave][r][lane] += e;
         }
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) D0[nt] = D1[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
@@ -568,8 +580,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     if (tid < 64) {
         double sw[6];
 #pragma unroll
-        for (int r = 0; r < 6; ++r)
-            sw[r] = ((S.acc[0][r][tid] + S.acc[1][r][tid]) + S.acc[2][r][tid]) + S.acc[3][r][tid];
+        for (int r = 0; r < 6; ++r) {
+            sw[r] = 0.0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) sw[r] += (double)S.accs[w][r][tid] + (double)S.accc[w][r][tid];
+        }
         const int i = b * kBlockNodes + tid;
         double xp[3] = {0.0, 0.0, 0.0};
         if (i < m.nv) {
@@ -2356,6 +2371,7 @@ hipError_t launch_combine(const DevMesh &m, const int *node_orig, const double *
                        node_orig, part, splits, band, rtv, vel, nonfinite);
     return hipGetLastError();
 }
+
 
 // ---------------------------------------------------------------------------
 // Velocity gradient of the piecewise-linear interpolant of nodal velocities
