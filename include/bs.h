@@ -177,6 +177,23 @@ typedef struct {
  * vel, unknown flag), BS_E_DEVICE (launch or runtime failure). */
 int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, bs_stats *st);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops): bs_eval_velocity without any allocation.
+ * The same kernels run on `stream` alone, with their partial sums, counters
+ * and lists in a static device array of 64 MiB that the library holds on
+ * every device it runs on until the process ends.  vel ([n_nodes][3] FP64,
+ * input node order) must be device memory: flags must hold BS_PTR_DEVICE
+ * (BS_EVAL_VALU_FAR allowed).  The policy's tables are installed by
+ * bs_set_policy.  No statistics; the call does not synchronise.  The array
+ * is shared by every call on a device, so calls that overlap on one device
+ * (other streams or threads) race and must be ordered by the caller.
+ * Errors: BS_E_STATE (NULL mesh), BS_E_ARG (NULL vel, host output, unknown
+ * flag, or a mesh and policy whose buffers exceed 64 MiB: 24 bytes per
+ * node slot for each tet split of the far field (8 splits on the matrix
+ * cores), 48 more per node slot, and 520 per node for the learned policy),
+ * BS_E_DEVICE. */
+int bs_eval_velocity_noalloc(bs_mesh *m, double *vel, uint32_t flags, void *stream);
+
 /* Velocity at n_pts arbitrary points pts ([n_pts][3] FP64; Section 3.1
  * evaluates the method at points that are not mesh nodes), written to vel
  * ([n_pts][3] FP64, the order of pts); pts and vel are device memory when

@@ -96,7 +96,7 @@ class Stats(ctypes.Structure):
 
 # every symbol include/bs.h declares
 EXPORTS = ["bs_mesh_upload", "bs_mesh_update", "bs_mesh_free", "bs_policy_default", "bs_set_policy",
-           "bs_eval_velocity", "bs_eval_points", "bs_advect_heun", "bs_velocity_gradient", "bs_mesh_read",
+           "bs_eval_velocity", "bs_eval_velocity_noalloc", "bs_eval_points", "bs_advect_heun", "bs_velocity_gradient", "bs_mesh_read",
            "bs_learn_sample_pairs", "bs_learn_pairs", "bs_mlp_train",
            "bs_mlp_grad", "bs_mlp_logits", "bs_status_string", "bs_last_error"]
 
@@ -151,6 +151,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     L.bs_set_policy.restype = ctypes.c_int
     L.bs_eval_velocity.argtypes = [vp, vp, ctypes.c_uint32, vp, ctypes.POINTER(Stats)]
     L.bs_eval_velocity.restype = ctypes.c_int
+    L.bs_eval_velocity_noalloc.argtypes = [vp, vp, ctypes.c_uint32, vp]
+    L.bs_eval_velocity_noalloc.restype = ctypes.c_int
     L.bs_eval_points.argtypes = [vp, ctypes.c_int64, vp, vp, ctypes.c_uint32, vp, ctypes.POINTER(Stats)]
     L.bs_eval_points.restype = ctypes.c_int
     L.bs_advect_heun.argtypes = [vp, ctypes.c_double, ctypes.c_int, vp, ctypes.c_uint32, vp, vp,
@@ -315,6 +317,20 @@ def bs_eval_velocity(mesh: BsMesh, out=None, stream=None, stats: bool = False, v
                                 _stream_handle(stream), ctypes.byref(st) if st is not None else None)
     _check(rc, "bs_eval_velocity")
     return (vel, st.as_dict()) if stats else vel
+
+
+def bs_eval_velocity_noalloc(mesh: BsMesh, out, stream=None, valu_far: bool = False):
+    """bs_eval_velocity into the device tensor `out` ([n,3] float64,
+    contiguous) without any allocation (the library's static scratch)."""
+    L = load_library()
+    if not (_is_torch(out) and out.is_cuda and str(out.dtype) == "torch.float64" and out.is_contiguous()):
+        raise ValueError("out must be a contiguous float64 device tensor")
+    if tuple(out.shape) != (mesh.n_nodes, 3):
+        raise ValueError("out must have shape [n_nodes, 3]")
+    flags = BS_PTR_DEVICE | (BS_EVAL_VALU_FAR if valu_far else 0)
+    _check(L.bs_eval_velocity_noalloc(mesh.handle, ctypes.c_void_p(out.data_ptr()), flags, _stream_handle(stream)),
+           "bs_eval_velocity_noalloc")
+    return out
 
 
 def bs_eval_points(mesh: BsMesh, pts, out=None, stream=None, stats: bool = False, valu_far: bool = False,

@@ -1113,6 +1113,10 @@ int bs_mesh_upload(const bs_mesh_desc *d, bs_mesh **out)
         return rc;
     }
     m->device = dev;
+    // set-up of the static scratch of bs_eval_velocity_noalloc, once per
+    // device (with the device current): a failed lookup only disables that
+    // entry point, which then reports it
+    (void)bsk::scratch_setup(dev);
     if ((rc = build_device_mesh(m, s))) {
         bs_mesh_free(m);
         return rc;
@@ -1181,20 +1185,61 @@ int bs_set_policy(bs_mesh *m, const bs_policy *p)
     }
     m->pol = *p;
     m->pol.mlp_bf16 = nullptr;
-    return BS_OK;
+    // the angular tables of the policy's orders, so that an evaluation never
+    // has to allocate them
+    return install_angular(m);
 }
 
 } // extern "C"
 
 namespace {
 
+// The fixed-rule far field runs on the matrix cores except in FP64 mode or
+// when the vector-ALU kernel is asked for.
+bool far_on_matrix_cores(const bs_mesh *m)
+{
+    const bs_policy &P = m->pol;
+    const bool fixed_like = P.kind == BS_POLICY_FIXED || P.kind == BS_POLICY_LEARNED;
+    return fixed_like && P.precision != BS_PREC_FP64 && m->far_mode == 0;
+}
+
+// Tet splits of the all-pairs Gauss kernels (0: no far-field kernel): eight
+// for the matrix-core kernel (one per XCD, see k_far_mfma), else enough
+// waves to fill 256 CUs.
+int far_splits(const bs_mesh *m)
+{
+    const bs_policy &P = m->pol;
+    const bool gauss_all =
+        P.kind == BS_POLICY_FIXED || P.kind == BS_POLICY_LEARNED || P.kind == BS_POLICY_GAUSS_ONLY;
+    if (!gauss_all || m->T <= 0) return 0;
+    const int node_blocks = m->npad / 1024;
+    if (far_on_matrix_cores(m)) return std::max(1, std::min<int>(8, (int)((m->T + 2047) / 2048)));
+    return std::max(1, std::min<int>((int)((4096 + 4 * node_blocks - 1) / (4 * node_blocks)), (int)((m->T + 255) / 256)));
+}
+
+// Device buffers of one evaluation that the caller provides instead of the
+// mesh (the no-allocation entry point): partial sums, counters, the walk's
+// fallback list and the learned policy's lists, and the output.
+struct EvalBufs {
+    double *part, *band, *rtv, *vel;
+    unsigned long long *cnt;
+    int *nonfinite, *fallback, *sel;
+};
+
 // One evaluation into m->vel (device, input node order), on stream s.
 // targets: the evaluation points after the nodes (bs_eval_points) instead
-// of the nodes; their velocities go to m->tvel.
-int eval_device(bs_mesh *m, hipStream_t s, bool targets)
+// of the nodes; their velocities go to m->tvel.  With given buffers (nodes
+// only) nothing is allocated: the buffers come from `given`, counters are
+// cleared by a kernel, every kernel runs on s and no event is recorded.
+int eval_device(bs_mesh *m, hipStream_t s, bool targets, const EvalBufs *given = nullptr)
 {
-    int rc = install_angular(m);
-    if (rc) return rc;
+    int rc;
+    if (given) {
+        if (m->ang_N != m->pol.n_phi || m->ang_M != m->pol.n_theta)
+            return fail(BS_E_STATE, "angular tables of the policy not installed");
+    } else if ((rc = install_angular(m))) {
+        return rc;
+    }
     const bs_policy &P = m->pol;
     bsk::DevMesh dm = dev_view(m);
     if (targets) {
@@ -1205,21 +1250,15 @@ int eval_device(bs_mesh *m, hipStream_t s, bool targets)
     }
     m->last_targets = targets;
 
-    // tet splits of the all-pairs Gauss kernel: enough waves to fill 256 CUs
-    const int node_blocks = m->npad / 1024;
-    int splits = 0;
     const bool fixed_like = P.kind == BS_POLICY_FIXED || P.kind == BS_POLICY_LEARNED;
-    const bool gauss_all = fixed_like || P.kind == BS_POLICY_GAUSS_ONLY;
-    // the fixed-rule far field runs on the matrix cores except in FP64 mode
-    const bool far_mfma = fixed_like && P.precision != BS_PREC_FP64 && m->far_mode == 0;
-    if (gauss_all && m->T > 0) {
-        if (far_mfma) // eight splits: one per XCD (see k_far_mfma)
-            splits = std::max(1, std::min<int>(8, (int)((m->T + 2047) / 2048)));
-        else
-            splits = std::max(1, std::min<int>((int)((4096 + 4 * node_blocks - 1) / (4 * node_blocks)),
-                                               (int)((m->T + 255) / 256)));
-        if ((rc = dalloc(m->part, 8 * 3 * (size_t)m->npad * splits))) return rc;
-    }
+    const bool far_mfma = far_on_matrix_cores(m);
+    const int splits = far_splits(m);
+    if (splits > 0 && !given && (rc = dalloc(m->part, 8 * 3 * (size_t)m->npad * splits))) return rc;
+    double *b_part = given ? given->part : (double *)m->part.p;
+    double *b_band = given ? given->band : (double *)m->band.p;
+    double *b_rtv = given ? given->rtv : (double *)m->rtv.p;
+    unsigned long long *cnt = given ? given->cnt : (unsigned long long *)m->cnt.p;
+    int *b_nonfinite = given ? given->nonfinite : (int *)m->nonfinite.p;
     bsk::Thresholds th{};
     const double hb = m->hbar;
     const double c_rt = P.near_cut * hb, c_11 = P.d_g11 * hb, c_4 = P.d_g4 * hb;
@@ -1255,41 +1294,49 @@ int eval_device(bs_mesh *m, hipStream_t s, bool targets)
     ang.M2 = 2 * P.n_theta;
 
     hipError_t e;
-    unsigned long long *cnt = (unsigned long long *)m->cnt.p;
-    if ((e = hipMemsetAsync(m->cnt.p, 0, 8 * bsk::kNumCounters, s)) ||
-        (e = hipMemsetAsync(m->nonfinite.p, 0, 4, s)))
+    if (given) {
+        if ((e = bsk::launch_fill_zero(cnt, 2 * bsk::kNumCounters, s)) ||
+            (e = bsk::launch_fill_zero(b_nonfinite, 1, s)))
+            return hip_fail(e, "clear counters");
+    } else if ((e = hipMemsetAsync(cnt, 0, 8 * bsk::kNumCounters, s)) || (e = hipMemsetAsync(b_nonfinite, 0, 4, s))) {
         return hip_fail(e, "clear counters");
+    }
     const double *part = nullptr, *band = nullptr, *rtv = nullptr;
-    (void)hipEventRecord(m->ev[0], s);
-    if ((e = hipStreamWaitEvent(m->aux[0], m->ev[0], 0)) || (e = hipStreamWaitEvent(m->aux[1], m->ev[0], 0)))
+    const bool one_stream = m->serial || given;
+    auto record = [&](int k, hipStream_t st) {
+        if (!given) (void)hipEventRecord(m->ev[k], st);
+    };
+    record(0, s);
+    if (!one_stream &&
+        ((e = hipStreamWaitEvent(m->aux[0], m->ev[0], 0)) || (e = hipStreamWaitEvent(m->aux[1], m->ev[0], 0))))
         return hip_fail(e, "fork streams");
     if (m->T > 0) {
         if (P.kind == BS_POLICY_GAUSS_ONLY) {
             const int pts = P.gauss_rule == BS_RULE_G1 ? 1 : P.gauss_rule == BS_RULE_G4 ? 4 : 11;
-            if ((e = bsk::launch_gauss_all(dm, pts, P.precision, splits, (double *)m->part.p, s)))
+            if ((e = bsk::launch_gauss_all(dm, pts, P.precision, splits, b_part, s)))
                 return hip_fail(e, "gauss kernel");
-            part = (const double *)m->part.p;
+            part = b_part;
         } else if (far_mfma) {
-            if ((e = bsk::launch_far_mfma(dm, th, P.precision, splits, (double *)m->part.p, s)))
+            if ((e = bsk::launch_far_mfma(dm, th, P.precision, splits, b_part, s)))
                 return hip_fail(e, "far-field kernel");
-            part = (const double *)m->part.p;
+            part = b_part;
         } else if (fixed_like) {
-            if ((e = bsk::launch_gauss_all(dm, 1, P.precision, splits, (double *)m->part.p, s)))
+            if ((e = bsk::launch_gauss_all(dm, 1, P.precision, splits, b_part, s)))
                 return hip_fail(e, "far-field kernel");
-            part = (const double *)m->part.p;
+            part = b_part;
         }
     }
-    (void)hipEventRecord(m->ev[1], s);
+    record(1, s);
     // band and ray tracing on their own streams, concurrent with the far field
-    hipStream_t sb = m->serial ? s : m->aux[0], sr = m->serial ? s : m->aux[1];
-    (void)hipEventRecord(m->ev[2], sb);
+    hipStream_t sb = one_stream ? s : m->aux[0], sr = one_stream ? s : m->aux[1];
+    record(2, sb);
     if (m->T > 0 && fixed_like) {
-        if ((e = bsk::launch_band(dm, th, P.precision, far_mfma ? 0 : 1, (double *)m->band.p, cnt, sb)))
+        if ((e = bsk::launch_band(dm, th, P.precision, far_mfma ? 0 : 1, b_band, cnt, sb)))
             return hip_fail(e, "band kernel");
-        band = (const double *)m->band.p;
+        band = b_band;
     }
-    (void)hipEventRecord(m->ev[3], sb);
-    (void)hipEventRecord(m->ev[4], sr);
+    record(3, sb);
+    record(4, sr);
     bsk::LearnParams lp{};
     lp.net = P.kind == BS_POLICY_LEARNED ? (const bsk::PackedNet *)m->mlp.p : nullptr;
     lp.conf_min = P.conf_min;
@@ -1297,43 +1344,62 @@ int eval_device(bs_mesh *m, hipStream_t s, bool targets)
     if (m->T > 0 && (fixed_like || P.kind == BS_POLICY_PURE_RT)) {
         const int all = P.kind == BS_POLICY_PURE_RT;
         if (m->convex && m->rt_mode == 0 && !targets) {
-            if ((rc = dalloc(m->fallback, 4 * ((size_t)m->n + 1)))) return rc;
-            int *nfb = (int *)m->fallback.p + m->n;
+            if (!given && (rc = dalloc(m->fallback, 4 * ((size_t)m->n + 1)))) return rc;
+            int *fb = given ? given->fallback : (int *)m->fallback.p;
+            int *nfb = fb + m->n;
             const float r_stop = all ? 3.0e38f : (float)((std::max(c_rt, m->max_vc) + m->max_vc) * (1.0 + 1e-4) + 1e-6);
             int *sel_list = nullptr, *sel_n = nullptr;
             float *sel_dmax = nullptr;
             if (lp.net) {
                 const size_t nn = (size_t)m->n;
-                if ((rc = dalloc(m->sel, 4 * (nn * bsk::kSelListCap + 2 * nn)))) return rc;
-                sel_list = (int *)m->sel.p;
+                if (!given && (rc = dalloc(m->sel, 4 * (nn * bsk::kSelListCap + 2 * nn)))) return rc;
+                sel_list = given ? given->sel : (int *)m->sel.p;
                 sel_n = sel_list + nn * bsk::kSelListCap;
                 sel_dmax = (float *)(sel_n + nn);
             }
-            if ((e = hipMemsetAsync(nfb, 0, 4, sr)) ||
-                (lp.net && (e = bsk::launch_select(dm, th, lp, P.precision, (double *)m->rtv.p, cnt, sel_list, sel_n,
+            if ((e = given ? bsk::launch_fill_zero(nfb, 1, sr) : hipMemsetAsync(nfb, 0, 4, sr)) ||
+                (lp.net && (e = bsk::launch_select(dm, th, lp, P.precision, b_rtv, cnt, sel_list, sel_n,
                                                    sel_dmax, sr))) ||
-                (e = bsk::launch_rt_walk(dm, th, ang, all, r_stop, P.precision, (double *)m->rtv.p, cnt,
-                                         (int *)m->fallback.p, nfb, sel_list, sel_n, sel_dmax, sr)) ||
-                (e = bsk::launch_rt(dm, th, ang, lp, all, P.precision, (double *)m->rtv.p, cnt,
-                                    (const int *)m->fallback.p, nfb, sr)))
+                (e = bsk::launch_rt_walk(dm, th, ang, all, r_stop, P.precision, b_rtv, cnt, fb, nfb, sel_list, sel_n,
+                                         sel_dmax, sr)) ||
+                (e = bsk::launch_rt(dm, th, ang, lp, all, P.precision, b_rtv, cnt, fb, nfb, sr)))
                 return hip_fail(e, "ray-tracing walk");
-        } else if ((e = bsk::launch_rt(dm, th, ang, lp, all, P.precision, (double *)m->rtv.p, cnt,
+        } else if ((e = bsk::launch_rt(dm, th, ang, lp, all, P.precision, b_rtv, cnt,
                                        targets ? (const int *)m->tlist.p : nullptr,
                                        targets ? (const int *)m->tlist.p + m->tn : nullptr, sr))) {
             return hip_fail(e, "ray-tracing kernel");
         }
-        rtv = (const double *)m->rtv.p;
+        rtv = b_rtv;
     }
-    (void)hipEventRecord(m->ev[5], sr);
-    if ((e = hipStreamWaitEvent(s, m->ev[3], 0)) || (e = hipStreamWaitEvent(s, m->ev[5], 0)))
+    record(5, sr);
+    if (!one_stream && ((e = hipStreamWaitEvent(s, m->ev[3], 0)) || (e = hipStreamWaitEvent(s, m->ev[5], 0))))
         return hip_fail(e, "join streams");
-    (void)hipEventRecord(m->ev[6], s);
+    record(6, s);
+    double *out = given ? given->vel : (double *)(targets ? m->tvel.p : m->vel.p);
     if ((e = bsk::launch_combine(dm, (const int *)(targets ? m->torig.p : m->node_orig.p), part, part ? splits : 0,
-                                 band, rtv, (double *)(targets ? m->tvel.p : m->vel.p), (int *)m->nonfinite.p, s)))
+                                 band, rtv, out, b_nonfinite, s)))
         return hip_fail(e, "combine kernel");
-    (void)hipEventRecord(m->ev[7], s);
-    if (!targets) m->vel_valid = true;
+    record(7, s);
+    if (!targets) m->vel_valid = !given;
     return BS_OK;
+}
+
+// Bytes of scratch an evaluation of the nodes needs under the current
+// policy and far-field mode, laid out (256-byte aligned) as part, band, rtv,
+// counters, non-finite flag, fallback list, learned lists; offsets in off[7].
+size_t eval_scratch_layout(const bs_mesh *m, size_t off[7])
+{
+    auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+    const size_t np = (size_t)m->npad, nn = (size_t)m->n;
+    const size_t sz[7] = {8 * 3 * np * (size_t)far_splits(m), 8 * 3 * np, 8 * 3 * np, 8 * (size_t)bsk::kNumCounters, 4,
+                          4 * (nn + 1),
+                          m->pol.kind == BS_POLICY_LEARNED ? 4 * (nn * bsk::kSelListCap + 2 * nn) : 0};
+    size_t o = 0;
+    for (int k = 0; k < 7; ++k) {
+        off[k] = o;
+        o += al(sz[k]);
+    }
+    return o;
 }
 
 int read_stats(bs_mesh *m, bs_stats *st)
@@ -1475,6 +1541,37 @@ int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, 
     }
     if (st && (rc = read_stats(m, st))) return rc;
     return BS_OK;
+}
+
+int bs_eval_velocity_noalloc(bs_mesh *m, double *vel, uint32_t flags, void *stream)
+{
+    g_err.clear();
+    if (!m) return fail(BS_E_STATE, "null mesh");
+    if (!vel) return fail(BS_E_ARG, "null output");
+    if (flags & ~(BS_PTR_DEVICE | BS_EVAL_VALU_FAR)) return fail(BS_E_ARG, "unknown flags 0x%x", flags);
+    if (!(flags & BS_PTR_DEVICE)) return fail(BS_E_ARG, "the output must be device memory (BS_PTR_DEVICE)");
+    char *base = (char *)bsk::scratch_ptr(m->device);
+    if (!base) return fail(BS_E_DEVICE, "the static scratch of device %d is not available", m->device);
+    m->far_mode = (flags & BS_EVAL_VALU_FAR) ? 1 : 0;
+    size_t off[7];
+    const size_t need = eval_scratch_layout(m, off);
+    if (need > bsk::kScratchBytes) {
+        m->far_mode = 0;
+        return fail(BS_E_ARG, "this mesh and policy need %zu bytes of scratch, above the static %zu", need,
+                    bsk::kScratchBytes);
+    }
+    EvalBufs g{};
+    g.part = (double *)(base + off[0]);
+    g.band = (double *)(base + off[1]);
+    g.rtv = (double *)(base + off[2]);
+    g.cnt = (unsigned long long *)(base + off[3]);
+    g.nonfinite = (int *)(base + off[4]);
+    g.fallback = (int *)(base + off[5]);
+    g.sel = m->pol.kind == BS_POLICY_LEARNED ? (int *)(base + off[6]) : nullptr;
+    g.vel = vel;
+    const int rc = eval_device(m, (hipStream_t)stream, false, &g);
+    m->far_mode = 0;
+    return rc;
 }
 
 int bs_eval_points(bs_mesh *m, int64_t n_pts, const double *pts, double *vel, uint32_t flags, void *stream,

@@ -129,4 +129,17 @@ hipError_t launch_velocity_gradient(const DevMesh &m, const int *node_orig, cons
 hipError_t launch_combine(const DevMesh &m, const int *node_orig, const double *part, int splits,
                           const double *band, const double *rtv, double *vel, int *nonfinite, hipStream_t s);
 
+// Zero `words` 32-bit words at p (a kernel, so that the clearing can sit in
+// a captured graph where memset nodes are avoided).
+hipError_t launch_fill_zero(void *p, size_t words, hipStream_t s);
+
+// The library's static device scratch: kScratchBytes per device, held by
+// every device the library runs on until the process ends.  scratch_setup
+// looks up its device address once per device (call it with that device
+// current); scratch_ptr returns that address, or nullptr when the lookup
+// failed or was not made.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+hipError_t scratch_setup(int device);
+void *scratch_ptr(int device);
+
 } // namespace bsk

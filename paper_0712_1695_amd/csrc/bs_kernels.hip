@@ -37,6 +37,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 namespace bsk {
@@ -2372,6 +2374,56 @@ hipError_t launch_combine(const DevMesh &m, const int *node_orig, const double *
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Static scratch of the no-allocation evaluation (bs_eval_velocity_noalloc):
+// partial sums, counters and lists live here instead of in mesh-owned
+// buffers.  In host code the array's name is only a stand-in for the symbol;
+// its device address comes from hipGetSymbolAddress, looked up once per
+// device with that device current.
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxScratchDevices];
+hipError_t g_scratch_rc[kMaxScratchDevices];
+bool g_scratch_done[kMaxScratchDevices];
+} // namespace
+
+hipError_t scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_rc[device] = e;
+        g_scratch_addr[device] = e == hipSuccess ? ptr : nullptr;
+        g_scratch_done[device] = true;
+    }
+    return g_scratch_rc[device];
+}
+
+void *scratch_ptr(int device)
+{
+    if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_done[device] ? g_scratch_addr[device] : nullptr;
+}
+
+__global__ void __launch_bounds__(256) k_fill_zero(unsigned *__restrict__ p, size_t words)
+{
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < words; i += (size_t)gridDim.x * 256) p[i] = 0u;
+}
+
+hipError_t launch_fill_zero(void *p, size_t words, hipStream_t s)
+{
+    if (words == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<size_t>((words + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, s, (unsigned *)p, words);
+    return hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------
 // Velocity gradient of the piecewise-linear interpolant of nodal velocities
