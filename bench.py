@@ -240,7 +240,7 @@ def main():
                     help="policy of the headline step")
     ap.add_argument("--precision", type=int, default=1)
     ap.add_argument("--quick", action="store_true",
-                    help="headline step, its per-kernel pass and the fixed leg only (profiling runs)")
+                    help="the headline steps and their per-kernel pass only (profiling runs)")
     ap.add_argument("--serial", action="store_true", help="time the headline steps with every kernel on one stream")
     ap.add_argument("--valu-far", action="store_true",
                     help="headline far field on the vector ALUs instead of the matrix cores")
@@ -266,7 +266,7 @@ def main():
     torch.cuda.set_device(0)
     nm = 16 * 16
     t_start = time.perf_counter()
-    blob, sel_info = (train_selector(W) if (args.policy == "learned" or not args.quick) else (None, None))
+    blob, sel_info = train_selector(W) if (args.policy == "learned" or not args.quick) else (None, None)
     learned_pol = dict(kind=bs.BS_POLICY_LEARNED, n_phi=16, n_theta=16, mlp_bf16=blob, conf_min=0.9)
     fixed_pol = dict(kind=bs.BS_POLICY_FIXED, n_phi=16, n_theta=16)
     head_pol = learned_pol if args.policy == "learned" else fixed_pol
@@ -327,7 +327,7 @@ def main():
 
     # ---- the fixed rule on the same mesh
     steps2 = max(2, args.steps // 2 + 1)
-    if args.policy == "learned":
+    if args.policy == "learned" and not args.quick:
         B.set_policy(**fixed_pol)
         t_fix = B.time(args.steps, args.warmup, **flags)
         err_fix = B.error()
