@@ -20,8 +20,10 @@ Besides the headline, the same JSON line carries:
               above the learned policy's is "vs_fixed_equal_accuracy";
   valu_far    the fixed rule with the far field on the vector ALUs
               (k_gauss_all, the design without matrix cores) and its roofline;
-  c2          the vortex-ring workload (97,175 nodes x 540,672 tets): fixed
-              and learned timings and errors;
+  c2, c3      the vortex-ring workload (97,175 nodes x 540,672 tets; the
+              selector's training distribution) and the Fourier-curl box
+              (117,649 x 663,552; held out): fixed and learned timings and
+              errors;
   lagrangian  Heun steps of the two-ring run with the learned policy
               (bs_advect_heun: mesh rebuild, two evaluations per step);
   roofline    the longest kernel of the headline step alone (HIP events on
@@ -221,13 +223,11 @@ def kernel_rooflines(st, kern, nm, workload, policy, precision, valu_far=False):
 
 def train_selector(W):
     """The learned policy's network, trained on the GPU (outside any timed
-    region) on pairs of the swirl box and the ring box at half resolution."""
+    region) on 10 million pairs of the swirl box and the ring box, and
+    evaluated on pairs of the held-out Fourier-curl box."""
     from paper_0712_1695_amd import selector
 
-    train_meshes = [W.make_config("C1"), W.make_config("C2", scale=(32, 32, 11))]
-    blob, info = selector.train([(t.xyz, t.omega, t.tets) for t in train_meshes])
-    info["trained_on"] = [t.name for t in train_meshes]
-    return blob, info
+    return selector.train_selector(W.make_config)
 
 
 def main():
@@ -389,18 +389,25 @@ def main():
             print(f"bench: Heun {np.median(secs):.3f} s per step", flush=True)
     B.free()
 
-    if not args.quick and args.workload != "C2":
-        # ---- the vortex-ring workload as a second leg
-        m2 = W.make_config("C2")
-        B2 = Bench(bs, torch, m2, args.precision)
-        B2.probes = load_probes("C2")
-        c2 = {"workload": f"C2: {WORKLOAD_TEXT['C2']}, {m2.n_nodes} nodes x {m2.n_tets} tets"}
-        for name, pol in (("fixed", fixed_pol), ("learned", learned_pol)):
-            B2.set_policy(**pol)
-            t = B2.time(args.steps * 2, args.warmup, **flags)
-            c2[name] = {"ms_per_step": t * 1e3, "value": B2.pairs / t, "probe_error": B2.error()}
-        B2.free()
-        line["c2"] = c2
+    if not args.quick:
+        # ---- the vortex ring (in the selector's training distribution) and
+        # the Fourier-curl box (held out from it) as further legs
+        for wl in ("C2", "C3"):
+            if wl == args.workload:
+                continue
+            m2 = W.make_config(wl)
+            B2 = Bench(bs, torch, m2, args.precision)
+            B2.probes = load_probes(wl)
+            leg = {"workload": f"{wl}: {WORKLOAD_TEXT[wl]}, {m2.n_nodes} nodes x {m2.n_tets} tets"}
+            for name, pol in (("fixed", fixed_pol), ("learned", learned_pol)):
+                B2.set_policy(**pol)
+                t = B2.time(args.steps * 2, args.warmup, **flags)
+                leg[name] = {"ms_per_step": t * 1e3, "value": B2.pairs / t, "probe_error": B2.error()}
+            B2.free()
+            line[wl.lower()] = leg
+            print(f"bench: {wl} fixed {leg['fixed']['ms_per_step']:.2f} ms (error {leg['fixed']['probe_error']:.3e}), "
+                  f"learned {leg['learned']['ms_per_step']:.2f} ms (error {leg['learned']['probe_error']:.3e})",
+                  flush=True)
 
     if not args.no_cpu_baseline and not args.quick:
         line["cpu_baseline"] = cpu_baseline(mesh)

@@ -117,8 +117,7 @@ def main():
     if args.learned:
         from . import BS_POLICY_LEARNED, selector
 
-        tm = [W.make_config("C1"), W.make_config("C2", scale=(32, 32, 11))]
-        blob, sel = selector.train([(t.xyz, t.omega, t.tets) for t in tm])
+        blob, sel = selector.train_selector(W.make_config, held_out=())
         policy = dict(kind=BS_POLICY_LEARNED, precision=BS_PREC_FP32_COMP, mlp_bf16=blob, conf_min=0.9)
     pos, om, secs, _, last = run(m.xyz, m.omega, m.tets, args.steps, args.dt, policy, stretch=args.stretch,
                                  remesh=args.remesh)

@@ -2,7 +2,7 @@
 of the piecewise-linear vorticity at seeded probe nodes of a workload, for
 the accuracy legs of the benchmark and the equal-accuracy test.
 
-    python tests/golden/make_probe_references.py C2 C5
+    python tests/golden/make_probe_references.py C2 C3 C5
 
 Probes: seeded (seed 7) interior nodes where |omega| exceeds its 60th
 percentile (the vortex cores, where the near field matters most).  Exact
@@ -30,7 +30,7 @@ import oracle  # noqa: E402
 import workloads as W  # noqa: E402
 from oracle import references as R  # noqa: E402
 
-N_PROBES = {"C2": 24, "C5": 32}
+N_PROBES = {"C2": 24, "C3": 24, "C5": 32}
 NEAR = 4.0
 ORDER = 16
 
@@ -59,7 +59,7 @@ def probes(m, k):
 
 def main():
     global _M
-    names = sys.argv[1:] or ["C2", "C5"]
+    names = sys.argv[1:] or ["C2", "C3", "C5"]
     for name in names:
         t0 = time.time()
         m = W.make_config(name)
