@@ -20,6 +20,8 @@ each function computes the quantity another way:
   degree-4 rule per sub-tetrahedron (for targets away from the element).
 * gaussian_vortex: a smooth, compactly decaying vorticity with an analytic
   velocity (for the convergence-under-refinement test).
+* hill_vorticity / hill_velocity: Hill's spherical vortex (Section 3.1), the
+  paper's test problem, with its closed-form velocity.
 """
 from __future__ import annotations
 
@@ -240,6 +242,42 @@ def tet_subdivision(x, tv, tw, levels=4):
     r3 = np.linalg.norm(r, axis=2) ** 3
     integ = -np.cross(r, om) / r3[..., None] / FOUR_PI
     return np.einsum("m,q,mqc->c", vol, w, integ)
+
+
+# ---------------------------------------------------------------- Hill's vortex
+
+def hill_vorticity(xyz, A=1.0, a=1.0):
+    """Hill's spherical vortex (Section 3.1): azimuthal vorticity
+    omega_theta = A r (r the distance from the z axis) inside the sphere of
+    radius a, i.e. omega = A (-y, x, 0) there, zero outside."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    inside = np.einsum("ij,ij->i", xyz, xyz) < a * a
+    om = A * np.stack([-xyz[:, 1], xyz[:, 0], np.zeros(len(xyz))], axis=1)
+    return np.where(inside[:, None], om, 0.0)
+
+
+def hill_velocity(xyz, A=1.0, a=1.0):
+    """Velocity of Hill's vortex in the frame where the fluid is at rest far
+    away (the form of Section 3.1's closed form with its misprints corrected):
+    inside (|x| < a), in cylindrical (r, z) components,
+        u_r = A r z / 5,   u_z = (A / 5) (5 a^2 / 3 - 2 r^2 - z^2);
+    outside, the potential flow of a sphere of radius a moving along +z at
+    U = 2 A a^2 / 15: u = U a^3 / (2 R^3) (3 (e.x) x / R^2 - e) with
+    e = (0, 0, 1), R = |x|.  (Its curl inside is A r e_theta, it is
+    divergence free, and both normal and tangential components match across
+    R = a.)"""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    R2 = x * x + y * y + z * z
+    inside = R2 < a * a
+    u_in = np.stack([A * x * z / 5.0, A * y * z / 5.0, A / 5.0 * (5.0 * a * a / 3.0 - 2.0 * (x * x + y * y) - z * z)],
+                    axis=1)
+    U = 2.0 * A * a * a / 15.0
+    with np.errstate(invalid="ignore", divide="ignore"):
+        R = np.sqrt(R2)
+        f = U * a ** 3 / (2.0 * R ** 3)
+        u_out = np.stack([f * 3.0 * z * x / R2, f * 3.0 * z * y / R2, f * (3.0 * z * z / R2 - 1.0)], axis=1)
+    return np.where(inside[:, None], u_in, u_out)
 
 
 # ---------------------------------------------------------------- smooth field

@@ -390,28 +390,69 @@ def test_pure_ray_tracing_convergence():
     claims = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_claims.json")))
     paper_p = claims["convergence_under_refinement"]["exponent"]
     L, sig = 2.0, 0.5
-    hs, errs = [], []
+    hs, errs, errs_h = [], [], []
     for cells in (16, 24, 32, 48):
         xyz, tets, hh, b = W.kuhn_grid((-L,) * 3, (L,) * 3, (cells,) * 3)
         xyz = W.jitter_interior(xyz, b, hh, 0.1, 11)
         tets = W.orient_positive(xyz, tets)
         om, v = R.gaussian_vortex(xyz, sig)
         vg, st = gpu_eval((xyz, om, tets), kind=bs.BS_POLICY_PURE_RT, n_phi=24, n_theta=24)
+        vh, sth = gpu_eval((xyz, om, tets), kind=bs.BS_POLICY_FIXED, n_phi=24, n_theta=24)
         r = np.linalg.norm(xyz, axis=1)
         sel = np.nonzero((r < 1.6 * sig) & (r > 0.3 * sig))[0]
         err = np.sqrt(np.sum((vg[sel] - v[sel]) ** 2) / np.sum(v[sel] ** 2))
-        _say(f"pure RT, {cells}^3 cells (h {hh[0]:.4f}, {xyz.shape[0]} nodes): rel error {err:.3e}, "
-             f"t_eval {st['t_eval_s'] * 1e3:.1f} ms")
+        err_h = np.sqrt(np.sum((vh[sel] - v[sel]) ** 2) / np.sum(v[sel] ** 2))
+        _say(f"{cells}^3 cells (h {hh[0]:.4f}, {xyz.shape[0]} nodes): pure RT rel error {err:.3e} "
+             f"({st['t_eval_s'] * 1e3:.1f} ms), hybrid {err_h:.3e} ({sth['t_eval_s'] * 1e3:.1f} ms)")
         hs.append(hh[0])
         errs.append(err)
+        errs_h.append(err_h)
         if cells == 16:
             tg = np.random.default_rng(0).choice(sel, size=16, replace=False)
             ref = oracle.evaluate(xyz, om, tets, oracle.make_policy("pure_rt", n_phi=24, n_theta=24), targets=tg)
             check(vg[tg], ref, "16^3 sample")
     p = np.polyfit(np.log(hs), np.log(errs), 1)[0]
-    _say(f"fitted order {p:.2f} (the paper's fit: {paper_p})")
+    ph = np.polyfit(np.log(hs), np.log(errs_h), 1)[0]
+    _say(f"fitted order: pure ray tracing {p:.2f}, hybrid (fixed rule) {ph:.2f} (the paper's fit: {paper_p})")
     assert 1.5 < p < 2.8
     assert abs(p - paper_p) < 0.7
+    # the hybrid's far field starts at a cut proportional to h, which could
+    # cost an order (the centroid rule's error summed over the far shells);
+    # it is reported beside pure ray tracing and must still converge
+    assert 1.0 < ph < 2.8
+
+
+def test_hill_vortex_convergence():
+    """The paper's test problem (Section 3.1, Table 1: Hill's spherical
+    vortex, omega_theta = A r inside the unit sphere) on jittered Kuhn meshes
+    of the ball whose boundary nodes lie on the sphere: pure ray tracing and
+    the hybrid fixed rule at 16 x 16 lines against the closed form at every
+    node inside 0.6 of the radius; both converge about second order.  At the
+    coarsest mesh both match the oracle."""
+    hs, errs, errs_h = [], [], []
+    for cells in (10, 14, 20, 28):
+        x, tets, _ = W.sphere_ball_mesh(cells=cells)
+        om = R.hill_vorticity(x * (1.0 - 1e-12))
+        sel = np.nonzero(np.linalg.norm(x, axis=1) < 0.6)[0]
+        ref = R.hill_velocity(x[sel])
+        vp, st = gpu_eval((x, om, tets), kind=bs.BS_POLICY_PURE_RT)
+        vh, sth = gpu_eval((x, om, tets), kind=bs.BS_POLICY_FIXED)
+        e_p = float(np.linalg.norm(vp[sel] - ref) / np.linalg.norm(ref))
+        e_h = float(np.linalg.norm(vh[sel] - ref) / np.linalg.norm(ref))
+        _say(f"Hill's vortex, {cells}^3 cells ({x.shape[0]} nodes, {tets.shape[0]} tets): rel error pure RT {e_p:.3e} "
+             f"({st['t_eval_s'] * 1e3:.1f} ms), hybrid {e_h:.3e} ({sth['t_eval_s'] * 1e3:.1f} ms)")
+        hs.append(2.0 / cells)
+        errs.append(e_p)
+        errs_h.append(e_h)
+        if cells == 10:
+            tg = np.random.default_rng(4).choice(sel, size=24, replace=False)
+            check(vp[tg], oracle.evaluate(x, om, tets, oracle.make_policy("pure_rt"), targets=tg), "pure RT sample")
+            check(vh[tg], oracle.evaluate(x, om, tets, oracle.make_policy("fixed"), targets=tg), "hybrid sample")
+    p = np.polyfit(np.log(hs), np.log(errs), 1)[0]
+    ph = np.polyfit(np.log(hs), np.log(errs_h), 1)[0]
+    _say(f"Hill's vortex fitted order: pure ray tracing {p:.2f}, hybrid {ph:.2f}")
+    assert 1.5 < p < 2.8 and 1.5 < ph < 2.8
+    assert errs[-1] < 3e-3 and errs_h[-1] < 3e-3
 
 
 @pytest.mark.parametrize("kind", ["fixed", "pure_rt"])

@@ -277,3 +277,56 @@ def test_second_order_convergence():
     p = np.polyfit(np.log(hs), np.log(errs), 1)[0]
     assert 1.5 < p < 2.8, (p, errs)
     assert abs(p - paper_p) < 0.7
+
+
+# --------------------------------------------------------------- Hill's vortex
+
+def test_hill_closed_form_is_the_velocity_of_its_vorticity():
+    """Section 3.1's Hill's vortex, in the corrected form: inside the sphere
+    the velocity's curl is A(-y, x, 0) and its divergence zero (central
+    differences), and the velocity is continuous across |x| = a (the inner
+    form against the outer dipole of a sphere moving at 2 A a^2 / 15)."""
+    A, a, e = 1.7, 1.3, 1e-5
+    rng = np.random.default_rng(5)
+    pts = rng.uniform(-0.6, 0.6, size=(20, 3)) * a
+    for p in pts:
+        J = np.zeros((3, 3))
+        for k in range(3):
+            d = np.zeros(3)
+            d[k] = e
+            J[:, k] = (R.hill_velocity((p + d)[None], A, a)[0] - R.hill_velocity((p - d)[None], A, a)[0]) / (2 * e)
+        curl = np.array([J[2, 1] - J[1, 2], J[0, 2] - J[2, 0], J[1, 0] - J[0, 1]])
+        assert np.allclose(curl, A * np.array([-p[1], p[0], 0.0]), atol=1e-8)
+        assert abs(np.trace(J)) < 1e-8
+    # continuity across the sphere, and decay far away
+    dirs = rng.standard_normal((30, 3))
+    dirs /= np.linalg.norm(dirs, axis=1)[:, None]
+    vin = R.hill_velocity(dirs * a * (1 - 1e-12), A, a)
+    vout = R.hill_velocity(dirs * a * (1 + 1e-12), A, a)
+    assert np.max(np.abs(vin - vout)) < 1e-9 * A * a * a
+    far = R.hill_velocity(dirs * 50 * a, A, a)
+    assert np.max(np.abs(far)) < 1e-5 * A * a * a
+    # omega = A (-y, x, 0) inside, zero outside
+    assert np.allclose(R.hill_vorticity(pts, A, a), A * np.stack([-pts[:, 1], pts[:, 0], 0 * pts[:, 0]], 1))
+    assert np.all(R.hill_vorticity(dirs * 1.01 * a, A, a) == 0.0)
+
+
+@pytest.mark.slow
+def test_hill_vortex_pure_ray_tracing_converges():
+    """The paper's test problem (Section 3.1, Table 1): Hill's vortex on a
+    jittered Kuhn mesh of the ball (the cube carried onto the sphere), pure
+    ray tracing with 16 x 16 lines, against the closed form at nodes inside
+    0.6 a.  The linear vorticity is reproduced exactly inside the
+    polyhedron, whose boundary nodes lie on the sphere, so the error falls
+    about second order in h (the paper's 16 x 16 errors on its random point
+    sets are of order 1e-2)."""
+    errs = []
+    for cells in (6, 10):
+        x, tets, _ = W.sphere_ball_mesh(cells=cells)
+        om = R.hill_vorticity(x * (1.0 - 1e-12))  # boundary nodes (on the sphere) carry the inner field
+        tg = np.nonzero(np.linalg.norm(x, axis=1) < 0.6)[0]
+        v = O.evaluate(x, om, tets, O.make_policy("pure_rt"), targets=tg)
+        ref = R.hill_velocity(x[tg])
+        errs.append(np.linalg.norm(v - ref) / np.linalg.norm(ref))
+    assert errs[0] < 0.05, errs
+    assert errs[1] < 0.55 * errs[0], errs  # (6/10)^2 = 0.36 for second order, 0.6 for first

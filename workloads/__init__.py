@@ -37,6 +37,7 @@ __all__ = [
     "CONFIGS",
     "single_tet",
     "ball_mesh",
+    "sphere_ball_mesh",
 ]
 
 
@@ -279,3 +280,19 @@ def ball_mesh(cells=12, radius=1.0, alpha=0.1, seed=7):
     remap[used] = np.arange(used.size)
     return Mesh(xyz=xyz[used], omega=np.zeros((used.size, 3)), tets=remap[tets].astype(np.int32), h=h,
                 name="ball")
+
+
+def sphere_ball_mesh(cells=10, radius=1.0, alpha=0.1, seed=7):
+    """Jittered Kuhn mesh of the cube [-1, 1]^3 carried onto the ball of the
+    given radius by the smooth cube-to-sphere map
+        x' = x sqrt(1 - y^2/2 - z^2/2 + y^2 z^2/3)   (and cyclically),
+    which takes the cube's faces onto the sphere: every boundary node lies on
+    the sphere, so the polyhedron approximates the ball to second order in h.
+    Returns (xyz [n,3], tets [T,4] positively oriented, boundary [n] bool)."""
+    xyz, tets, h, b = kuhn_grid((-1.0, -1.0, -1.0), (1.0, 1.0, 1.0), (cells,) * 3)
+    xyz = jitter_interior(xyz, b, h, alpha, seed)
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    out = radius * np.stack([x * np.sqrt(1.0 - y * y / 2.0 - z * z / 2.0 + y * y * z * z / 3.0),
+                             y * np.sqrt(1.0 - z * z / 2.0 - x * x / 2.0 + z * z * x * x / 3.0),
+                             z * np.sqrt(1.0 - x * x / 2.0 - y * y / 2.0 + x * x * y * y / 3.0)], axis=1)
+    return out, orient_positive(out, tets), b
