@@ -1203,9 +1203,11 @@ bool far_on_matrix_cores(const bs_mesh *m)
     return fixed_like && P.precision != BS_PREC_FP64 && m->far_mode == 0;
 }
 
-// Tet splits of the all-pairs Gauss kernels (0: no far-field kernel): eight
-// for the matrix-core kernel (one per XCD, see k_far_mfma), else enough
-// waves to fill 256 CUs.
+// Tet splits of the all-pairs Gauss kernels (0: no far-field kernel).  The
+// matrix-core kernel: eight (one eighth of the tets per XCD, see
+// k_far_mfma), times the number of sub-splits that keeps each split's
+// 32-byte records within 3 MiB of an XCD's 4 MiB L2.  The vector-ALU kernel:
+// enough waves to fill 256 CUs.
 int far_splits(const bs_mesh *m)
 {
     const bs_policy &P = m->pol;
@@ -1213,7 +1215,12 @@ int far_splits(const bs_mesh *m)
         P.kind == BS_POLICY_FIXED || P.kind == BS_POLICY_LEARNED || P.kind == BS_POLICY_GAUSS_ONLY;
     if (!gauss_all || m->T <= 0) return 0;
     const int node_blocks = m->npad / 1024;
-    if (far_on_matrix_cores(m)) return std::max(1, std::min<int>(8, (int)((m->T + 2047) / 2048)));
+    if (far_on_matrix_cores(m)) {
+        const int base = std::max(1, std::min<int>(8, (int)((m->T + 2047) / 2048)));
+        if (base < 8) return base;
+        const int64_t per_xcd = 32 * ((m->T + 7) / 8);
+        return 8 * (int)std::max<int64_t>(1, (per_xcd + (3 << 20) - 1) / (3 << 20));
+    }
     return std::max(1, std::min<int>((int)((4096 + 4 * node_blocks - 1) / (4 * node_blocks)), (int)((m->T + 255) / 256)));
 }
 

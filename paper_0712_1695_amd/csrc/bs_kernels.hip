@@ -340,11 +340,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int q = lane >> 4, i16 = lane & 15, c4 = lane & 3;
-    // workgroup id = block * splits + split: consecutive ids go to the eight
-    // XCDs in turn, so with eight splits each XCD streams one eighth of the
-    // tets through its own L2
-    const int bl = blockIdx.x / splits;
-    const int split = blockIdx.x - bl * splits;
+    // Consecutive workgroup ids go to the eight XCDs in turn.  With fewer
+    // than eight splits: id = block * splits + split.  With 8 S splits: XCD
+    // x = id % 8 owns the splits x S .. x S + S - 1 (one eighth of the tets)
+    // and takes them one after the other, every block on a split before the
+    // next (id / 8 = sub * nblk + block), so the split's records (sized to
+    // fit the XCD's L2 by the host) are read by all blocks while resident.
+    int bl, split;
+    if (splits >= 8) {
+        const int per_xcd = splits >> 3;
+        const int rest = (int)(blockIdx.x >> 3);
+        const int sub = rest / m.nblk;
+        bl = rest - sub * m.nblk;
+        split = (int)(blockIdx.x & 7) * per_xcd + sub;
+    } else {
+        bl = blockIdx.x / splits;
+        split = blockIdx.x - bl * splits;
+    }
     const int b = m.blk0 + bl;
     const int t0 = split * per_split;
     const int t1 = min(m.T, t0 + per_split);
@@ -606,7 +618,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 hipError_t launch_far_mfma(const DevMesh &m, const Thresholds &th, int precision, int splits, double *part,
                            hipStream_t s)
 {
-    if (splits < 1 || precision < 0 || precision > 1) return hipErrorInvalidValue;
+    if (splits < 1 || (splits > 8 && splits % 8) || precision < 0 || precision > 1) return hipErrorInvalidValue;
     const int per = ((m.T + splits - 1) / splits + kFarChunk - 1) / kFarChunk * kFarChunk;
     const dim3 grid(m.nblk * splits);
     if (precision == 0)
