@@ -250,6 +250,16 @@ int bs_advect_heun(bs_mesh *m, double dt, int steps, double *xyz_out, uint32_t f
  * BS_E_NONFINITE (a host velocity), BS_E_DEVICE. */
 int bs_velocity_gradient(bs_mesh *m, const double *vel, double *grad, uint32_t flags, void *stream);
 
+/* Vortex stretching rate (omega . grad) v at every node (Sections 1 and 3:
+ * the Lagrangian vortex method moves vorticity-carrying nodes; the paper
+ * gives no discretisation of the stretching term): rate[i] = G_i omega_i
+ * with G_i the nodal velocity gradient of bs_velocity_gradient and omega_i
+ * the mesh's current nodal vorticity, rate [n_nodes][3] FP64 in input node
+ * order.  vel: nodal velocities as for bs_velocity_gradient (NULL: the last
+ * bs_eval_velocity).  rate and vel are device memory with BS_PTR_DEVICE.
+ * Errors as bs_velocity_gradient. */
+int bs_stretching_rate(bs_mesh *m, const double *vel, double *rate, uint32_t flags, void *stream);
+
 /* The mesh's current FP64 node positions and nodal vorticity ([n_nodes][3]
  * each, input order; either pointer may be NULL), e.g. after
  * bs_advect_heun; device memory when flags has BS_PTR_DEVICE, else host.

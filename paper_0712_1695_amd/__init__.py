@@ -96,7 +96,8 @@ class Stats(ctypes.Structure):
 
 # every symbol include/bs.h declares
 EXPORTS = ["bs_mesh_upload", "bs_mesh_update", "bs_mesh_free", "bs_policy_default", "bs_set_policy",
-           "bs_eval_velocity", "bs_eval_velocity_noalloc", "bs_eval_points", "bs_advect_heun", "bs_velocity_gradient", "bs_mesh_read",
+           "bs_eval_velocity", "bs_eval_velocity_noalloc", "bs_eval_points", "bs_advect_heun", "bs_velocity_gradient",
+           "bs_stretching_rate", "bs_mesh_read",
            "bs_learn_sample_pairs", "bs_learn_pairs", "bs_mlp_train",
            "bs_mlp_grad", "bs_mlp_logits", "bs_status_string", "bs_last_error"]
 
@@ -160,6 +161,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     L.bs_advect_heun.restype = ctypes.c_int
     L.bs_velocity_gradient.argtypes = [vp, vp, vp, ctypes.c_uint32, vp]
     L.bs_velocity_gradient.restype = ctypes.c_int
+    L.bs_stretching_rate.argtypes = [vp, vp, vp, ctypes.c_uint32, vp]
+    L.bs_stretching_rate.restype = ctypes.c_int
     L.bs_mesh_read.argtypes = [vp, vp, vp, ctypes.c_uint32, vp]
     L.bs_mesh_read.restype = ctypes.c_int
     L.bs_learn_sample_pairs.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64, vp, ctypes.POINTER(ctypes.c_int64)]
@@ -407,6 +410,30 @@ def bs_velocity_gradient(mesh: BsMesh, vel=None, out=None, stream=None):
     _check(L.bs_velocity_gradient(mesh.handle, pv, pg, BS_PTR_DEVICE if dev else BS_PTR_HOST,
                                   _stream_handle(stream)), "bs_velocity_gradient")
     return g
+
+
+def bs_stretching_rate(mesh: BsMesh, vel=None, out=None, stream=None):
+    """Vortex stretching rate (omega . grad) v [n,3] with the mesh's nodal
+    vorticity and the gradient of vel ([n,3] float64 numpy array or device
+    tensor; None: the last bs_eval_velocity).  Returns numpy, or the device
+    tensor `out` (contiguous float64 [n,3])."""
+    L = load_library()
+    pv, dv, kv = _ptr(vel, np.float64)
+    if vel is not None and tuple(vel.shape) != (mesh.n_nodes, 3):
+        raise ValueError("vel must be [n_nodes, 3]")
+    if out is None:
+        r = np.empty((mesh.n_nodes, 3), dtype=np.float64)
+        pr, dev = ctypes.c_void_p(r.ctypes.data), False
+    else:
+        if not (_is_torch(out) and out.is_cuda and str(out.dtype) == "torch.float64" and out.is_contiguous()
+                and tuple(out.shape) == (mesh.n_nodes, 3)):
+            raise ValueError("out must be a contiguous float64 device tensor [n_nodes, 3]")
+        r, pr, dev = out, ctypes.c_void_p(out.data_ptr()), True
+    if vel is not None and dv != dev:
+        raise ValueError("vel and out must both be host arrays or both device tensors")
+    _check(L.bs_stretching_rate(mesh.handle, pv, pr, BS_PTR_DEVICE if dev else BS_PTR_HOST, _stream_handle(stream)),
+           "bs_stretching_rate")
+    return r
 
 
 def bs_mesh_read(mesh: BsMesh):

@@ -241,6 +241,7 @@ struct bs_mesh {
     bool last_targets = false; // the last evaluation was of the points
     bool vel_valid = false;    // vel holds the nodes' velocities at the current positions and vorticity
     DBuf gvel, tgrad, ngrad;   // velocity gradient: input velocities, per-tet |T| G and |T|, nodal G
+    DBuf om64, srate;          // FP64 nodal vorticity (input order) and the stretching rate G omega
     int rt_mode = 0; // 0: walk where the boundary is convex, 1: always the candidate kernel
     int far_mode = 0; // 0: matrix-core far field (fixed-rule policies, FP32 modes), 1: vector-ALU kernel
     int serial = 0;   // 1: every kernel on the caller's stream
@@ -819,7 +820,7 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
         (rc = dalloc(m->cnt, 8 * bsk::kNumCounters)) || (rc = dalloc(m->nonfinite, 4)) ||
         (rc = dalloc(m->nbr, sizeof(int4) * (size_t)T)) ||
         (rc = dalloc(m->tsph, sizeof(float4) * tsph.size())) || (rc = dalloc(m->inc_start, 4 * inc_start.size())) ||
-        (rc = dalloc(m->inc_list, 4 * inc_list.size())))
+        (rc = dalloc(m->inc_list, 4 * inc_list.size())) || (rc = dalloc(m->om64, 8 * 3 * (size_t)std::max<int64_t>(n, 1))))
         return rc;
     hipError_t e;
 #define BS_UP(buf, vec)                                                                                            \
@@ -844,6 +845,7 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
     BS_UP(tsph, tsph)
     BS_UP(inc_start, inc_start)
     BS_UP(inc_list, inc_list)
+    BS_UP(om64, m->omega)
 #undef BS_UP
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "upload");
@@ -1159,7 +1161,7 @@ void bs_mesh_free(bs_mesh *m)
                     &m->nbr, &m->inc_start, &m->inc_list, &m->fallback,
                     &m->cell_start, &m->part, &m->band, &m->rtv, &m->vel, &m->cnt, &m->nonfinite, &m->dir,
                     &m->dir64, &m->cphi, &m->dia, &m->mlp, &m->sel, &m->torig, &m->tlist, &m->tvel,
-                    &m->gvel, &m->tgrad, &m->ngrad};
+                    &m->gvel, &m->tgrad, &m->ngrad, &m->om64, &m->srate};
     for (DBuf *b : bufs) dfree(*b);
     for (auto &a : m->aux)
         if (a) (void)hipStreamSynchronize(a);
@@ -1464,6 +1466,19 @@ int velocity_gradient_device(bs_mesh *m, const double *vel, hipStream_t s)
     return BS_OK;
 }
 
+// Stretching rate G omega of every node into m->srate ([n][3] FP64, input
+// order) from device velocities vel ([n][3], input order) and the mesh's
+// current vorticity.
+int stretching_device(bs_mesh *m, const double *vel, hipStream_t s)
+{
+    int rc = velocity_gradient_device(m, vel, s);
+    if (rc || (rc = dalloc(m->srate, 8 * 3 * (size_t)std::max<int64_t>(m->n, 1)))) return rc;
+    const hipError_t e = bsk::launch_stretching((int)m->n, (const double *)m->ngrad.p, (const double *)m->om64.p,
+                                                (double *)m->srate.p, s);
+    if (e != hipSuccess) return hip_fail(e, "stretching kernel");
+    return BS_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -1500,6 +1515,41 @@ int bs_velocity_gradient(bs_mesh *m, const double *vel, double *grad, uint32_t f
                             (flags & BS_PTR_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s)) ||
         (e = hipStreamSynchronize(s)))
         return hip_fail(e, "velocity gradient");
+    return BS_OK;
+}
+
+int bs_stretching_rate(bs_mesh *m, const double *vel, double *rate, uint32_t flags, void *stream)
+{
+    g_err.clear();
+    if (!m) return fail(BS_E_STATE, "null mesh");
+    if (!rate) return fail(BS_E_ARG, "null output");
+    if (flags & ~BS_PTR_DEVICE) return fail(BS_E_ARG, "unknown flags 0x%x", flags);
+    if (!vel && !m->vel_valid) return fail(BS_E_STATE, "no velocities: evaluate the nodes first or pass vel");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    const size_t n3 = 3 * (size_t)m->n;
+    const double *dvel = (const double *)m->vel.p;
+    if (vel) {
+        if (flags & BS_PTR_DEVICE) {
+            dvel = vel;
+        } else {
+            for (size_t i = 0; i < n3; ++i)
+                if (!std::isfinite(vel[i])) return fail(BS_E_NONFINITE, "non-finite velocity");
+            int rc = dalloc(m->gvel, 8 * std::max<size_t>(n3, 1));
+            if (rc) return rc;
+            if ((e = hipMemcpyAsync(m->gvel.p, vel, 8 * n3, hipMemcpyHostToDevice, s)) ||
+                (e = hipStreamSynchronize(s)))
+                return hip_fail(e, "upload velocities");
+            dvel = (const double *)m->gvel.p;
+        }
+    }
+    if (m->n == 0) return BS_OK;
+    int rc = stretching_device(m, dvel, s);
+    if (rc) return rc;
+    if ((e = hipMemcpyAsync(rate, m->srate.p, 8 * n3,
+                            (flags & BS_PTR_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s)) ||
+        (e = hipStreamSynchronize(s)))
+        return hip_fail(e, "stretching rate");
     return BS_OK;
 }
 
@@ -1642,12 +1692,11 @@ int bs_advect_heun(bs_mesh *m, double dt, int steps, double *xyz_out, uint32_t f
     hipStream_t s = (hipStream_t)stream;
     const size_t n3 = 3 * (size_t)m->n;
     std::vector<double> x = m->xyz, v1(n3), v2(n3), xs(n3);
-    std::vector<double> w = m->omega, s1, s2, ws, g;
+    std::vector<double> w = m->omega, s1, s2, ws;
     if (stretch) {
         s1.resize(n3);
         s2.resize(n3);
         ws.resize(n3);
-        g.resize(3 * n3);
     }
     double t_dev = 0.0;
     int rc = BS_OK;
@@ -1665,16 +1714,12 @@ int bs_advect_heun(bs_mesh *m, double dt, int steps, double *xyz_out, uint32_t f
     };
     // vortex stretching (w . grad) v at every node, from the velocities just
     // evaluated (the gradient of their piecewise-linear interpolant)
-    auto stretch_to = [&](const std::vector<double> &om, std::vector<double> &out) -> int {
-        int r = velocity_gradient_device(m, (const double *)m->vel.p, s);
+    auto stretch_to = [&](std::vector<double> &out) -> int {
+        int r = stretching_device(m, (const double *)m->vel.p, s);
         if (r) return r;
-        if ((e = hipMemcpyAsync(g.data(), m->ngrad.p, 8 * g.size(), hipMemcpyDeviceToHost, s)) ||
+        if ((e = hipMemcpyAsync(out.data(), m->srate.p, 8 * n3, hipMemcpyDeviceToHost, s)) ||
             (e = hipStreamSynchronize(s)))
-            return hip_fail(e, "read velocity gradient");
-        for (size_t i = 0; i < (size_t)m->n; ++i)
-            for (int a = 0; a < 3; ++a)
-                out[3 * i + a] = (g[9 * i + 3 * a] * om[3 * i] + g[9 * i + 3 * a + 1] * om[3 * i + 1]) +
-                                 g[9 * i + 3 * a + 2] * om[3 * i + 2];
+            return hip_fail(e, "read stretching rate");
         return BS_OK;
     };
     auto move_to = [&](const std::vector<double> &pos, const std::vector<double> &om) -> int {
@@ -1689,12 +1734,12 @@ int bs_advect_heun(bs_mesh *m, double dt, int steps, double *xyz_out, uint32_t f
     for (int k = 0; k < steps && rc == BS_OK; ++k) {
         const auto t0 = std::chrono::steady_clock::now();
         const std::vector<double> x0 = x, w0 = w;
-        if ((rc = eval_to(v1)) == BS_OK && (!stretch || (rc = stretch_to(w, s1)) == BS_OK)) {
+        if ((rc = eval_to(v1)) == BS_OK && (!stretch || (rc = stretch_to(s1)) == BS_OK)) {
             for (size_t i = 0; i < n3; ++i) xs[i] = x[i] + dt * v1[i];
             if (stretch)
                 for (size_t i = 0; i < n3; ++i) ws[i] = w[i] + dt * s1[i];
             if ((rc = move_to(xs, stretch ? ws : w)) == BS_OK && (rc = eval_to(v2)) == BS_OK &&
-                (!stretch || (rc = stretch_to(ws, s2)) == BS_OK)) {
+                (!stretch || (rc = stretch_to(s2)) == BS_OK)) {
                 for (size_t i = 0; i < n3; ++i) x[i] = x[i] + 0.5 * dt * (v1[i] + v2[i]);
                 if (stretch)
                     for (size_t i = 0; i < n3; ++i) w[i] = w[i] + 0.5 * dt * (s1[i] + s2[i]);

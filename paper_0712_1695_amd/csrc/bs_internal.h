@@ -126,6 +126,8 @@ hipError_t launch_rt_walk(const DevMesh &m, const Thresholds &th, const AngTab &
 // node's tets; tg: scratch of 10 doubles per tet.
 hipError_t launch_velocity_gradient(const DevMesh &m, const int *node_orig, const double *vel, double *tg,
                                     double *grad, hipStream_t s);
+// Vortex stretching rate rate[i] = grad[i] om[i] (input order, FP64).
+hipError_t launch_stretching(int n, const double *grad, const double *om, double *rate, hipStream_t s);
 hipError_t launch_combine(const DevMesh &m, const int *node_orig, const double *part, int splits,
                           const double *band, const double *rtv, double *vel, int *nonfinite, hipStream_t s);
 

@@ -2508,6 +2508,26 @@ __global__ void __launch_bounds__(256) k_node_grad(DevMesh m, const int *__restr
     for (int q = 0; q < 9; ++q) out[q] = g[q] * inv;
 }
 
+// Vortex stretching rate of every node, (omega . grad) v = G omega, from
+// the nodal gradients (input order) and the nodal vorticity (FP64, input
+// order), in the order ((G_a0 w0 + G_a1 w1) + G_a2 w2).
+__global__ void __launch_bounds__(256) k_stretch(int n, const double *__restrict__ grad, const double *__restrict__ om,
+                                                 double *__restrict__ rate)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double *g = grad + 9 * (size_t)i;
+    const double w0 = om[3 * (size_t)i], w1 = om[3 * (size_t)i + 1], w2 = om[3 * (size_t)i + 2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) rate[3 * (size_t)i + a] = (g[3 * a] * w0 + g[3 * a + 1] * w1) + g[3 * a + 2] * w2;
+}
+
+hipError_t launch_stretching(int n, const double *grad, const double *om, double *rate, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_stretch, dim3((n + 255) / 256), dim3(256), 0, s, n, grad, om, rate);
+    return hipGetLastError();
+}
+
 hipError_t launch_velocity_gradient(const DevMesh &m, const int *node_orig, const double *vel, double *tg,
                                     double *grad, hipStream_t s)
 {

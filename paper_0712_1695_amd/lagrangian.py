@@ -25,7 +25,7 @@ import time
 import numpy as np
 
 from . import (BS_POLICY_FIXED, BS_PREC_FP32_COMP, bs_advect_heun, bs_eval_velocity, bs_mesh_free, bs_mesh_read,
-               bs_mesh_upload, bs_set_policy, bs_velocity_gradient)
+               bs_mesh_upload, bs_set_policy, bs_stretching_rate)
 
 
 def retetrahedralise(xyz, min_quality=1e-6):
@@ -55,7 +55,7 @@ def _stage(x, w, policy, stretch):
     try:
         bs_set_policy(h, **policy)
         v = bs_eval_velocity(h)
-        s = np.einsum("iab,ib->ia", bs_velocity_gradient(h), w) if stretch else None
+        s = bs_stretching_rate(h) if stretch else None
         return v, s, tets
     finally:
         bs_mesh_free(h)

@@ -85,6 +85,8 @@ def test_calls_on_null_mesh():
     assert L.bs_eval_points(None, 1, None, None, 0, None, None) == bs.BS_E_STATE
     assert L.bs_velocity_gradient(None, None, None, 0, None) == bs.BS_E_STATE
     assert L.bs_mesh_read(None, None, None, 0, None) == bs.BS_E_STATE
+    assert L.bs_stretching_rate(None, None, None, 0, None) == bs.BS_E_STATE
+    assert L.bs_eval_velocity_noalloc(None, None, 0, None) == bs.BS_E_STATE
     L.bs_mesh_free(None)
 
 

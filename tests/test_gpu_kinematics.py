@@ -47,6 +47,25 @@ def test_velocity_gradient_matches_oracle(bs, name, scale):
         bs.bs_mesh_free(h)
 
 
+def test_stretching_rate_matches_oracle(bs):
+    """bs_stretching_rate: G_i omega_i with the mesh's vorticity, against the
+    oracle's gradient and stretching on seeded velocities; the last
+    evaluation's velocities give the rate of that evaluation."""
+    m = W.make_config("C5", scale=(9, 8, 10))
+    vel = np.random.default_rng(12).standard_normal((m.n_nodes, 3))
+    h = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
+    try:
+        r = bs.bs_stretching_rate(h, vel=vel)
+        ref = K.stretching(K.nodal_velocity_gradient(m.xyz, m.tets, vel), m.omega)
+        err = np.max(np.abs(r - ref)) / np.max(np.abs(ref))
+        _say(f"stretching rate: max |s - s_oracle| / max |s_oracle| = {err:.3e}")
+        assert err <= 1e-9
+        v = bs.bs_eval_velocity(h)
+        assert np.array_equal(bs.bs_stretching_rate(h), bs.bs_stretching_rate(h, vel=v))
+    finally:
+        bs.bs_mesh_free(h)
+
+
 def test_gradient_of_the_last_evaluation(bs):
     m = W.make_config("C1", scale=(5, 5, 5))
     h = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
