@@ -144,9 +144,40 @@ typedef struct {
     const uint16_t *mlp_bf16; /* LEARNED: host pointer to the packed weights    */
     int64_t mlp_len;          /* LEARNED: number of uint16 in mlp_bf16          */
     float conf_min;           /* LEARNED: in [0, 1]                             */
+    int far_field;            /* BS_FAR_*: how the 1-point-rule pairs are summed */
+    double tree_theta;        /* BS_FAR_TREECODE: opening ratio, in (0, 1)      */
+    int tree_order;           /* BS_FAR_TREECODE: expansion order, 2, 4 or 6    */
 } bs_policy;
 
-/* Fill *p with the defaults: FIXED, N = M = 16, cuts 2 / 4 / 8, FP32_COMP. */
+/* Far field of the FIXED and LEARNED policies (the pairs the distance rule
+ * gives the 1-point rule).  ALL_PAIRS sums every such pair.  TREECODE is the
+ * fast-multipole-like evaluation the paper leaves to future work (Section
+ * 4), defined here as a batched Barnes-Hut treecode:
+ *   - sources: the 1-point rule of each tet (centroid c_t, strength
+ *     W_t = |T| omega(c_t) / 4pi);
+ *   - clusters: the nodes of the recursive median split of the centroids
+ *     (the node order's rule, leaves of at most 64 tets);
+ *   - targets: the 64-node blocks of the node order;
+ *   - each has the sphere (midpoint of the bounding box, largest distance
+ *     to it) of its points in FP64.
+ * Block B accepts cluster S iff
+ *     |c_B - c_S|^2 >= (r_B + max(r_S / tree_theta, r_S + kappa))^2,
+ *     kappa = max(d_g4 hbar, largest vertex-centroid distance) (1 + 1e-3),
+ * so that every pair of (B, S) is a 1-point pair and every node sees the
+ * cluster within ratio tree_theta.  Accepted clusters are evaluated by
+ * their Cartesian multipole expansion of order tree_order.  Leaves that are
+ * not accepted are summed pair by pair (the 1-point pairs only).  The error
+ * against ALL_PAIRS is the expansions' truncation: at most
+ *     |W| q^(P+1) ((P+2) - (P+1) q) / (R^2 (1 - q)^2)
+ * per source at distance R from its cluster's centre, q = r_S / R <= theta.
+ * TREECODE builds its plan (tree, spheres, interaction lists) on the host
+ * when the policy is set and whenever the nodes move; it is refused for the
+ * other policy kinds. */
+#define BS_FAR_ALL_PAIRS 0
+#define BS_FAR_TREECODE 1
+
+/* Fill *p with the defaults: FIXED, N = M = 16, cuts 2 / 4 / 8, FP32_COMP,
+ * ALL_PAIRS (tree_theta 0.3, tree_order 4 for TREECODE). */
 void bs_policy_default(bs_policy *p);
 
 /* Validate and install a policy on a mesh (copied; mlp weights copied to the
@@ -165,6 +196,8 @@ typedef struct {
     int64_t reoriented;       /* negatively oriented input tetrahedra          */
     int32_t nonfinite_out;    /* 1 if any output component is NaN or Inf       */
     double hbar;              /* mean edge length                              */
+    int64_t tree_expansions;  /* TREECODE: (node, cluster) expansion terms     */
+    int64_t tree_direct;      /* TREECODE: (node, tet) pairs of direct leaves  */
 } bs_stats;
 
 /* Velocity at every node, written to vel ([n_nodes][3] FP64, input node

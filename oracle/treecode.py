@@ -272,24 +272,71 @@ class Treecode:
             self._moments[key] = moments(self.cen[t], self.W[t], self.csph[j][0], order)
         return self._moments[key]
 
+    def all_moments(self, order):
+        """Moments [cluster, multi-index, 3] of every cluster about its
+        centre: for each depth of the tree, every tet of a cluster at that
+        depth adds W_t (c_t - c_S)^k to it (a bincount over the clusters)."""
+        key = ("all", order)
+        if key in self._moments:
+            return self._moments[key]
+        torder, start, end, left, right = self.tree
+        nn = len(start)
+        depth = np.zeros(nn, dtype=np.int64)
+        for j in range(nn):
+            if left[j] >= 0:
+                depth[left[j]] = depth[right[j]] = depth[j] + 1
+        ks = multi_indices(order)
+        ctr = np.array([c for (c, _) in self.csph])
+        M = np.zeros((nn, len(ks), 3))
+        for dlev in range(depth.max() + 1):
+            ids = np.nonzero(depth == dlev)[0]
+            lens = end[ids] - start[ids]
+            anc = np.repeat(ids, lens)
+            pos = np.concatenate([np.arange(start[j], end[j]) for j in ids])
+            t = torder[pos]
+            d = self.cen[t] - ctr[anc]
+            for q, (i, j2, l) in enumerate(ks):
+                f = d[:, 0] ** i * d[:, 1] ** j2 * d[:, 2] ** l
+                for c in range(3):
+                    M[:, q, c] += np.bincount(anc, weights=f * self.W[t, c], minlength=nn)
+        self._moments[key] = M
+        return M
+
     def lists(self, theta, blocks):
         return interaction_lists([self.bsph[b] for b in blocks], self.tree, self.csph, theta, self.kappa)
 
     def far(self, theta, order, targets):
         """Treecode far field (the 1-point-rule pairs) at node indices
-        targets, FP64 [m, 3]."""
+        targets, FP64 [m, 3]: every (target, accepted cluster) expansion in
+        one batch, then the direct leaves block by block."""
         targets = np.asarray(targets, dtype=np.int64)
         out = np.zeros((len(targets), 3))
         blocks = np.unique(self.block_of[targets])
-        for b, (acc, direct) in zip(blocks, self.lists(theta, blocks)):
-            rows = np.nonzero(self.block_of[targets] == b)[0]
-            ids = targets[rows]
-            x = self.xyz[ids]
-            for j in acc:
-                out[rows] += expansion_velocity(x, self.csph[j][0], self.cluster_moments(j, order), order)
+        lists = self.lists(theta, blocks)
+        M = self.all_moments(order)
+        ctr = np.array([c for (c, _) in self.csph])
+        rows, clus = [], []
+        for b, (acc, direct) in zip(blocks, lists):
+            r = np.nonzero(self.block_of[targets] == b)[0]
+            if acc:
+                rows.append(np.repeat(r, len(acc)))
+                clus.append(np.tile(np.asarray(acc, dtype=np.int64), len(r)))
             if direct:
+                ids = targets[r]
                 t = np.concatenate([self.cluster_tets(j) for j in direct])
-                out[rows] += direct_g1(x, ids, self.cen[t], self.W[t], self.tets[t], self.hbar, self.d_g4)
+                out[r] += direct_g1(self.xyz[ids], ids, self.cen[t], self.W[t], self.tets[t], self.hbar, self.d_g4)
+        if rows:
+            rows = np.concatenate(rows)
+            clus = np.concatenate(clus)
+            for q in range(0, len(rows), 1 << 16):
+                rr, cc = rows[q:q + (1 << 16)], clus[q:q + (1 << 16)]
+                a, col = taylor_coefficients(self.xyz[targets[rr]] - ctr[cc], order + 1)
+                v = np.zeros((len(rr), 3))
+                for qk, k in enumerate(multi_indices(order)):
+                    g = np.stack([(k[i] + 1) * a[:, col[tuple(k[c] + (c == i) for c in range(3))]]
+                                  for i in range(3)], axis=1)
+                    v += (-1) ** sum(k) * np.cross(g, M[cc, qk])
+                np.add.at(out, rr, v)
         return out
 
     def direct_far(self, targets):

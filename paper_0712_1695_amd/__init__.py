@@ -44,6 +44,7 @@ BS_ADVECT_STRETCH = 0x40
 BS_RULE_G1, BS_RULE_G4, BS_RULE_G11, BS_RULE_RT = 0, 1, 2, 3
 BS_POLICY_FIXED, BS_POLICY_PURE_RT, BS_POLICY_GAUSS_ONLY, BS_POLICY_LEARNED = 0, 1, 2, 3
 BS_PREC_FP32_NAIVE, BS_PREC_FP32_COMP, BS_PREC_FP64 = 0, 1, 2
+BS_FAR_ALL_PAIRS, BS_FAR_TREECODE = 0, 1
 
 
 class MeshDesc(ctypes.Structure):
@@ -71,6 +72,9 @@ class Policy(ctypes.Structure):
         ("mlp_bf16", ctypes.c_void_p),
         ("mlp_len", ctypes.c_int64),
         ("conf_min", ctypes.c_float),
+        ("far_field", ctypes.c_int),
+        ("tree_theta", ctypes.c_double),
+        ("tree_order", ctypes.c_int),
     ]
 
 
@@ -85,13 +89,16 @@ class Stats(ctypes.Structure):
         ("reoriented", ctypes.c_int64),
         ("nonfinite_out", ctypes.c_int32),
         ("hbar", ctypes.c_double),
+        ("tree_expansions", ctypes.c_int64),
+        ("tree_direct", ctypes.c_int64),
     ]
 
     def as_dict(self):
         return dict(t_eval_s=self.t_eval_s, t_kernel_s=list(self.t_kernel_s), pairs=self.pairs,
                     pairs_by_rule=list(self.pairs_by_rule), rt_hit_lines=self.rt_hit_lines,
                     fp64_retests=self.fp64_retests, reoriented=self.reoriented,
-                    nonfinite_out=self.nonfinite_out, hbar=self.hbar)
+                    nonfinite_out=self.nonfinite_out, hbar=self.hbar, tree_expansions=self.tree_expansions,
+                    tree_direct=self.tree_direct)
 
 
 # every symbol include/bs.h declares
@@ -281,7 +288,8 @@ def bs_policy_default() -> Policy:
 def bs_set_policy(mesh: BsMesh, policy: Optional[Policy] = None, **kw):
     """Install a policy: a Policy struct, or the defaults updated with kw
     (kind, n_phi, n_theta, near_cut, d_g11, d_g4, gauss_rule, precision,
-    mlp_bf16 (uint16 numpy array), conf_min)."""
+    mlp_bf16 (uint16 numpy array), conf_min, far_field ("all_pairs",
+    "treecode" or BS_FAR_*), tree_theta, tree_order)."""
     L = load_library()
     p = policy if policy is not None else bs_policy_default()
     keep = None
@@ -290,6 +298,8 @@ def bs_set_policy(mesh: BsMesh, policy: Optional[Policy] = None, **kw):
             keep = np.ascontiguousarray(v, dtype=np.uint16)
             p.mlp_bf16 = keep.ctypes.data
             p.mlp_len = keep.size
+        elif k == "far_field" and isinstance(v, str):
+            p.far_field = {"all_pairs": BS_FAR_ALL_PAIRS, "treecode": BS_FAR_TREECODE}[v]
         else:
             setattr(p, k, v)
     _check(L.bs_set_policy(mesh.handle if mesh is not None else None, ctypes.byref(p)), "bs_set_policy")

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbs.so")
-SOURCES = ["bs_host.cpp", "bs_kernels.hip", "bs_learn.hip"]
+SOURCES = ["bs_host.cpp", "bs_kernels.hip", "bs_learn.hip", "bs_tree.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

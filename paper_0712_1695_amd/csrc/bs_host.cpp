@@ -242,6 +242,17 @@ struct bs_mesh {
     bool vel_valid = false;    // vel holds the nodes' velocities at the current positions and vorticity
     DBuf gvel, tgrad, ngrad;   // velocity gradient: input velocities, per-tet |T| G and |T|, nodal G
     DBuf om64, srate;          // FP64 nodal vorticity (input order) and the stretching rate G omega
+    // treecode far field (BS_FAR_TREECODE): the plan of the current positions
+    // and policy (tree, spheres, interaction lists) and the moment buffers
+    struct TreePlan {
+        bool valid = false;
+        double theta = 0.0, d_g4 = 0.0;
+        int order = 0, nnode = 0, nleaf = 0;
+        std::vector<int> level_start; // tree level L: clusters [level_start[L], level_start[L+1])
+        int64_t exp_nodes = 0, dir_nodes = 0, exp_pts = 0, dir_pts = 0; // expansion terms, direct pairs
+        DBuf nrange, child, leaves, c64, crec, src64, g1t, tidt, M, N, acc_start, acc, dir_start, dir;
+    } tree;
+    std::vector<int32_t> h_torig; // evaluation points in their k-d order (host copy)
     int rt_mode = 0; // 0: walk where the boundary is convex, 1: always the candidate kernel
     int far_mode = 0; // 0: matrix-core far field (fixed-rule policies, FP32 modes), 1: vector-ALU kernel
     int serial = 0;   // 1: every kernel on the caller's stream
@@ -575,6 +586,322 @@ void block_spheres(const std::vector<float> &xh, int npad, int64_t p0, int64_t c
     }
 }
 
+bool uses_treecode(const bs_policy &P)
+{
+    return P.far_field == BS_FAR_TREECODE && (P.kind == BS_POLICY_FIXED || P.kind == BS_POLICY_LEARNED);
+}
+
+// f(i) for every i in [0, count), items dealt to up to 16 threads.
+template <class F>
+void parallel_items(int64_t count, F &&f)
+{
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int64_t nt = std::min<int64_t>(std::min<unsigned>(hw ? hw : 1u, 16u), count);
+    if (nt <= 1) {
+        for (int64_t i = 0; i < count; ++i) f(i);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    std::vector<std::thread> th;
+    for (int64_t k = 0; k < nt; ++k)
+        th.emplace_back([&] {
+            for (int64_t i; (i = next.fetch_add(1)) < count;) f(i);
+        });
+    for (auto &t : th) t.join();
+}
+
+// The treecode's sphere of the points P[idx[k]], k in [a, b) (FP64 [.][3]):
+// centre the midpoint of their bounding box, radius the largest distance to
+// it, each operation in this order.
+void tree_sphere(const double *P, const int32_t *idx, int64_t a, int64_t b, double c[3], double &r)
+{
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t k = a; k < b; ++k)
+        for (int q = 0; q < 3; ++q) {
+            const double v = P[3 * (int64_t)idx[k] + q];
+            lo[q] = std::min(lo[q], v);
+            hi[q] = std::max(hi[q], v);
+        }
+    for (int q = 0; q < 3; ++q) c[q] = 0.5 * (lo[q] + hi[q]);
+    double r2 = 0.0;
+    for (int64_t k = a; k < b; ++k) {
+        const double *x = P + 3 * (int64_t)idx[k];
+        const double dx = x[0] - c[0], dy = x[1] - c[1], dz = x[2] - c[2];
+        r2 = std::max(r2, (dx * dx + dy * dy) + dz * dz);
+    }
+    r = std::sqrt(r2);
+}
+
+// Breadth-first k-d tree of points C ([T][3] FP64): the node order's split
+// rule (longest side of the bounding box, the k smallest by (coordinate,
+// index) first, k the multiple of 64 nearest half the range), leaves of at
+// most 64.  order: point at each tree position; range and child per cluster;
+// level_start: first cluster of every level, then the count.
+void tree_kd(const double *C, int64_t T, std::vector<int32_t> &order, std::vector<int2> &range,
+             std::vector<int2> &child, std::vector<int> &level_start)
+{
+    order.resize((size_t)T);
+    for (int64_t i = 0; i < T; ++i) order[(size_t)i] = (int32_t)i;
+    range.assign(1, make_int2(0, (int)T));
+    child.assign(1, make_int2(-1, -1));
+    level_start.assign(1, 0);
+    int l0 = 0;
+    for (;;) {
+        const int l1 = (int)range.size();
+        std::vector<int> ks((size_t)(l1 - l0), 0);
+        parallel_items(l1 - l0, [&](int64_t q) {
+            const int a = range[(size_t)(l0 + q)].x, b = range[(size_t)(l0 + q)].y, len = b - a;
+            if (len <= bsk::kBlockNodes) return;
+            double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+            for (int k = a; k < b; ++k)
+                for (int c = 0; c < 3; ++c) {
+                    const double v = C[3 * (int64_t)order[(size_t)k] + c];
+                    lo[c] = std::min(lo[c], v);
+                    hi[c] = std::max(hi[c], v);
+                }
+            int ax = 0;
+            for (int c = 1; c < 3; ++c)
+                if (hi[c] - lo[c] > hi[ax] - lo[ax]) ax = c;
+            int k = ((len / 2 + bsk::kBlockNodes / 2) / bsk::kBlockNodes) * bsk::kBlockNodes;
+            k = std::min(std::max(k, bsk::kBlockNodes), len - 1);
+            std::nth_element(order.begin() + a, order.begin() + a + k, order.begin() + b, [&](int32_t u, int32_t v) {
+                const double xu = C[3 * (int64_t)u + ax], xv = C[3 * (int64_t)v + ax];
+                return xu < xv || (xu == xv && u < v);
+            });
+            ks[(size_t)q] = k;
+        });
+        for (int q = 0; q < l1 - l0; ++q) {
+            if (!ks[(size_t)q]) continue;
+            const int2 r = range[(size_t)(l0 + q)];
+            child[(size_t)(l0 + q)] = make_int2((int)range.size(), (int)range.size() + 1);
+            range.push_back(make_int2(r.x, r.x + ks[(size_t)q]));
+            range.push_back(make_int2(r.x + ks[(size_t)q], r.y));
+            child.push_back(make_int2(-1, -1));
+            child.push_back(make_int2(-1, -1));
+        }
+        level_start.push_back(l1);
+        if ((int)range.size() == l1) break;
+        l0 = l1;
+    }
+}
+
+// Does a block (centre cB, radius rB) accept a cluster (cS, rS)?  The
+// treecode's test, each FP64 operation in this order.
+inline bool tree_accepts(const double *cB, double rB, const double *cS, double rS, double theta, double kappa)
+{
+    const double dx = cB[0] - cS[0], dy = cB[1] - cS[1], dz = cB[2] - cS[2];
+    const double D2 = (dx * dx + dy * dy) + dz * dz;
+    const double rho = std::max(rS / theta, rS + kappa);
+    return D2 >= (rB + rho) * (rB + rho);
+}
+
+// The treecode plan of the current positions and policy (BS_FAR_TREECODE):
+// tree of the tet centroids, cluster and block spheres, interaction lists of
+// every node block and evaluation-point block, per-tet sources in tree
+// order, and the moment buffers; uploaded on stream s.
+int build_tree_plan(bs_mesh *m, hipStream_t s)
+{
+    auto &tp = m->tree;
+    tp.valid = false;
+    const bs_policy &P = m->pol;
+    const int64_t n = m->n, T = m->T, tn = m->tn;
+    const double *X = m->xyz.data(), *Wn = m->omega.data();
+    if (T <= 0) {
+        tp.theta = P.tree_theta;
+        tp.order = P.tree_order;
+        tp.d_g4 = P.d_g4;
+        tp.nnode = tp.nleaf = 0;
+        tp.exp_nodes = tp.dir_nodes = tp.exp_pts = tp.dir_pts = 0;
+        tp.valid = true;
+        return BS_OK;
+    }
+    // sources: FP64 centroids and strengths of the 1-point rule
+    std::vector<double> cen((size_t)(3 * T)), wsrc((size_t)(3 * T));
+    parallel_for(T, [&](int64_t a, int64_t b) {
+        for (int64_t t = a; t < b; ++t) {
+            const int32_t *id = &m->tets[(size_t)(4 * t)];
+            double v[4][3];
+            for (int j = 0; j < 4; ++j)
+                for (int c = 0; c < 3; ++c) v[j][c] = X[3 * (int64_t)id[j] + c];
+            double e[3][3];
+            for (int j = 0; j < 3; ++j)
+                for (int c = 0; c < 3; ++c) e[j][c] = v[j + 1][c] - v[0][c];
+            const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                               e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                               e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+            const double f = std::fabs(det) / 6.0 / (4.0 * M_PI);
+            for (int c = 0; c < 3; ++c) {
+                cen[(size_t)(3 * t + c)] = (((v[0][c] + v[1][c]) + v[2][c]) + v[3][c]) * 0.25;
+                const double w = (((Wn[3 * (int64_t)id[0] + c] + Wn[3 * (int64_t)id[1] + c]) +
+                                   Wn[3 * (int64_t)id[2] + c]) + Wn[3 * (int64_t)id[3] + c]) * 0.25;
+                wsrc[(size_t)(3 * t + c)] = f * w;
+            }
+        }
+    });
+    std::vector<int32_t> order;
+    std::vector<int2> range, child;
+    tree_kd(cen.data(), T, order, range, child, tp.level_start);
+    const int nnode = (int)range.size();
+    std::vector<int> leaves;
+    for (int j = 0; j < nnode; ++j)
+        if (child[(size_t)j].x < 0) leaves.push_back(j);
+    std::vector<double> c64((size_t)4 * nnode);
+    std::vector<float> crec((size_t)8 * nnode, 0.f);
+    parallel_items(nnode, [&](int64_t j) {
+        double c[3], r;
+        tree_sphere(cen.data(), order.data(), range[(size_t)j].x, range[(size_t)j].y, c, r);
+        for (int q = 0; q < 3; ++q) {
+            c64[(size_t)(4 * j + q)] = c[q];
+            const float h = (float)c[q];
+            crec[(size_t)(8 * j + q)] = h;
+            crec[(size_t)(8 * j + 3 + q)] = (float)(c[q] - (double)h);
+        }
+        c64[(size_t)(4 * j + 3)] = r;
+    });
+
+    // target blocks: the nodes' (0 .. nblk-1) and the points' (tblk0 ..)
+    const double kappa = std::max(P.d_g4 * m->hbar, m->max_vc) * (1.0 + 1e-3);
+    const int nbt = std::max(m->nblk, m->tblk0 + m->tnblk);
+    std::vector<int32_t> orig((size_t)n);
+    for (int64_t i = 0; i < n; ++i) orig[(size_t)m->h_rank[(size_t)i]] = (int32_t)i;
+    std::vector<std::vector<int>> acc((size_t)nbt), dir((size_t)nbt);
+    std::vector<int> bcount((size_t)nbt, 0);
+    parallel_items(nbt, [&](int64_t b) {
+        const double *Pt;
+        const int32_t *idx;
+        int64_t cnt;
+        if (b < m->nblk) {
+            Pt = X;
+            idx = orig.data() + 64 * b;
+            cnt = std::min<int64_t>(64, n - 64 * b);
+        } else if (b >= m->tblk0 && b < m->tblk0 + m->tnblk) {
+            Pt = m->tgt.data();
+            idx = m->h_torig.data() + 64 * (b - m->tblk0);
+            cnt = std::min<int64_t>(64, tn - 64 * (b - m->tblk0));
+        } else {
+            return;
+        }
+        bcount[(size_t)b] = (int)cnt;
+        double cB[3], rB;
+        tree_sphere(Pt, idx, 0, cnt, cB, rB);
+        std::vector<int> stack{0};
+        while (!stack.empty()) {
+            const int j = stack.back();
+            stack.pop_back();
+            if (tree_accepts(cB, rB, &c64[(size_t)(4 * j)], c64[(size_t)(4 * j + 3)], P.tree_theta, kappa))
+                acc[(size_t)b].push_back(j);
+            else if (child[(size_t)j].x < 0)
+                dir[(size_t)b].push_back(j);
+            else {
+                stack.push_back(child[(size_t)j].y);
+                stack.push_back(child[(size_t)j].x);
+            }
+        }
+    });
+    std::vector<int> acc_start((size_t)nbt + 1, 0), dir_start((size_t)nbt + 1, 0);
+    tp.exp_nodes = tp.dir_nodes = tp.exp_pts = tp.dir_pts = 0;
+    for (int b = 0; b < nbt; ++b) {
+        acc_start[(size_t)b + 1] = acc_start[(size_t)b] + (int)acc[(size_t)b].size();
+        dir_start[(size_t)b + 1] = dir_start[(size_t)b] + (int)dir[(size_t)b].size();
+        int64_t dt = 0;
+        for (int j : dir[(size_t)b]) dt += range[(size_t)j].y - range[(size_t)j].x;
+        const int64_t ex = (int64_t)acc[(size_t)b].size() * bcount[(size_t)b], dp = dt * bcount[(size_t)b];
+        if (b < m->nblk) {
+            tp.exp_nodes += ex;
+            tp.dir_nodes += dp;
+        } else {
+            tp.exp_pts += ex;
+            tp.dir_pts += dp;
+        }
+    }
+    std::vector<int> acc_list((size_t)std::max(1, acc_start.back())), dir_list((size_t)std::max(1, dir_start.back()));
+    for (int b = 0; b < nbt; ++b) {
+        std::copy(acc[(size_t)b].begin(), acc[(size_t)b].end(), acc_list.begin() + acc_start[(size_t)b]);
+        std::copy(dir[(size_t)b].begin(), dir[(size_t)b].end(), dir_list.begin() + dir_start[(size_t)b]);
+    }
+
+    // per-tet sources in tree order: FP64 (moments) and binary32 (direct
+    // leaves: the rule's centroid fl32(c_t), strength), vertex slots
+    std::vector<double> src64((size_t)8 * T, 0.0);
+    std::vector<float> g1t((size_t)8 * T, 0.f);
+    std::vector<int4> tidt((size_t)T);
+    parallel_for(T, [&](int64_t a, int64_t b) {
+        for (int64_t k = a; k < b; ++k) {
+            const int64_t t = order[(size_t)k];
+            for (int c = 0; c < 3; ++c) {
+                src64[(size_t)(8 * k + c)] = cen[(size_t)(3 * t + c)];
+                src64[(size_t)(8 * k + 3 + c)] = wsrc[(size_t)(3 * t + c)];
+                g1t[(size_t)(8 * k + c)] = (float)cen[(size_t)(3 * t + c)];
+                g1t[(size_t)(8 * k + 3 + c)] = (float)wsrc[(size_t)(3 * t + c)];
+            }
+            const int32_t *id = &m->tets[(size_t)(4 * t)];
+            tidt[(size_t)k] = make_int4(m->h_rank[(size_t)id[0]], m->h_rank[(size_t)id[1]], m->h_rank[(size_t)id[2]],
+                                        m->h_rank[(size_t)id[3]]);
+        }
+    });
+
+    const int NK = bsk::tree_ncoef(P.tree_order), NC = bsk::tree_ncoef(P.tree_order + 1) - 1;
+    int rc;
+    if ((rc = dalloc(tp.nrange, sizeof(int2) * range.size())) || (rc = dalloc(tp.child, sizeof(int2) * child.size())) ||
+        (rc = dalloc(tp.leaves, 4 * leaves.size())) || (rc = dalloc(tp.c64, 8 * c64.size())) ||
+        (rc = dalloc(tp.crec, 4 * crec.size())) || (rc = dalloc(tp.src64, 8 * src64.size())) ||
+        (rc = dalloc(tp.g1t, 4 * g1t.size())) || (rc = dalloc(tp.tidt, sizeof(int4) * tidt.size())) ||
+        (rc = dalloc(tp.M, 8 * 3 * (size_t)nnode * NK)) || (rc = dalloc(tp.N, 4 * 3 * (size_t)nnode * NC)) ||
+        (rc = dalloc(tp.acc_start, 4 * acc_start.size())) || (rc = dalloc(tp.acc, 4 * acc_list.size())) ||
+        (rc = dalloc(tp.dir_start, 4 * dir_start.size())) || (rc = dalloc(tp.dir, 4 * dir_list.size())))
+        return rc;
+    hipError_t e;
+#define BS_UP(buf, vec)                                                                                            \
+    if ((e = hipMemcpyAsync(tp.buf.p, (vec).data(), sizeof((vec)[0]) * (vec).size(), hipMemcpyHostToDevice, s)) != \
+        hipSuccess)                                                                                                \
+        return hip_fail(e, "upload tree " #buf);
+    BS_UP(nrange, range)
+    BS_UP(child, child)
+    BS_UP(leaves, leaves)
+    BS_UP(c64, c64)
+    BS_UP(crec, crec)
+    BS_UP(src64, src64)
+    BS_UP(g1t, g1t)
+    BS_UP(tidt, tidt)
+    BS_UP(acc_start, acc_start)
+    BS_UP(acc, acc_list)
+    BS_UP(dir_start, dir_start)
+    BS_UP(dir, dir_list)
+#undef BS_UP
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "upload tree");
+    tp.nnode = nnode;
+    tp.nleaf = (int)leaves.size();
+    tp.theta = P.tree_theta;
+    tp.order = P.tree_order;
+    tp.d_g4 = P.d_g4;
+    tp.valid = true;
+    return BS_OK;
+}
+
+bsk::TreeView tree_view(bs_mesh *m)
+{
+    bsk::TreeView t{};
+    auto &tp = m->tree;
+    t.order = tp.order;
+    t.nnode = tp.nnode;
+    t.nleaf = tp.nleaf;
+    t.nrange = (const int2 *)tp.nrange.p;
+    t.child = (const int2 *)tp.child.p;
+    t.leaves = (const int *)tp.leaves.p;
+    t.c64 = (const double *)tp.c64.p;
+    t.crec = (const float *)tp.crec.p;
+    t.src64 = (const double *)tp.src64.p;
+    t.g1t = (const float *)tp.g1t.p;
+    t.tidt = (const int4 *)tp.tidt.p;
+    t.M = (double *)tp.M.p;
+    t.N = (float *)tp.N.p;
+    t.acc_start = (const int *)tp.acc_start.p;
+    t.acc = (const int *)tp.acc.p;
+    t.dir_start = (const int *)tp.dir_start.p;
+    t.dir = (const int *)tp.dir.p;
+    return t;
+}
+
 int build_device_mesh(bs_mesh *m, hipStream_t s)
 {
     m->vel_valid = false;
@@ -590,6 +917,8 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
     for (int64_t i = 0; i < n; ++i) rank[(size_t)orig[(size_t)i]] = (int32_t)i;
     const int64_t tn = m->tn;
     const std::vector<int32_t> torig = kd_leaf_order(m->tgt.data(), tn);
+    m->h_torig = torig;
+    m->tree.valid = false;
     const int64_t t0 = tn > 0 ? ((n + 1023) / 1024) * 1024 : n;
     const int npad = (int)(((t0 + tn + 1023) / 1024) * 1024);
     const int nblk = (int)((n + bsk::kBlockNodes - 1) / bsk::kBlockNodes);
@@ -849,6 +1178,7 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
 #undef BS_UP
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "upload");
+    if (uses_treecode(m->pol) && (rc = build_tree_plan(m, s))) return rc;
     return BS_OK;
 }
 
@@ -1011,6 +1341,15 @@ int check_policy(const bs_policy *p)
                         (long long)p->mlp_len);
         if (!(p->conf_min >= 0.f && p->conf_min <= 1.f)) return fail(BS_E_POLICY, "conf_min must lie in [0, 1]");
     }
+    if (p->far_field != BS_FAR_ALL_PAIRS && p->far_field != BS_FAR_TREECODE)
+        return fail(BS_E_POLICY, "unknown far_field %d", p->far_field);
+    if (p->far_field == BS_FAR_TREECODE) {
+        if (p->kind != BS_POLICY_FIXED && p->kind != BS_POLICY_LEARNED)
+            return fail(BS_E_POLICY, "the treecode far field needs the FIXED or LEARNED policy");
+        if (!(p->tree_theta > 0.0 && p->tree_theta < 1.0)) return fail(BS_E_POLICY, "tree_theta must lie in (0, 1)");
+        if (p->tree_order != 2 && p->tree_order != 4 && p->tree_order != 6)
+            return fail(BS_E_POLICY, "tree_order must be 2, 4 or 6 (got %d)", p->tree_order);
+    }
     return BS_OK;
 }
 
@@ -1032,6 +1371,9 @@ void bs_policy_default(bs_policy *p)
     p->gauss_rule = BS_RULE_G1;
     p->precision = BS_PREC_FP32_COMP;
     p->conf_min = 0.9f;
+    p->far_field = BS_FAR_ALL_PAIRS;
+    p->tree_theta = 0.3;
+    p->tree_order = 4;
 }
 
 const char *bs_status_string(int s)
@@ -1161,7 +1503,10 @@ void bs_mesh_free(bs_mesh *m)
                     &m->nbr, &m->inc_start, &m->inc_list, &m->fallback,
                     &m->cell_start, &m->part, &m->band, &m->rtv, &m->vel, &m->cnt, &m->nonfinite, &m->dir,
                     &m->dir64, &m->cphi, &m->dia, &m->mlp, &m->sel, &m->torig, &m->tlist, &m->tvel,
-                    &m->gvel, &m->tgrad, &m->ngrad, &m->om64, &m->srate};
+                    &m->gvel, &m->tgrad, &m->ngrad, &m->om64, &m->srate,
+                    &m->tree.nrange, &m->tree.child, &m->tree.leaves, &m->tree.c64, &m->tree.crec,
+                    &m->tree.src64, &m->tree.g1t, &m->tree.tidt, &m->tree.M, &m->tree.N, &m->tree.acc_start,
+                    &m->tree.acc, &m->tree.dir_start, &m->tree.dir};
     for (DBuf *b : bufs) dfree(*b);
     for (auto &a : m->aux)
         if (a) (void)hipStreamSynchronize(a);
@@ -1187,6 +1532,12 @@ int bs_set_policy(bs_mesh *m, const bs_policy *p)
     }
     m->pol = *p;
     m->pol.mlp_bf16 = nullptr;
+    // the treecode's plan for the current positions (no evaluation builds it)
+    const auto &tp = m->tree;
+    if (uses_treecode(m->pol) &&
+        !(tp.valid && tp.theta == p->tree_theta && tp.order == p->tree_order && tp.d_g4 == p->d_g4) &&
+        (rc = build_tree_plan(m, nullptr)))
+        return rc;
     // the angular tables of the policy's orders, so that an evaluation never
     // has to allocate them
     return install_angular(m);
@@ -1202,7 +1553,7 @@ bool far_on_matrix_cores(const bs_mesh *m)
 {
     const bs_policy &P = m->pol;
     const bool fixed_like = P.kind == BS_POLICY_FIXED || P.kind == BS_POLICY_LEARNED;
-    return fixed_like && P.precision != BS_PREC_FP64 && m->far_mode == 0;
+    return fixed_like && P.precision != BS_PREC_FP64 && m->far_mode == 0 && P.far_field == BS_FAR_ALL_PAIRS;
 }
 
 // Tet splits of the all-pairs Gauss kernels (0: no far-field kernel).  The
@@ -1216,6 +1567,7 @@ int far_splits(const bs_mesh *m)
     const bool gauss_all =
         P.kind == BS_POLICY_FIXED || P.kind == BS_POLICY_LEARNED || P.kind == BS_POLICY_GAUSS_ONLY;
     if (!gauss_all || m->T <= 0) return 0;
+    if (uses_treecode(P)) return 2; // expansions, direct leaves
     const int node_blocks = m->npad / 1024;
     if (far_on_matrix_cores(m)) {
         const int base = std::max(1, std::min<int>(8, (int)((m->T + 2047) / 2048)));
@@ -1261,6 +1613,8 @@ int eval_device(bs_mesh *m, hipStream_t s, bool targets, const EvalBufs *given =
 
     const bool fixed_like = P.kind == BS_POLICY_FIXED || P.kind == BS_POLICY_LEARNED;
     const bool far_mfma = far_on_matrix_cores(m);
+    const bool treecode = uses_treecode(P);
+    if (treecode && !m->tree.valid) return fail(BS_E_STATE, "treecode plan missing (set the policy again)");
     const int splits = far_splits(m);
     if (splits > 0 && !given && (rc = dalloc(m->part, 8 * 3 * (size_t)m->npad * splits))) return rc;
     double *b_part = given ? given->part : (double *)m->part.p;
@@ -1325,6 +1679,12 @@ int eval_device(bs_mesh *m, hipStream_t s, bool targets, const EvalBufs *given =
             if ((e = bsk::launch_gauss_all(dm, pts, P.precision, splits, b_part, s)))
                 return hip_fail(e, "gauss kernel");
             part = b_part;
+        } else if (treecode) {
+            const bsk::TreeView tv = tree_view(m);
+            if ((e = bsk::launch_tree_moments(tv, m->tree.level_start.data(), (int)m->tree.level_start.size() - 1, s)) ||
+                (e = bsk::launch_tree_far(dm, tv, th.g4_2, th.inc_far, P.precision, b_part, s)))
+                return hip_fail(e, "treecode far field");
+            part = b_part;
         } else if (far_mfma) {
             if ((e = bsk::launch_far_mfma(dm, th, P.precision, splits, b_part, s)))
                 return hip_fail(e, "far-field kernel");
@@ -1340,7 +1700,7 @@ int eval_device(bs_mesh *m, hipStream_t s, bool targets, const EvalBufs *given =
     hipStream_t sb = one_stream ? s : m->aux[0], sr = one_stream ? s : m->aux[1];
     record(2, sb);
     if (m->T > 0 && fixed_like) {
-        if ((e = bsk::launch_band(dm, th, P.precision, far_mfma ? 0 : 1, b_band, cnt, sb)))
+        if ((e = bsk::launch_band(dm, th, P.precision, (far_mfma || treecode) ? 0 : 1, b_band, cnt, sb)))
             return hip_fail(e, "band kernel");
         band = b_band;
     }
@@ -1448,6 +1808,10 @@ int read_stats(bs_mesh *m, bs_stats *st)
     st->reoriented = m->reoriented;
     st->nonfinite_out = nf;
     st->hbar = m->hbar;
+    if (uses_treecode(P) && m->tree.valid) {
+        st->tree_expansions = m->last_targets ? m->tree.exp_pts : m->tree.exp_nodes;
+        st->tree_direct = m->last_targets ? m->tree.dir_pts : m->tree.dir_nodes;
+    }
     return BS_OK;
 }
 

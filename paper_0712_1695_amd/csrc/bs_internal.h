@@ -131,6 +131,39 @@ hipError_t launch_stretching(int n, const double *grad, const double *om, double
 hipError_t launch_combine(const DevMesh &m, const int *node_orig, const double *part, int splits,
                           const double *band, const double *rtv, double *vel, int *nonfinite, hipStream_t s);
 
+// Treecode far field (BS_FAR_TREECODE): the plan the host builds and the
+// per-evaluation moment buffers.  Clusters are numbered breadth first, so
+// every tree level is a contiguous range of ids; tets are in tree order
+// (each cluster a contiguous range).  Lists are indexed by global block id
+// (node blocks, then the evaluation points' blocks from blk0 of their view).
+struct TreeView {
+    int order;            // expansion order P (2, 4 or 6)
+    int nnode, nleaf;
+    const int2 *nrange;   // [nnode] tet range [x, y) in tree order
+    const int2 *child;    // [nnode] children, (-1, -1) for a leaf
+    const int *leaves;    // [nleaf] leaf ids
+    const double *c64;    // [nnode][4] centre (FP64)
+    const float *crec;    // [nnode][8] centre split hi.xyz, lo.xyz (binary32), 0, 0
+    const double *src64;  // [T][8] centroid xyz, W xyz (FP64), 0, 0, tree order
+    const float *g1t;     // [T][8] binary32 centroid, W, 0, 0, tree order
+    const int4 *tidt;     // [T] vertex slots, tree order
+    double *M;            // [nnode][ncoef(P)][3] moments about the centre (FP64)
+    float *N;             // [nnode][ncoef(P+1) - 1][3] curl moments (binary32)
+    const int *acc_start, *acc; // per block: accepted clusters (CSR)
+    const int *dir_start, *dir; // per block: leaves summed pair by pair (CSR)
+};
+// Multi-indices of degree <= d.
+constexpr int tree_ncoef(int d) { return (d + 1) * (d + 2) * (d + 3) / 6; }
+// Moments of every cluster for the current sources: P2M at the leaves, then
+// M2M level by level (levels [level_start[L], level_start[L+1]), nlevel of
+// them), then the curl moments.
+hipError_t launch_tree_moments(const TreeView &t, const int *level_start, int nlevel, hipStream_t s);
+// Expansions into part[0] and direct leaves into part[1] ([2][3][npad]) for
+// the view's blocks.  g4_2: the rule's binary32 squared 4-point cut;
+// inc: test incidence in direct leaves (a tet vertex can lie beyond the cut).
+hipError_t launch_tree_far(const DevMesh &m, const TreeView &t, float g4_2, int inc, int precision, double *part,
+                           hipStream_t s);
+
 // Zero `words` 32-bit words at p (a kernel, so that the clearing can sit in
 // a captured graph where memset nodes are avoided).
 hipError_t launch_fill_zero(void *p, size_t words, hipStream_t s);

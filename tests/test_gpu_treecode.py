@@ -1,0 +1,240 @@
+"""GPU parity of the treecode far field (BS_FAR_TREECODE) against the FP64
+reference of the same definition (oracle/treecode.py), through the C ABI.
+
+Expected velocity: the oracle's fixed-rule velocity, minus its 1-point
+pairs summed directly, plus the reference treecode's far field (same tree,
+same acceptance, FP64 expansions).  Tolerances as the all-pairs parity
+tests (rel-L2 1e-6, per node 5e-6 of max(|v_i|, rms |v|)): the two sides
+differ by binary32 rounding only.  The interaction counts the library
+reports must equal the reference's exactly, so both took the same
+acceptance decisions on every (block, cluster).  At the two-ring size the
+library's treecode is compared with its own all-pairs sum within the
+truncation bound, per node.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import treecode as TC
+import paper_0712_1695_amd as bs
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+NODE_TOL = 5e-6
+SMALL_CUTS = dict(near_cut=1.0, d_g11=1.5, d_g4=2.0)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    torch.cuda.set_device(0)
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def check(a, b, label, tol=TOL, node_tol=NODE_TOL):
+    e = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    scale = np.sqrt(np.mean(np.sum(b * b, axis=1)))
+    per = np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), scale)
+    _say(f"  {label}: rel-L2 {e:.3e}, worst node {per.max():.3e} (of {len(per)})")
+    assert e <= tol, (label, e)
+    assert per.max() <= node_tol, (label, per.max(), int(per.argmax()))
+
+
+def expected(m, tc, theta, order, targets, cuts):
+    pol = oracle.make_policy("fixed", **cuts)
+    v = oracle.evaluate(m.xyz, m.omega, m.tets, pol, targets=targets)
+    return v - tc.direct_far(targets) + tc.far(theta, order, targets)
+
+
+def counts(tc, theta):
+    blocks = list(range(len(tc.block_nodes)))
+    ex = dp = 0
+    for b, (acc, direct) in zip(blocks, tc.lists(theta, blocks)):
+        nb = len(tc.block_nodes[b])
+        ex += len(acc) * nb
+        dp += sum(len(tc.cluster_tets(j)) for j in direct) * nb
+    return ex, dp
+
+
+def gpu_tree(m, theta, order, precision=bs.BS_PREC_FP32_COMP, **pol):
+    h = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
+    try:
+        bs.bs_set_policy(h, far_field="treecode", tree_theta=theta, tree_order=order, precision=precision, **pol)
+        return bs.bs_eval_velocity(h, stats=True)
+    finally:
+        bs.bs_mesh_free(h)
+
+
+@pytest.mark.parametrize("theta,order", [(0.3, 2), (0.3, 4), (0.5, 4), (0.5, 6), (0.7, 6)])
+def test_treecode_matches_reference_c1(theta, order):
+    m = W.make_config("C1")
+    _say(f"treecode on C1, theta {theta}, order {order}, cuts 1 / 1.5 / 2")
+    hbar = oracle.mean_edge(m.xyz, m.tets)
+    tc = TC.Treecode(m.xyz, m.omega, m.tets, hbar, d_g4=SMALL_CUTS["d_g4"])
+    allnodes = np.arange(m.n_nodes)
+    ref = expected(m, tc, theta, order, allnodes, SMALL_CUTS)
+    v, st = gpu_tree(m, theta, order, **SMALL_CUTS)
+    check(v, ref, f"theta {theta} P {order}")
+    ex, dp = counts(tc, theta)
+    _say(f"  expansions {st['tree_expansions']} (reference {ex}), direct pairs {st['tree_direct']} (reference {dp})")
+    assert (st["tree_expansions"], st["tree_direct"]) == (ex, dp)
+    assert ex > 0 and dp > 0
+
+
+@pytest.mark.parametrize("precision", [bs.BS_PREC_FP32_NAIVE, bs.BS_PREC_FP64])
+def test_treecode_precision_modes_c1(precision):
+    m = W.make_config("C1")
+    _say(f"treecode on C1, precision {precision}")
+    hbar = oracle.mean_edge(m.xyz, m.tets)
+    tc = TC.Treecode(m.xyz, m.omega, m.tets, hbar, d_g4=SMALL_CUTS["d_g4"])
+    ref = expected(m, tc, 0.5, 4, np.arange(m.n_nodes), SMALL_CUTS)
+    v, _ = gpu_tree(m, 0.5, 4, precision=precision, **SMALL_CUTS)
+    check(v, ref, f"precision {precision}")
+
+
+def test_treecode_incident_pairs_beyond_the_cut():
+    """Cuts below the largest vertex-centroid distance: direct leaves must
+    take the incidence test (the rule's ray-traced pairs stay out)."""
+    m = W.make_config("C1")
+    hbar = oracle.mean_edge(m.xyz, m.tets)
+    cuts = dict(near_cut=0.2, d_g11=0.3, d_g4=0.4)
+    _say("treecode on C1 with cuts 0.2 / 0.3 / 0.4 (incident pairs beyond the 4-point cut)")
+    tc = TC.Treecode(m.xyz, m.omega, m.tets, hbar, d_g4=cuts["d_g4"])
+    assert tc.vcmax > cuts["d_g4"] * hbar
+    ref = expected(m, tc, 0.5, 4, np.arange(m.n_nodes), cuts)
+    v, st = gpu_tree(m, 0.5, 4, **cuts)
+    check(v, ref, "small cuts")
+    assert (st["tree_expansions"], st["tree_direct"]) == counts(tc, 0.5)
+
+
+def test_treecode_ragged_mesh():
+    """A mesh whose node and tet counts are not multiples of 64."""
+    m = W.make_config("C1", scale=(7, 9, 5))
+    assert m.n_nodes % 64 and m.n_tets % 64
+    _say(f"treecode on a ragged box mesh ({m.n_nodes} nodes, {m.n_tets} tets)")
+    hbar = oracle.mean_edge(m.xyz, m.tets)
+    cuts = dict(near_cut=1.0, d_g11=1.2, d_g4=1.5)
+    tc = TC.Treecode(m.xyz, m.omega, m.tets, hbar, d_g4=cuts["d_g4"])
+    ref = expected(m, tc, 0.5, 4, np.arange(m.n_nodes), cuts)
+    v, st = gpu_tree(m, 0.5, 4, **cuts)
+    check(v, ref, "ragged")
+    assert (st["tree_expansions"], st["tree_direct"]) == counts(tc, 0.5)
+
+
+def test_treecode_matches_reference_ring_sampled():
+    m = W.make_config("C2")
+    rng = np.random.default_rng(21)
+    targets = np.sort(rng.choice(m.n_nodes, 128, replace=False))
+    _say("treecode on C2 (default theta 0.3, order 4), 128 sampled nodes")
+    hbar = oracle.mean_edge(m.xyz, m.tets)
+    tc = TC.Treecode(m.xyz, m.omega, m.tets, hbar)
+    ref = expected(m, tc, 0.3, 4, targets, {})
+    v, st = gpu_tree(m, 0.3, 4)
+    check(v[targets], ref, "C2 sampled")
+    full = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("fixed"), targets=targets)
+    err = np.linalg.norm(v[targets] - full) / np.linalg.norm(full)
+    _say(f"  against the all-pairs sum: rel-L2 {err:.3e}; expansions {st['tree_expansions']:.3e}, "
+         f"direct pairs {st['tree_direct']:.3e} of {m.n_nodes * m.n_tets:.3e}")
+    assert err < 1e-4
+
+
+def test_treecode_with_the_learned_policy():
+    """The learned policy changes ray-traced pairs only, so its treecode
+    result minus its all-pairs result is the reference's treecode minus
+    direct sum, whatever the selector decides."""
+    import json
+    import os
+
+    m = W.make_config("C1")
+    blob = np.array(json.load(open(os.path.join(os.path.dirname(__file__), "golden", "selector_blob.json")))["blob_bf16_bits"],
+                    dtype=np.uint16)
+    hbar = oracle.mean_edge(m.xyz, m.tets)
+    tc = TC.Treecode(m.xyz, m.omega, m.tets, hbar, d_g4=SMALL_CUTS["d_g4"])
+    allnodes = np.arange(m.n_nodes)
+    want = tc.far(0.5, 4, allnodes) - tc.direct_far(allnodes)
+    h = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
+    try:
+        bs.bs_set_policy(h, kind=bs.BS_POLICY_LEARNED, mlp_bf16=blob, **SMALL_CUTS)
+        v_all = bs.bs_eval_velocity(h)
+        bs.bs_set_policy(h, kind=bs.BS_POLICY_LEARNED, mlp_bf16=blob, far_field="treecode", tree_theta=0.5,
+                         tree_order=4, **SMALL_CUTS)
+        v_tree = bs.bs_eval_velocity(h)
+    finally:
+        bs.bs_mesh_free(h)
+    d = v_tree - v_all
+    err = np.abs(d - want).max() / np.abs(v_all).max()
+    _say(f"learned + treecode: max |(tree - all) - reference| / max |v| = {err:.3e} "
+         f"(treecode change {np.abs(want).max() / np.abs(v_all).max():.3e})")
+    assert err <= NODE_TOL
+
+
+def test_treecode_at_points_and_after_moving_the_nodes():
+    """Evaluation points get their own blocks; moving the nodes rebuilds the
+    plan.  Both against the all-pairs result within the truncation error."""
+    m = W.make_config("C1")
+    rng = np.random.default_rng(22)
+    pts = rng.uniform(-0.95, 0.95, size=(300, 3))
+    h = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
+    try:
+        for step in range(2):
+            bs.bs_set_policy(h, **SMALL_CUTS)
+            pa = bs.bs_eval_points(h, pts)
+            va = bs.bs_eval_velocity(h)
+            bs.bs_set_policy(h, far_field="treecode", tree_theta=0.3, tree_order=6, **SMALL_CUTS)
+            pt = bs.bs_eval_points(h, pts)
+            vt = bs.bs_eval_velocity(h)
+            ep = np.abs(pt - pa).max() / np.abs(pa).max()
+            ev = np.abs(vt - va).max() / np.abs(va).max()
+            _say(f"  step {step}: points {ep:.3e}, nodes {ev:.3e} (treecode vs all pairs, order 6)")
+            assert ep < 1e-5 and ev < 1e-5
+            # move the nodes (same connectivity) and do it again
+            xyz = m.xyz + 0.01 * np.sin(3 * m.xyz[:, [1, 2, 0]])
+            bs.bs_mesh_update(h, xyz, None)
+    finally:
+        bs.bs_mesh_free(h)
+
+
+def test_treecode_two_rings_within_the_truncation_bound():
+    """Full size (80^3 cells): at 256 sampled nodes the library's treecode
+    differs from its own all-pairs far field by at most the sum of the
+    accepted clusters' truncation bounds plus binary32 rounding."""
+    m = W.make_config("C5")
+    rng = np.random.default_rng(23)
+    targets = np.sort(rng.choice(m.n_nodes, 256, replace=False))
+    h = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
+    try:
+        va = bs.bs_eval_velocity(h)
+        bs.bs_set_policy(h, far_field="treecode", tree_theta=0.3, tree_order=4)
+        vt, st = bs.bs_eval_velocity(h, stats=True)
+    finally:
+        bs.bs_mesh_free(h)
+    hbar = oracle.mean_edge(m.xyz, m.tets)
+    tc = TC.Treecode(m.xyz, m.omega, m.tets, hbar)
+    torder, start, end, _, _ = tc.tree
+    absW = np.linalg.norm(tc.W, axis=1)
+    cum = np.concatenate([[0.0], np.cumsum(absW[torder])])
+    blocks = np.unique(tc.block_of[targets])
+    lists = dict(zip(blocks, tc.lists(0.3, blocks)))
+    scale = np.abs(va).max()
+    worst = 0.0
+    for i in targets:
+        acc, _ = lists[tc.block_of[i]]
+        bound = 0.0
+        for j in acc:
+            cS, rS = tc.csph[j]
+            R = np.linalg.norm(m.xyz[i] - cS)
+            bound += TC.truncation_bound(cum[end[j]] - cum[start[j]], rS, R, 4)
+        e = np.linalg.norm(vt[i] - va[i])
+        assert e <= bound + 2e-6 * scale, (i, e, bound)
+        worst = max(worst, e / (bound + 2e-6 * scale))
+    err = np.linalg.norm(vt[targets] - va[targets]) / np.linalg.norm(va[targets])
+    _say(f"two rings: treecode vs all pairs rel-L2 {err:.3e}; worst error / (bound + rounding) {worst:.3f}; "
+         f"expansions {st['tree_expansions']:.3e}, direct pairs {st['tree_direct']:.3e}, "
+         f"far field {st['t_kernel_s'][0] * 1e3:.1f} ms")
