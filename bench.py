@@ -18,6 +18,11 @@ Besides the headline, the same JSON line carries:
               settings (cuts, lines) timed beside the learned policy: the
               speed ratio to the fastest fixed setting whose error is not
               above the learned policy's is "vs_fixed_equal_accuracy";
+  treecode    the fixed and learned policies with the treecode far field
+              (BS_FAR_TREECODE, theta 0.3, order 4: the fast-multipole-like
+              evaluation of the 1-point pairs): time, error at the probes,
+              speed against the same policy summing every pair, the far
+              field's roofline;
   valu_far    the fixed rule with the far field on the vector ALUs
               (k_gauss_all, the design without matrix cores) and its roofline;
   c2, c3      the vortex-ring workload (97,175 nodes x 540,672 tets; the
@@ -52,6 +57,26 @@ DEFAULT_CUTS = (2.0, 4.0, 8.0)
 # equal-accuracy comparison: narrower ray-traced zones and more lines are
 # more accurate at 16 x 16 and above
 LADDER = ((1.5, 4.0, 8.0, 24), (1.5, 4.0, 8.0, 32), (1.0, 4.0, 8.0, 24), (2.0, 4.0, 8.0, 32), (2.0, 4.0, 8.0, 48))
+TREE_THETA, TREE_ORDER = 0.3, 4  # the treecode leg's opening ratio and expansion order
+
+
+def expansion_flops(P):
+    """Flops of one (node, cluster) expansion term as formulated: the
+    offset from the centre's hi/lo split (9), |r|^2 (5), reciprocal and
+    reciprocal square root (2), two scalings per degree (4 per degree), per
+    Taylor coefficient of degree 1..P+1 the recurrence (2 per r_c term less 1,
+    one add per further a_(m-2e_c) term, 1 mul, 2 for the second sum's FMA)
+    and 6 for the contraction with the curl moments."""
+    D = P + 1
+    fl = 9 + 5 + 2 + 4 * D
+    for n in range(1, D + 1):
+        for i in range(n, -1, -1):
+            for j in range(n - i, -1, -1):
+                m = (i, j, n - i - j)
+                k1 = sum(1 for c in m if c >= 1)
+                k2 = sum(1 for c in m if c >= 2)
+                fl += 2 * k1 - 1 + 1 + ((k2 - 1) + 2 if k2 else 0) + 6
+    return fl
 
 
 def algorithmic_flops(st, nm):
@@ -221,6 +246,16 @@ def kernel_rooflines(st, kern, nm, workload, policy, precision, valu_far=False):
     ]
 
 
+def tree_roofline(st, kern, order, workload, policy, precision):
+    """The treecode far field (moments, expansions and direct leaves
+    together, one duration): 26 flops per 1-point pair of the direct leaves,
+    expansion_flops per expansion term."""
+    direct_g1 = st["pairs_by_rule"][0] - st["tree_covered"]
+    kflops = FLOPS_PER_POINT * direct_g1 + expansion_flops(order) * st["tree_expansions"]
+    return roof_entry("k_tree_direct+k_tree_m2p", "treecode far field: direct leaves and expansions, vector ALUs, "
+                      "with the moment passes", "alu", kflops, kern[0], workload, policy, precision)
+
+
 def train_selector(W):
     """The learned policy's network, trained on the GPU (outside any timed
     region) on 10 million pairs of the swirl box and the ring box, and
@@ -244,6 +279,8 @@ def main():
     ap.add_argument("--serial", action="store_true", help="time the headline steps with every kernel on one stream")
     ap.add_argument("--valu-far", action="store_true",
                     help="headline far field on the vector ALUs instead of the matrix cores")
+    ap.add_argument("--far", default="all_pairs", choices=["all_pairs", "treecode"],
+                    help="far field of the headline step (treecode: the profiling runs of the treecode kernels)")
     ap.add_argument("--heun-steps", type=int, default=10, help="Heun steps of the Lagrangian leg (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -269,7 +306,10 @@ def main():
     blob, sel_info = train_selector(W) if (args.policy == "learned" or not args.quick) else (None, None)
     learned_pol = dict(kind=bs.BS_POLICY_LEARNED, n_phi=16, n_theta=16, mlp_bf16=blob, conf_min=0.9)
     fixed_pol = dict(kind=bs.BS_POLICY_FIXED, n_phi=16, n_theta=16)
-    head_pol = learned_pol if args.policy == "learned" else fixed_pol
+    head_pol = dict(learned_pol if args.policy == "learned" else fixed_pol)
+    tree_kw = dict(far_field=bs.BS_FAR_TREECODE, tree_theta=TREE_THETA, tree_order=TREE_ORDER)
+    if args.far == "treecode":
+        head_pol.update(tree_kw)
     flags = dict(valu_far=args.valu_far)
 
     mesh = W.make_config(args.workload)
@@ -288,6 +328,8 @@ def main():
 
     flops = algorithmic_flops(st_head, nm)
     kernels = kernel_rooflines(st_head, kern, nm, args.workload, args.policy, args.precision, args.valu_far)
+    if args.far == "treecode":
+        kernels[0] = tree_roofline(st_head, kern, TREE_ORDER, args.workload, args.policy, args.precision)
     roof = dict(max(kernels, key=lambda r: r["avg_duration_ms"]))
     cuts = "RT < 2 hbar, G11 < 4, G4 < 8, else G1"
     line = {
@@ -308,6 +350,7 @@ def main():
                         f"{mesh.n_tets} tets, {args.policy} policy "
                         f"({'selector on the pairs the fixed rule ray-traces, ' if args.policy == 'learned' else ''}"
                         f"{cuts}), 16x16 lines, "
+                        f"{'treecode far field (theta %.1f, order %d), ' % (TREE_THETA, TREE_ORDER) if args.far == 'treecode' else ''}"
                         f"{['fp32 naive', 'fp32 compensated', 'fp64 accumulation'][args.precision]}",
             "pairs_per_step": B.pairs,
             "pairs_by_rule": st_head["pairs_by_rule"],
@@ -364,6 +407,34 @@ def main():
                 "fixed_reaches_learned_error": bool(ok),
                 "vs_fixed_equal_accuracy": best["ms_per_step"] / (t_head * 1e3),
             }
+
+        # ---- the treecode far field with both policies
+        if args.policy == "learned" and args.far == "all_pairs":
+            tree = {"theta": TREE_THETA, "order": TREE_ORDER,
+                    "what": "BS_FAR_TREECODE: the 1-point pairs by a batched Barnes-Hut treecode (clusters of the "
+                            "k-d tree of the centroids, Cartesian expansions, 64-node target blocks), every other "
+                            "pair as in the all-pairs evaluation"}
+            for name, pol, t_ref in (("fixed", fixed_pol, t_fix), ("learned", learned_pol, t_head)):
+                t0 = time.perf_counter()
+                B.set_policy(**pol, **tree_kw)
+                t_plan = time.perf_counter() - t0
+                t = B.time(steps2, 1)
+                err = B.error()
+                kt, st_t, _ = B.kernels(steps2)
+                tree[name] = {"ms_per_step": t * 1e3, "probe_error": err, "vs_all_pairs_speed": t_ref / t,
+                              "plan_s": t_plan, "tree_expansions": st_t["tree_expansions"],
+                              "tree_direct": st_t["tree_direct"], "tree_covered": st_t["tree_covered"],
+                              "kernel_ms_serial": {"far": kt[0] * 1e3, "band": kt[1] * 1e3, "rt": kt[2] * 1e3},
+                              "roofline_far": tree_roofline(st_t, kt, TREE_ORDER, args.workload, name,
+                                                            args.precision)}
+                print(f"bench: treecode {name} {t * 1e3:.2f} ms (error {err:.3e}, {t_ref / t:.2f}x all pairs)",
+                      flush=True)
+            ok = [r for r in line["accuracy"]["fixed_ladder"] if r["probe_error"] <= tree["learned"]["probe_error"]] \
+                if "accuracy" in line else []
+            if ok:
+                best = min(ok, key=lambda r: r["ms_per_step"])
+                tree["learned_vs_fixed_all_pairs_equal_accuracy"] = best["ms_per_step"] / tree["learned"]["ms_per_step"]
+            line["treecode"] = tree
 
         # ---- the far field on the vector ALUs (the design without matrix cores)
         B.set_policy(**fixed_pol)

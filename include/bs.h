@@ -198,6 +198,7 @@ typedef struct {
     double hbar;              /* mean edge length                              */
     int64_t tree_expansions;  /* TREECODE: (node, cluster) expansion terms     */
     int64_t tree_direct;      /* TREECODE: (node, tet) pairs of direct leaves  */
+    int64_t tree_covered;     /* TREECODE: (node, tet) pairs the expansions sum */
 } bs_stats;
 
 /* Velocity at every node, written to vel ([n_nodes][3] FP64, input node

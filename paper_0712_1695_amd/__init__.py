@@ -91,6 +91,7 @@ class Stats(ctypes.Structure):
         ("hbar", ctypes.c_double),
         ("tree_expansions", ctypes.c_int64),
         ("tree_direct", ctypes.c_int64),
+        ("tree_covered", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -98,7 +99,7 @@ class Stats(ctypes.Structure):
                     pairs_by_rule=list(self.pairs_by_rule), rt_hit_lines=self.rt_hit_lines,
                     fp64_retests=self.fp64_retests, reoriented=self.reoriented,
                     nonfinite_out=self.nonfinite_out, hbar=self.hbar, tree_expansions=self.tree_expansions,
-                    tree_direct=self.tree_direct)
+                    tree_direct=self.tree_direct, tree_covered=self.tree_covered)
 
 
 # every symbol include/bs.h declares

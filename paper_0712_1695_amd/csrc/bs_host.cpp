@@ -250,6 +250,7 @@ struct bs_mesh {
         int order = 0, nnode = 0, nleaf = 0;
         std::vector<int> level_start; // tree level L: clusters [level_start[L], level_start[L+1])
         int64_t exp_nodes = 0, dir_nodes = 0, exp_pts = 0, dir_pts = 0; // expansion terms, direct pairs
+        int64_t cov_nodes = 0, cov_pts = 0; // pairs the expansions sum
         DBuf nrange, child, leaves, c64, crec, src64, g1t, tidt, M, N, acc_start, acc, dir_start, dir;
     } tree;
     std::vector<int32_t> h_torig; // evaluation points in their k-d order (host copy)
@@ -266,6 +267,7 @@ struct bs_mesh {
     // timing: 0 start, 1 far field done (caller's stream); 2-3 band (aux[0]);
     // 4-5 ray tracing (aux[1]); 6-7 combine (caller's stream)
     hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr; // treecode: the moments are done, band and ray tracing may start
     hipStream_t aux[2] = {nullptr, nullptr}; // the band and ray-tracing kernels run beside the far field
 };
 
@@ -711,7 +713,7 @@ int build_tree_plan(bs_mesh *m, hipStream_t s)
         tp.order = P.tree_order;
         tp.d_g4 = P.d_g4;
         tp.nnode = tp.nleaf = 0;
-        tp.exp_nodes = tp.dir_nodes = tp.exp_pts = tp.dir_pts = 0;
+        tp.exp_nodes = tp.dir_nodes = tp.exp_pts = tp.dir_pts = tp.cov_nodes = tp.cov_pts = 0;
         tp.valid = true;
         return BS_OK;
     }
@@ -799,19 +801,23 @@ int build_tree_plan(bs_mesh *m, hipStream_t s)
         }
     });
     std::vector<int> acc_start((size_t)nbt + 1, 0), dir_start((size_t)nbt + 1, 0);
-    tp.exp_nodes = tp.dir_nodes = tp.exp_pts = tp.dir_pts = 0;
+    tp.exp_nodes = tp.dir_nodes = tp.exp_pts = tp.dir_pts = tp.cov_nodes = tp.cov_pts = 0;
     for (int b = 0; b < nbt; ++b) {
         acc_start[(size_t)b + 1] = acc_start[(size_t)b] + (int)acc[(size_t)b].size();
         dir_start[(size_t)b + 1] = dir_start[(size_t)b] + (int)dir[(size_t)b].size();
-        int64_t dt = 0;
+        int64_t dt = 0, ct = 0;
         for (int j : dir[(size_t)b]) dt += range[(size_t)j].y - range[(size_t)j].x;
-        const int64_t ex = (int64_t)acc[(size_t)b].size() * bcount[(size_t)b], dp = dt * bcount[(size_t)b];
+        for (int j : acc[(size_t)b]) ct += range[(size_t)j].y - range[(size_t)j].x;
+        const int64_t ex = (int64_t)acc[(size_t)b].size() * bcount[(size_t)b], dp = dt * bcount[(size_t)b],
+                      cv = ct * bcount[(size_t)b];
         if (b < m->nblk) {
             tp.exp_nodes += ex;
             tp.dir_nodes += dp;
+            tp.cov_nodes += cv;
         } else {
             tp.exp_pts += ex;
             tp.dir_pts += dp;
+            tp.cov_pts += cv;
         }
     }
     std::vector<int> acc_list((size_t)std::max(1, acc_start.back())), dir_list((size_t)std::max(1, dir_start.back()));
@@ -876,6 +882,14 @@ int build_tree_plan(bs_mesh *m, hipStream_t s)
     tp.d_g4 = P.d_g4;
     tp.valid = true;
     return BS_OK;
+}
+
+// Parts each target block's treecode lists are cut into: about four waves
+// per wave slot of the chip (256 CUs x 4 SIMDs x 8) over the node blocks.
+int tree_chunks(const bs_mesh *m)
+{
+    const int nb = std::max(1, m->nblk);
+    return std::max(1, std::min(bsk::kTreeMaxChunks, (32768 + nb - 1) / nb));
 }
 
 bsk::TreeView tree_view(bs_mesh *m)
@@ -1471,6 +1485,10 @@ int bs_mesh_upload(const bs_mesh_desc *d, bs_mesh **out)
             bs_mesh_free(m);
             return fail(BS_E_DEVICE, "hipEventCreate");
         }
+    if (hipEventCreate(&m->ev_fork) != hipSuccess) {
+        bs_mesh_free(m);
+        return fail(BS_E_DEVICE, "hipEventCreate");
+    }
     for (auto &a : m->aux)
         if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess) {
             bs_mesh_free(m);
@@ -1512,6 +1530,7 @@ void bs_mesh_free(bs_mesh *m)
         if (a) (void)hipStreamSynchronize(a);
     for (auto &e : m->ev)
         if (e) (void)hipEventDestroy(e);
+    if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
     for (auto &a : m->aux)
         if (a) (void)hipStreamDestroy(a);
     delete m;
@@ -1567,7 +1586,7 @@ int far_splits(const bs_mesh *m)
     const bool gauss_all =
         P.kind == BS_POLICY_FIXED || P.kind == BS_POLICY_LEARNED || P.kind == BS_POLICY_GAUSS_ONLY;
     if (!gauss_all || m->T <= 0) return 0;
-    if (uses_treecode(P)) return 2; // expansions, direct leaves
+    if (uses_treecode(P)) return 2 * tree_chunks(m); // expansions, direct leaves
     const int node_blocks = m->npad / 1024;
     if (far_on_matrix_cores(m)) {
         const int base = std::max(1, std::min<int>(8, (int)((m->T + 2047) / 2048)));
@@ -1670,8 +1689,20 @@ int eval_device(bs_mesh *m, hipStream_t s, bool targets, const EvalBufs *given =
         if (!given) (void)hipEventRecord(m->ev[k], st);
     };
     record(0, s);
+    // the treecode's moments first, alone: a chain of small launches (one per
+    // tree level) that would otherwise wait for slots behind the band and
+    // ray-tracing kernels
+    const bsk::TreeView tv = treecode ? tree_view(m) : bsk::TreeView{};
+    if (treecode && m->T > 0 &&
+        (e = bsk::launch_tree_moments(tv, m->tree.level_start.data(), (int)m->tree.level_start.size() - 1, s)))
+        return hip_fail(e, "treecode moments");
+    hipEvent_t fork = m->ev[0];
+    if (!one_stream && treecode) {
+        fork = m->ev_fork;
+        if ((e = hipEventRecord(fork, s))) return hip_fail(e, "fork event");
+    }
     if (!one_stream &&
-        ((e = hipStreamWaitEvent(m->aux[0], m->ev[0], 0)) || (e = hipStreamWaitEvent(m->aux[1], m->ev[0], 0))))
+        ((e = hipStreamWaitEvent(m->aux[0], fork, 0)) || (e = hipStreamWaitEvent(m->aux[1], fork, 0))))
         return hip_fail(e, "fork streams");
     if (m->T > 0) {
         if (P.kind == BS_POLICY_GAUSS_ONLY) {
@@ -1680,9 +1711,7 @@ int eval_device(bs_mesh *m, hipStream_t s, bool targets, const EvalBufs *given =
                 return hip_fail(e, "gauss kernel");
             part = b_part;
         } else if (treecode) {
-            const bsk::TreeView tv = tree_view(m);
-            if ((e = bsk::launch_tree_moments(tv, m->tree.level_start.data(), (int)m->tree.level_start.size() - 1, s)) ||
-                (e = bsk::launch_tree_far(dm, tv, th.g4_2, th.inc_far, P.precision, b_part, s)))
+            if ((e = bsk::launch_tree_far(dm, tv, th.g4_2, th.inc_far, P.precision, tree_chunks(m), b_part, s)))
                 return hip_fail(e, "treecode far field");
             part = b_part;
         } else if (far_mfma) {
@@ -1811,6 +1840,7 @@ int read_stats(bs_mesh *m, bs_stats *st)
     if (uses_treecode(P) && m->tree.valid) {
         st->tree_expansions = m->last_targets ? m->tree.exp_pts : m->tree.exp_nodes;
         st->tree_direct = m->last_targets ? m->tree.dir_pts : m->tree.dir_nodes;
+        st->tree_covered = m->last_targets ? m->tree.cov_pts : m->tree.cov_nodes;
     }
     return BS_OK;
 }

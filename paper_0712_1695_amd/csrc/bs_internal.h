@@ -158,11 +158,14 @@ constexpr int tree_ncoef(int d) { return (d + 1) * (d + 2) * (d + 3) / 6; }
 // M2M level by level (levels [level_start[L], level_start[L+1]), nlevel of
 // them), then the curl moments.
 hipError_t launch_tree_moments(const TreeView &t, const int *level_start, int nlevel, hipStream_t s);
-// Expansions into part[0] and direct leaves into part[1] ([2][3][npad]) for
-// the view's blocks.  g4_2: the rule's binary32 squared 4-point cut;
-// inc: test incidence in direct leaves (a tet vertex can lie beyond the cut).
-hipError_t launch_tree_far(const DevMesh &m, const TreeView &t, float g4_2, int inc, int precision, double *part,
-                           hipStream_t s);
+// Expansions into part[0 .. chunks) and direct leaves into part[chunks ..
+// 2 chunks) ([2 chunks][3][npad]) for the view's blocks, each block's lists
+// cut into `chunks` parts (1 .. kTreeMaxChunks).  g4_2: the rule's binary32
+// squared 4-point cut; inc: test incidence in direct leaves (a tet vertex
+// can lie beyond the cut).
+constexpr int kTreeMaxChunks = 8;
+hipError_t launch_tree_far(const DevMesh &m, const TreeView &t, float g4_2, int inc, int precision, int chunks,
+                           double *part, hipStream_t s);
 
 // Zero `words` 32-bit words at p (a kernel, so that the clearing can sit in
 // a captured graph where memset nodes are avoided).

@@ -13,16 +13,20 @@
 //   k_tree_curl  the curl moments N_m = sum_c (-1)^(|m|-1) m_c e_c x M_{m-e_c},
 //                1 <= |m| <= P+1, binary32, so that the expansion's velocity
 //                is v(x) = sum_m a_m(x - c) N_m with a_m = d^m (1/|r|) / m!;
-//   k_tree_m2p   one wave per target block, lane = node: the accepted
-//                clusters' expansions, a_m by the Lindsay-Krasny recurrence
+//   k_tree_m2p   one wave per (target block, chunk of its list), lane =
+//                node: the accepted clusters' expansions, a_m by the
+//                Lindsay-Krasny recurrence
 //                n |r|^2 a_m + (2n-1) sum_c r_c a_{m-e_c} + (n-1) sum_c a_{m-2e_c} = 0
 //                in registers, N_m as scalar operands, one TwoSum fold per
 //                cluster;
-//   k_tree_direct one wave per target block, lane = node: the pairs of the
-//                block's direct leaves that the fixed rule gives the 1-point
-//                rule (its binary32 test), one TwoSum fold per leaf.
-// Waves take blocks in contiguous k-d ranges per XCD (workgroup ids are dealt
-// to the eight XCDs in turn), so each XCD's L2 holds one region's clusters.
+//   k_tree_direct one wave per (target block, chunk of its list), lane =
+//                node: the pairs of the block's direct leaves that the fixed
+//                rule gives the 1-point rule (its binary32 test), one TwoSum
+//                fold per leaf.
+// Every chunk writes a partial buffer of its own; the combine kernel adds
+// them in FP64 in a fixed order.  Waves take blocks in contiguous k-d ranges
+// per XCD (workgroup ids are dealt to the eight XCDs in turn), so each XCD's
+// L2 holds one region's clusters.
 #include "bs_internal.h"
 
 #include <utility>
@@ -278,21 +282,36 @@ __global__ void __launch_bounds__(256) k_tree_curl(TreeView t)
 
 // ---- evaluation
 
-// Target block of this wave: workgroup ids are dealt to the eight XCDs in
-// turn, and XCD x takes logical workgroups [x per_xcd, (x+1) per_xcd), so
-// each XCD walks one contiguous range of k-d blocks.  -1 past the end.
-__device__ __forceinline__ int tree_block(int per_xcd, int nblk)
+// Work item of this wave: (target block, chunk of its list).  Workgroup ids
+// are dealt to the eight XCDs in turn, and XCD x takes logical workgroups
+// [x per_xcd, (x+1) per_xcd), so each XCD walks one contiguous range of k-d
+// blocks; the chunks of a block are neighbours.  Each block's list is cut
+// into `chunks` parts (many short waves rather than one per block, so that
+// the last waves do not run alone).  Returns the block, or -1 past the end.
+__device__ __forceinline__ int tree_item(int per_xcd, int nblk, int chunks, int &chunk)
 {
     const int g = blockIdx.x;
     const int lg = (g & 7) * per_xcd + (g >> 3);
-    const int b = 4 * lg + (threadIdx.x >> 6);
+    const int w = 4 * lg + (threadIdx.x >> 6);
+    const int b = w / chunks;
+    chunk = w - b * chunks;
     return b < nblk ? b : -1;
 }
 
-template <int P, int PREC>
-__global__ void __launch_bounds__(256) k_tree_m2p(DevMesh m, TreeView t, int per_xcd, double *__restrict__ part)
+// Entries [q0, q1) of list [a, b) for chunk c of `chunks`.
+__device__ __forceinline__ void chunk_range(int a, int b, int c, int chunks, int &q0, int &q1)
 {
-    const int b = tree_block(per_xcd, m.nblk);
+    const int len = b - a;
+    q0 = a + (int)(((long long)len * c) / chunks);
+    q1 = a + (int)(((long long)len * (c + 1)) / chunks);
+}
+
+template <int P, int PREC>
+__global__ void __launch_bounds__(256) k_tree_m2p(DevMesh m, TreeView t, int per_xcd, int chunks,
+                                                   double *__restrict__ part)
+{
+    int chunk;
+    const int b = tree_item(per_xcd, m.nblk, chunks, chunk);
     if (b < 0) return;
     constexpr int NC = tree_ncoef(P + 1) - 1;
     const int gb = m.blk0 + b;
@@ -302,7 +321,8 @@ __global__ void __launch_bounds__(256) k_tree_m2p(DevMesh m, TreeView t, int per
     const float xl = m.xl[p], yl = m.xl[np + p], zl = m.xl[2 * np + p];
     float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
     double dx = 0.0, dy = 0.0, dz = 0.0;
-    const int a0 = t.acc_start[gb], a1 = t.acc_start[gb + 1];
+    int a0, a1;
+    chunk_range(t.acc_start[gb], t.acc_start[gb + 1], chunk, chunks, a0, a1);
     for (int q = a0; q < a1; ++q) {
         const int j = t.acc[q];
         const float *cr = t.crec + 8 * (size_t)j;
@@ -330,16 +350,18 @@ __global__ void __launch_bounds__(256) k_tree_m2p(DevMesh m, TreeView t, int per
         dy = (double)sy + (double)cy;
         dz = (double)sz + (double)cz;
     }
-    part[p] = dx;
-    part[np + p] = dy;
-    part[2 * np + p] = dz;
+    double *o = part + (size_t)chunk * 3 * np;
+    o[p] = dx;
+    o[np + p] = dy;
+    o[2 * np + p] = dz;
 }
 
 template <int PREC, int INC>
-__global__ void __launch_bounds__(256) k_tree_direct(DevMesh m, TreeView t, float g4_2, int per_xcd,
+__global__ void __launch_bounds__(256) k_tree_direct(DevMesh m, TreeView t, float g4_2, int per_xcd, int chunks,
                                                       double *__restrict__ part)
 {
-    const int b = tree_block(per_xcd, m.nblk);
+    int chunk;
+    const int b = tree_item(per_xcd, m.nblk, chunks, chunk);
     if (b < 0) return;
     const int gb = m.blk0 + b;
     const int p = 64 * gb + (threadIdx.x & 63);
@@ -347,7 +369,8 @@ __global__ void __launch_bounds__(256) k_tree_direct(DevMesh m, TreeView t, floa
     const float x = m.xh[p], y = m.xh[np + p], z = m.xh[2 * np + p];
     float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
     double dx = 0.0, dy = 0.0, dz = 0.0;
-    const int l0 = t.dir_start[gb], l1 = t.dir_start[gb + 1];
+    int l0, l1;
+    chunk_range(t.dir_start[gb], t.dir_start[gb + 1], chunk, chunks, l0, l1);
     for (int q = l0; q < l1; ++q) {
         const int2 r = t.nrange[t.dir[q]];
         float ax = 0.f, ay = 0.f, az = 0.f;
@@ -391,9 +414,10 @@ __global__ void __launch_bounds__(256) k_tree_direct(DevMesh m, TreeView t, floa
         dy = (double)sy + (double)cy;
         dz = (double)sz + (double)cz;
     }
-    part[p] = dx;
-    part[np + p] = dy;
-    part[2 * np + p] = dz;
+    double *o = part + (size_t)chunk * 3 * np;
+    o[p] = dx;
+    o[np + p] = dy;
+    o[2 * np + p] = dz;
 }
 
 template <int P>
@@ -419,26 +443,29 @@ hipError_t moments_p(const TreeView &t, const int *level_start, int nlevel, hipS
 }
 
 template <int P, int PREC>
-void launch_m2p(const DevMesh &m, const TreeView &t, int per_xcd, double *part, hipStream_t s)
+void launch_m2p(const DevMesh &m, const TreeView &t, int per_xcd, int chunks, double *part, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_tree_m2p<P, PREC>), dim3(8 * per_xcd), dim3(256), 0, s, m, t, per_xcd, part);
+    hipLaunchKernelGGL((k_tree_m2p<P, PREC>), dim3(8 * per_xcd), dim3(256), 0, s, m, t, per_xcd, chunks, part);
 }
 
 template <int PREC>
-void launch_m2p_prec(const DevMesh &m, const TreeView &t, int per_xcd, double *part, hipStream_t s)
+void launch_m2p_prec(const DevMesh &m, const TreeView &t, int per_xcd, int chunks, double *part, hipStream_t s)
 {
-    if (t.order == 2) launch_m2p<2, PREC>(m, t, per_xcd, part, s);
-    else if (t.order == 4) launch_m2p<4, PREC>(m, t, per_xcd, part, s);
-    else launch_m2p<6, PREC>(m, t, per_xcd, part, s);
+    if (t.order == 2) launch_m2p<2, PREC>(m, t, per_xcd, chunks, part, s);
+    else if (t.order == 4) launch_m2p<4, PREC>(m, t, per_xcd, chunks, part, s);
+    else launch_m2p<6, PREC>(m, t, per_xcd, chunks, part, s);
 }
 
 template <int PREC>
-void launch_direct(const DevMesh &m, const TreeView &t, float g4_2, int inc, int per_xcd, double *part, hipStream_t s)
+void launch_direct(const DevMesh &m, const TreeView &t, float g4_2, int inc, int per_xcd, int chunks, double *part,
+                   hipStream_t s)
 {
     if (inc)
-        hipLaunchKernelGGL((k_tree_direct<PREC, 1>), dim3(8 * per_xcd), dim3(256), 0, s, m, t, g4_2, per_xcd, part);
+        hipLaunchKernelGGL((k_tree_direct<PREC, 1>), dim3(8 * per_xcd), dim3(256), 0, s, m, t, g4_2, per_xcd, chunks,
+                           part);
     else
-        hipLaunchKernelGGL((k_tree_direct<PREC, 0>), dim3(8 * per_xcd), dim3(256), 0, s, m, t, g4_2, per_xcd, part);
+        hipLaunchKernelGGL((k_tree_direct<PREC, 0>), dim3(8 * per_xcd), dim3(256), 0, s, m, t, g4_2, per_xcd, chunks,
+                           part);
 }
 
 } // namespace
@@ -451,23 +478,24 @@ hipError_t launch_tree_moments(const TreeView &t, const int *level_start, int nl
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_tree_far(const DevMesh &m, const TreeView &t, float g4_2, int inc, int precision, double *part,
-                           hipStream_t s)
+hipError_t launch_tree_far(const DevMesh &m, const TreeView &t, float g4_2, int inc, int precision, int chunks,
+                           double *part, hipStream_t s)
 {
     if (t.order != 2 && t.order != 4 && t.order != 6) return hipErrorInvalidValue;
+    if (chunks < 1 || chunks > kTreeMaxChunks) return hipErrorInvalidValue;
     if (m.nblk <= 0) return hipSuccess;
-    const int wg = (m.nblk + 3) / 4;
+    const int wg = (m.nblk * chunks + 3) / 4;
     const int per_xcd = (wg + 7) / 8;
-    double *p0 = part, *p1 = part + 3 * (size_t)m.npad;
+    double *p0 = part, *p1 = part + 3 * (size_t)m.npad * chunks;
     if (precision == 0) {
-        launch_m2p_prec<0>(m, t, per_xcd, p0, s);
-        launch_direct<0>(m, t, g4_2, inc, per_xcd, p1, s);
+        launch_m2p_prec<0>(m, t, per_xcd, chunks, p0, s);
+        launch_direct<0>(m, t, g4_2, inc, per_xcd, chunks, p1, s);
     } else if (precision == 1) {
-        launch_m2p_prec<1>(m, t, per_xcd, p0, s);
-        launch_direct<1>(m, t, g4_2, inc, per_xcd, p1, s);
+        launch_m2p_prec<1>(m, t, per_xcd, chunks, p0, s);
+        launch_direct<1>(m, t, g4_2, inc, per_xcd, chunks, p1, s);
     } else {
-        launch_m2p_prec<2>(m, t, per_xcd, p0, s);
-        launch_direct<2>(m, t, g4_2, inc, per_xcd, p1, s);
+        launch_m2p_prec<2>(m, t, per_xcd, chunks, p0, s);
+        launch_direct<2>(m, t, g4_2, inc, per_xcd, chunks, p1, s);
     }
     return hipGetLastError();
 }
