@@ -292,7 +292,10 @@ __device__ __forceinline__ int tree_item(int per_xcd, int nblk, int chunks, int 
 {
     const int g = blockIdx.x;
     const int lg = (g & 7) * per_xcd + (g >> 3);
-    const int w = 4 * lg + (threadIdx.x >> 6);
+    // the wave's index, made uniform for the compiler: every list index and
+    // record address below is then wave-uniform (scalar loads, scalar loop
+    // control) rather than per lane
+    const int w = 4 * lg + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int b = w / chunks;
     chunk = w - b * chunks;
     return b < nblk ? b : -1;
