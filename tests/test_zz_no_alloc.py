@@ -2,8 +2,8 @@
 through the C ABI: its velocities against bs_eval_velocity's on the same
 mesh, on two calls in a row (the second with a smaller mesh, so that the
 static scratch holds the first call's contents), for the fixed and learned
-policies and the vector-ALU far field; a mesh too large for the scratch is
-refused before anything runs."""
+policies, the vector-ALU far field and the treecode far field; a mesh too
+large for the scratch is refused before anything runs."""
 import ctypes
 import json
 import os
@@ -63,7 +63,9 @@ def test_noalloc_matches_eval_velocity_two_calls(bs):
     cases = [("fixed", dict(kind=bs.BS_POLICY_FIXED), False),
              ("fixed, vector-ALU far field", dict(kind=bs.BS_POLICY_FIXED), True),
              ("learned", dict(kind=bs.BS_POLICY_LEARNED, mlp_bf16=bits, conf_min=float(blob["conf_min"])), False),
-             ("pure ray tracing 8x12", dict(kind=bs.BS_POLICY_PURE_RT, n_phi=8, n_theta=12), False)]
+             ("pure ray tracing 8x12", dict(kind=bs.BS_POLICY_PURE_RT, n_phi=8, n_theta=12), False),
+             ("fixed, treecode far field", dict(kind=bs.BS_POLICY_FIXED, near_cut=1.0, d_g11=1.5, d_g4=2.0,
+                                                far_field="treecode", tree_theta=0.5, tree_order=4), False)]
     for label, pol, valu in cases:
         for cells in ((12, 11, 10), (5, 6, 4)):  # second call smaller: the scratch keeps the first's contents
             m = W.make_config("C1", scale=cells)
