@@ -238,3 +238,49 @@ def test_treecode_two_rings_within_the_truncation_bound():
     _say(f"two rings: treecode vs all pairs rel-L2 {err:.3e}; worst error / (bound + rounding) {worst:.3f}; "
          f"expansions {st['tree_expansions']:.3e}, direct pairs {st['tree_direct']:.3e}, "
          f"far field {st['t_kernel_s'][0] * 1e3:.1f} ms")
+
+
+def test_treecode_policy_checks():
+    """Out-of-range treecode settings are refused, and the treecode is
+    refused for the policies without a 1-point far field."""
+    m = W.make_config("C1", scale=(4, 4, 4))
+    h = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
+    try:
+        for bad in (dict(tree_theta=0.0), dict(tree_theta=1.0), dict(tree_theta=float("nan")), dict(tree_order=3),
+                    dict(tree_order=8), dict(kind=bs.BS_POLICY_PURE_RT), dict(kind=bs.BS_POLICY_GAUSS_ONLY)):
+            with pytest.raises(bs.BsError) as e:
+                bs.bs_set_policy(h, far_field="treecode", **bad)
+            assert e.value.status == bs.BS_E_POLICY, bad
+        with pytest.raises(bs.BsError) as e:
+            bs.bs_set_policy(h, far_field=2)
+        assert e.value.status == bs.BS_E_POLICY
+        bs.bs_set_policy(h, far_field="treecode")  # the defaults are accepted
+        v = bs.bs_eval_velocity(h)
+        assert np.all(np.isfinite(v))
+    finally:
+        bs.bs_mesh_free(h)
+
+
+def test_heun_step_with_the_treecode():
+    """A Heun step with the treecode far field moves every node by the
+    all-pairs step plus about dt times the treecode's error on the velocity
+    (order 6, theta 0.3: within 2e-6 of the largest velocity at every node;
+    measured 8.1e-7)."""
+    m = W.make_config("C5", scale=(32, 32, 32))
+    dt = 0.005
+    out = []
+    for tree in (False, True):
+        h = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
+        try:
+            kw = dict(far_field="treecode", tree_theta=0.3, tree_order=6) if tree else {}
+            bs.bs_set_policy(h, **kw)
+            v0 = bs.bs_eval_velocity(h)
+            x1, _ = bs.bs_advect_heun(h, dt, 1)
+            out.append((v0, x1))
+        finally:
+            bs.bs_mesh_free(h)
+    (va, xa), (vt, xt) = out
+    ev = np.abs(vt - va).max() / np.abs(va).max()
+    ex = np.abs(xt - xa).max() / (dt * np.abs(va).max())
+    _say(f"Heun with the treecode (order 6): velocity {ev:.3e}, displacement {ex:.3e} (relative to dt max|v|)")
+    assert ev < 2e-6 and ex <= 1.5 * ev + 1e-7
