@@ -167,6 +167,86 @@ void parallel_for(int64_t n, F &&f)
     for (auto &t : th) t.join();
 }
 
+// f(i) for every i in [0, count), items dealt to up to 16 threads.
+template <class F>
+void parallel_items(int64_t count, F &&f)
+{
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int64_t nt = std::min<int64_t>(std::min<unsigned>(hw ? hw : 1u, 16u), count);
+    if (nt <= 1) {
+        for (int64_t i = 0; i < count; ++i) f(i);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    std::vector<std::thread> th;
+    for (int64_t k = 0; k < nt; ++k)
+        th.emplace_back([&] {
+            for (int64_t i; (i = next.fetch_add(1)) < count;) f(i);
+        });
+    for (auto &t : th) t.join();
+}
+
+// Stable counting sort of the keys key(i) in [0, nkeys) of items
+// i in [0, count): start[nkeys + 1] (CSR offsets) and out[start[key] ..] =
+// the items of each key in increasing i, as a sequential pass would leave
+// them; contiguous ranges of i are counted and placed by separate threads
+// (at most 16, fewer when a per-thread count array would be large).
+template <class K>
+void stable_bucket(int64_t count, int64_t nkeys, K &&key, std::vector<int32_t> &start, std::vector<int32_t> &out)
+{
+    start.assign((size_t)nkeys + 1, 0);
+    out.resize((size_t)count);
+    const int64_t nc = std::max<int64_t>(1, std::min<int64_t>({16, (int64_t)((1ll << 25) / std::max<int64_t>(nkeys, 1)),
+                                                                 count / 4096 + 1}));
+    std::vector<std::vector<int32_t>> cnt((size_t)nc);
+    auto lo = [&](int64_t c) { return count * c / nc; };
+    parallel_items(nc, [&](int64_t c) {
+        auto &h = cnt[(size_t)c];
+        h.assign((size_t)nkeys, 0);
+        for (int64_t i = lo(c); i < lo(c + 1); ++i) h[(size_t)key(i)]++;
+    });
+    // start of every key; then each chunk's first slot per key
+    for (int64_t k = 0; k < nkeys; ++k) {
+        int32_t tot = 0;
+        for (int64_t c = 0; c < nc; ++c) tot += cnt[(size_t)c][(size_t)k];
+        start[(size_t)k + 1] = start[(size_t)k] + tot;
+    }
+    for (int64_t k = 0; k < nkeys; ++k) {
+        int32_t at = start[(size_t)k];
+        for (int64_t c = 0; c < nc; ++c) {
+            const int32_t v = cnt[(size_t)c][(size_t)k];
+            cnt[(size_t)c][(size_t)k] = at;
+            at += v;
+        }
+    }
+    parallel_items(nc, [&](int64_t c) {
+        auto &h = cnt[(size_t)c];
+        for (int64_t i = lo(c); i < lo(c + 1); ++i) out[(size_t)h[(size_t)key(i)]++] = (int32_t)i;
+    });
+}
+
+// Pinned host memory (hipHostMalloc), grown on demand and kept: the
+// staging of the records uploaded at every rebuild.
+struct PinnedBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+int pinned_reserve(PinnedBuf &b, size_t bytes)
+{
+    if (b.p && b.bytes >= bytes) return BS_OK;
+    if (b.p) (void)hipHostFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    hipError_t e = hipHostMalloc(&b.p, std::max<size_t>(bytes, 256), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return hip_fail(e, "hipHostMalloc (record staging)");
+    }
+    b.bytes = std::max<size_t>(bytes, 256);
+    return BS_OK;
+}
+
 // Node slots (nodes, then evaluation points from the next multiple of 1024,
 // padded to a multiple of 1024) are indexed in 32-bit int by the kernels as
 // c * npad + i for c < 3: 3 * 2^29 stays below 2^31.  The tet count is held
@@ -223,7 +303,7 @@ struct bs_mesh {
     std::vector<float> h_xh;                            // binary32 node coordinates, input node order
     std::vector<int32_t> nbr_in;  // [T][4] face neighbours (input tet numbering, -1 boundary)
     std::vector<int64_t> edge_keys; // unique edges, sorted (lo * (n + 1) + hi); built on first use
-    std::vector<float> h_g1, h_g4, h_g11; // host staging of the Gauss records (reused between builds)
+    PinnedBuf h_g1, h_g4, h_g11; // pinned host staging of the Gauss records (reused between builds)
     std::vector<int4> h_tid;
     bool manifold = true;         // every face shared by at most two tets
     bool convex = false;          // boundary is one closed, locally convex surface (rays never re-enter)
@@ -531,30 +611,40 @@ std::vector<int32_t> kd_leaf_order(const double *X, int64_t n)
     struct Range {
         int64_t a, b;
     };
-    std::vector<Range> stack{{0, n}};
-    while (!stack.empty()) {
-        const Range r = stack.back();
-        stack.pop_back();
-        const int64_t len = r.b - r.a;
-        if (len <= bsk::kBlockNodes) continue;
-        double lo3[3] = {1e300, 1e300, 1e300}, hi3[3] = {-1e300, -1e300, -1e300};
-        for (int64_t k = r.a; k < r.b; ++k)
-            for (int c = 0; c < 3; ++c) {
-                const double v = X[3 * (int64_t)orig[(size_t)k] + c];
-                lo3[c] = std::min(lo3[c], v);
-                hi3[c] = std::max(hi3[c], v);
-            }
-        int ax = 0;
-        for (int c = 1; c < 3; ++c)
-            if (hi3[c] - lo3[c] > hi3[ax] - lo3[ax]) ax = c;
-        int64_t k = ((len / 2 + bsk::kBlockNodes / 2) / bsk::kBlockNodes) * bsk::kBlockNodes;
-        k = std::min(std::max<int64_t>(k, bsk::kBlockNodes), len - 1);
-        std::nth_element(orig.begin() + r.a, orig.begin() + r.a + k, orig.begin() + r.b, [&](int32_t u, int32_t v) {
-            const double xu = X[3 * (int64_t)u + ax], xv = X[3 * (int64_t)v + ax];
-            return xu < xv || (xu == xv && u < v);
+    // the ranges of one level are split in parallel: each split depends only
+    // on its own range, so the order is that of splitting them one by one
+    std::vector<Range> level{{0, n}};
+    while (!level.empty()) {
+        std::vector<int64_t> ks(level.size(), 0);
+        parallel_items((int64_t)level.size(), [&](int64_t q) {
+            const Range r = level[(size_t)q];
+            const int64_t len = r.b - r.a;
+            if (len <= bsk::kBlockNodes) return;
+            double lo3[3] = {1e300, 1e300, 1e300}, hi3[3] = {-1e300, -1e300, -1e300};
+            for (int64_t k = r.a; k < r.b; ++k)
+                for (int c = 0; c < 3; ++c) {
+                    const double v = X[3 * (int64_t)orig[(size_t)k] + c];
+                    lo3[c] = std::min(lo3[c], v);
+                    hi3[c] = std::max(hi3[c], v);
+                }
+            int ax = 0;
+            for (int c = 1; c < 3; ++c)
+                if (hi3[c] - lo3[c] > hi3[ax] - lo3[ax]) ax = c;
+            int64_t k = ((len / 2 + bsk::kBlockNodes / 2) / bsk::kBlockNodes) * bsk::kBlockNodes;
+            k = std::min(std::max<int64_t>(k, bsk::kBlockNodes), len - 1);
+            std::nth_element(orig.begin() + r.a, orig.begin() + r.a + k, orig.begin() + r.b, [&](int32_t u, int32_t v) {
+                const double xu = X[3 * (int64_t)u + ax], xv = X[3 * (int64_t)v + ax];
+                return xu < xv || (xu == xv && u < v);
+            });
+            ks[(size_t)q] = k;
         });
-        stack.push_back({r.a + k, r.b});
-        stack.push_back({r.a, r.a + k});
+        std::vector<Range> next;
+        for (size_t q = 0; q < level.size(); ++q)
+            if (ks[q]) {
+                next.push_back({level[q].a, level[q].a + ks[q]});
+                next.push_back({level[q].a + ks[q], level[q].b});
+            }
+        level.swap(next);
     }
     return orig;
 }
@@ -591,25 +681,6 @@ void block_spheres(const std::vector<float> &xh, int npad, int64_t p0, int64_t c
 bool uses_treecode(const bs_policy &P)
 {
     return P.far_field == BS_FAR_TREECODE && (P.kind == BS_POLICY_FIXED || P.kind == BS_POLICY_LEARNED);
-}
-
-// f(i) for every i in [0, count), items dealt to up to 16 threads.
-template <class F>
-void parallel_items(int64_t count, F &&f)
-{
-    const unsigned hw = std::thread::hardware_concurrency();
-    const int64_t nt = std::min<int64_t>(std::min<unsigned>(hw ? hw : 1u, 16u), count);
-    if (nt <= 1) {
-        for (int64_t i = 0; i < count; ++i) f(i);
-        return;
-    }
-    std::atomic<int64_t> next{0};
-    std::vector<std::thread> th;
-    for (int64_t k = 0; k < nt; ++k)
-        th.emplace_back([&] {
-            for (int64_t i; (i = next.fetch_add(1)) < count;) f(i);
-        });
-    for (auto &t : th) t.join();
 }
 
 // The treecode's sphere of the points P[idx[k]], k in [a, b) (FP64 [.][3]):
@@ -918,6 +989,7 @@ bsk::TreeView tree_view(bs_mesh *m)
 
 int build_device_mesh(bs_mesh *m, hipStream_t s)
 {
+    int rc;
     m->vel_valid = false;
     const int64_t n = m->n, T = m->T;
     const double *X = m->xyz.data(), *W = m->omega.data();
@@ -975,26 +1047,47 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
     std::vector<float> cen32((size_t)(3 * T));
     double clo[3] = {1e300, 1e300, 1e300}, chi[3] = {-1e300, -1e300, -1e300};
     double max_vc = 0.0;
-    for (int64_t t = 0; t < T; ++t) {
-        const int32_t *id = &m->tets[4 * t];
-        double vc = 0.0;
-        for (int c = 0; c < 3; ++c) {
-            const double v = (((X[3 * (int64_t)id[0] + c] + X[3 * (int64_t)id[1] + c]) + X[3 * (int64_t)id[2] + c]) +
-                              X[3 * (int64_t)id[3] + c]) * 0.25;
-            cen[(size_t)(3 * t + c)] = v;
-            cen32[(size_t)(3 * t + c)] = (float)v;
-            clo[c] = std::min(clo[c], v);
-            chi[c] = std::max(chi[c], v);
-        }
-        for (int j = 0; j < 4; ++j) {
-            double d2 = 0.0;
-            for (int c = 0; c < 3; ++c) {
-                const double d = X[3 * (int64_t)id[j] + c] - cen[(size_t)(3 * t + c)];
-                d2 += d * d;
+    {
+        // chunks in parallel, their extremes combined after (min and max are
+        // exact, so the result does not depend on the split)
+        const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(64, T / 4096));
+        std::vector<double> part((size_t)(7 * nch));
+        parallel_items(nch, [&](int64_t c0) {
+            double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300}, mv = 0.0;
+            for (int64_t t = T * c0 / nch; t < T * (c0 + 1) / nch; ++t) {
+                const int32_t *id = &m->tets[4 * t];
+                double vc = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    const double v = (((X[3 * (int64_t)id[0] + c] + X[3 * (int64_t)id[1] + c]) +
+                                       X[3 * (int64_t)id[2] + c]) + X[3 * (int64_t)id[3] + c]) * 0.25;
+                    cen[(size_t)(3 * t + c)] = v;
+                    cen32[(size_t)(3 * t + c)] = (float)v;
+                    lo[c] = std::min(lo[c], v);
+                    hi[c] = std::max(hi[c], v);
+                }
+                for (int j = 0; j < 4; ++j) {
+                    double d2 = 0.0;
+                    for (int c = 0; c < 3; ++c) {
+                        const double d = X[3 * (int64_t)id[j] + c] - cen[(size_t)(3 * t + c)];
+                        d2 += d * d;
+                    }
+                    vc = std::max(vc, d2);
+                }
+                mv = std::max(mv, std::sqrt(vc));
             }
-            vc = std::max(vc, d2);
+            for (int c = 0; c < 3; ++c) {
+                part[(size_t)(7 * c0 + c)] = lo[c];
+                part[(size_t)(7 * c0 + 3 + c)] = hi[c];
+            }
+            part[(size_t)(7 * c0 + 6)] = mv;
+        });
+        for (int64_t c0 = 0; c0 < nch && T > 0; ++c0) {
+            for (int c = 0; c < 3; ++c) {
+                clo[c] = std::min(clo[c], part[(size_t)(7 * c0 + c)]);
+                chi[c] = std::max(chi[c], part[(size_t)(7 * c0 + 3 + c)]);
+            }
+            max_vc = std::max(max_vc, part[(size_t)(7 * c0 + 6)]);
         }
-        max_vc = std::max(max_vc, std::sqrt(vc));
     }
     m->max_vc = max_vc;
     m->max_abs = max_abs;
@@ -1016,23 +1109,19 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
     bins.cs = (float)cs;
     m->bins = bins;
     const int64_t ncell = (int64_t)bins.dim[0] * bins.dim[1] * bins.dim[2];
-    std::vector<int32_t> cell_of((size_t)T), cell_start((size_t)ncell + 1, 0);
-    for (int64_t t = 0; t < T; ++t) {
-        int ic[3];
-        for (int c = 0; c < 3; ++c) {
-            int k = (int)std::floor((cen32[(size_t)(3 * t + c)] - bins.lo[c]) / bins.cs);
-            ic[c] = std::min(bins.dim[c] - 1, std::max(0, k));
+    std::vector<int32_t> cell_of((size_t)T), cell_start, order;
+    parallel_for(T, [&](int64_t a, int64_t b) {
+        for (int64_t t = a; t < b; ++t) {
+            int ic[3];
+            for (int c = 0; c < 3; ++c) {
+                int k = (int)std::floor((cen32[(size_t)(3 * t + c)] - bins.lo[c]) / bins.cs);
+                ic[c] = std::min(bins.dim[c] - 1, std::max(0, k));
+            }
+            cell_of[(size_t)t] = (ic[2] * bins.dim[1] + ic[1]) * bins.dim[0] + ic[0];
         }
-        const int32_t cell = (ic[2] * bins.dim[1] + ic[1]) * bins.dim[0] + ic[0];
-        cell_of[(size_t)t] = cell;
-        cell_start[(size_t)cell + 1]++;
-    }
-    for (int64_t c = 0; c < ncell; ++c) cell_start[(size_t)c + 1] += cell_start[(size_t)c];
-    std::vector<int32_t> order((size_t)T);
-    {
-        std::vector<int32_t> fill(cell_start.begin(), cell_start.end() - 1);
-        for (int64_t t = 0; t < T; ++t) order[(size_t)fill[(size_t)cell_of[(size_t)t]]++] = (int32_t)t;
-    }
+    });
+    // tets by bin, in input order within a bin
+    stable_bucket(T, ncell, [&](int64_t t) { return cell_of[(size_t)t]; }, cell_start, order);
 
     m->h_rank = rank;
     m->h_order = order;
@@ -1046,11 +1135,11 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
     // rewritten below): moving the nodes rebuilds them at each Lagrangian
     // stage, and fresh multi-GB vectors cost more to zero and fault in than
     // to fill
-    std::vector<float> &g1 = m->h_g1, &g4 = m->h_g4, &g11 = m->h_g11;
+    if ((rc = pinned_reserve(m->h_g1, 4 * (size_t)T * 8)) || (rc = pinned_reserve(m->h_g4, 4 * (size_t)T * 32)) ||
+        (rc = pinned_reserve(m->h_g11, 4 * (size_t)T * 88)))
+        return rc;
+    float *g1 = (float *)m->h_g1.p, *g4 = (float *)m->h_g4.p, *g11 = (float *)m->h_g11.p;
     std::vector<int4> &tid = m->h_tid;
-    g1.resize((size_t)T * 8);
-    g4.resize((size_t)T * 32);
-    g11.resize((size_t)T * 88);
     tid.resize((size_t)T);
     const TetRule R1 = tet_rule(1), R4 = tet_rule(4), R11 = tet_rule(11);
     parallel_for(T, [&](int64_t a, int64_t b) {
@@ -1124,40 +1213,40 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
 
     // ---- face neighbours (sorted numbering) and incident tets per node
     std::vector<int32_t> slot((size_t)T);
-    for (int64_t k = 0; k < T; ++k) slot[(size_t)order[(size_t)k]] = (int32_t)k;
+    parallel_for(T, [&](int64_t a, int64_t b) {
+        for (int64_t k = a; k < b; ++k) slot[(size_t)order[(size_t)k]] = (int32_t)k;
+    });
     std::vector<int4> nbr((size_t)T);
-    std::vector<int32_t> inc_start((size_t)n + 1, 0), inc_list((size_t)(4 * T));
-    for (int64_t k = 0; k < T; ++k) {
-        const int64_t t = order[(size_t)k];
-        int32_t q[4];
-        for (int f = 0; f < 4; ++f) {
-            const int32_t u = m->nbr_in[(size_t)(4 * t + f)];
-            q[f] = u >= 0 ? slot[(size_t)u] : -1;
-        }
-        nbr[(size_t)k] = make_int4(q[0], q[1], q[2], q[3]);
-        for (int j = 0; j < 4; ++j) inc_start[(size_t)rank[(size_t)m->tets[(size_t)(4 * t + j)]] + 1]++;
-    }
-    for (int64_t i = 0; i < n; ++i) inc_start[(size_t)i + 1] += inc_start[(size_t)i];
-    {
-        std::vector<int32_t> fill(inc_start.begin(), inc_start.end() - 1);
-        for (int64_t k = 0; k < T; ++k) {
+    parallel_for(T, [&](int64_t a, int64_t b) {
+        for (int64_t k = a; k < b; ++k) {
             const int64_t t = order[(size_t)k];
-            for (int j = 0; j < 4; ++j) inc_list[(size_t)fill[(size_t)rank[(size_t)m->tets[(size_t)(4 * t + j)]]]++] =
-                (int32_t)k;
+            int32_t q[4];
+            for (int f = 0; f < 4; ++f) {
+                const int32_t u = m->nbr_in[(size_t)(4 * t + f)];
+                q[f] = u >= 0 ? slot[(size_t)u] : -1;
+            }
+            nbr[(size_t)k] = make_int4(q[0], q[1], q[2], q[3]);
         }
-    }
+    });
+    // the tets incident to each node, in increasing sorted position: the
+    // corners 4k + j of sorted tet k bucketed by their node
+    std::vector<int32_t> inc_start, inc_list;
+    stable_bucket(4 * T, n, [&](int64_t i) { return rank[(size_t)m->tets[(size_t)(4 * order[(size_t)(i >> 2)] + (i & 3))]]; },
+                  inc_start, inc_list);
+    parallel_for(4 * T, [&](int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; ++i) inc_list[(size_t)i] >>= 2;
+    });
     m->convex = T > 0 && boundary_convex(m);
 
     // ---- upload
-    int rc;
     const size_t nb = sizeof(float) * 3 * (size_t)npad;
     if ((rc = dalloc(m->xh, nb)) || (rc = dalloc(m->xl, nb)) || (rc = dalloc(m->om, nb)) ||
         (rc = dalloc(m->nrec, sizeof(float4) * nrec.size())) ||
         (rc = dalloc(m->blk, sizeof(float4) * blk.size())) || (rc = dalloc(m->node_orig, 4 * (size_t)n)) ||
         (rc = dalloc(m->torig, 4 * torig.size())) || (rc = dalloc(m->tlist, 4 * tlist.size())) ||
         (rc = dalloc(m->tvel, 8 * 3 * (size_t)tn)) ||
-        (rc = dalloc(m->g1, 4 * g1.size())) || (rc = dalloc(m->g4, 4 * g4.size())) ||
-        (rc = dalloc(m->g11, 4 * g11.size())) || (rc = dalloc(m->tid, sizeof(int4) * (size_t)T)) ||
+        (rc = dalloc(m->g1, 4 * (size_t)T * 8)) || (rc = dalloc(m->g4, 4 * (size_t)T * 32)) ||
+        (rc = dalloc(m->g11, 4 * (size_t)T * 88)) || (rc = dalloc(m->tid, sizeof(int4) * (size_t)T)) ||
         (rc = dalloc(m->cell_start, 4 * cell_start.size())) || (rc = dalloc(m->band, 8 * 3 * (size_t)npad)) ||
         (rc = dalloc(m->rtv, 8 * 3 * (size_t)npad)) || (rc = dalloc(m->vel, 8 * 3 * (size_t)n)) ||
         (rc = dalloc(m->cnt, 8 * bsk::kNumCounters)) || (rc = dalloc(m->nonfinite, 4)) ||
@@ -1179,9 +1268,10 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
     BS_UP(node_orig, orig)
     BS_UP(torig, torig)
     BS_UP(tlist, tlist)
-    BS_UP(g1, g1)
-    BS_UP(g4, g4)
-    BS_UP(g11, g11)
+    if (T > 0 && ((e = hipMemcpyAsync(m->g1.p, g1, 4 * (size_t)T * 8, hipMemcpyHostToDevice, s)) ||
+                  (e = hipMemcpyAsync(m->g4.p, g4, 4 * (size_t)T * 32, hipMemcpyHostToDevice, s)) ||
+                  (e = hipMemcpyAsync(m->g11.p, g11, 4 * (size_t)T * 88, hipMemcpyHostToDevice, s))))
+        return hip_fail(e, "upload Gauss records");
     BS_UP(tid, tid)
     BS_UP(cell_start, cell_start)
     BS_UP(nbr, nbr)
@@ -1526,6 +1616,8 @@ void bs_mesh_free(bs_mesh *m)
                     &m->tree.src64, &m->tree.g1t, &m->tree.tidt, &m->tree.M, &m->tree.N, &m->tree.acc_start,
                     &m->tree.acc, &m->tree.dir_start, &m->tree.dir};
     for (DBuf *b : bufs) dfree(*b);
+    for (PinnedBuf *b : {&m->h_g1, &m->h_g4, &m->h_g11})
+        if (b->p) (void)hipHostFree(b->p);
     for (auto &a : m->aux)
         if (a) (void)hipStreamSynchronize(a);
     for (auto &e : m->ev)
