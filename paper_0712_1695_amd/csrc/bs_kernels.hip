@@ -1704,6 +1704,7 @@ struct WalkLds {
     float ia[kIncCap][9];  // positions relative to the node
     float iw[kIncCap][9];  // vorticity
     float in[kIncCap][9];  // canonical normals of the edges pq, qr, pr
+    float inn[kIncCap][3]; // below this magnitude an edge value takes its sign from FP64: 1e-5 (|nx| + |ny| + |nz|)
     int iid[kIncCap][3];   // node ids of p, q, r
     int imeta[kIncCap];    // bits 0-2: flip of pq, qr, pr
     int inb[kIncCap];      // tet across the face (-1: boundary)
@@ -2047,6 +2048,7 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c) W.in[lane][3 * e + c] = N[c];
+            W.inn[lane][e] = 1e-5f * (fabsf(N[0]) + fabsf(N[1]) + fabsf(N[2]));
         }
         float N[3];
         cross_canon(a[1], a[2], N);
@@ -2101,7 +2103,7 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
                 const float nx = W.in[i][3 * e], ny = W.in[i][3 * e + 1], nz = W.in[i][3 * e + 2];
                 const float c = fmaf(d.x, nx, fmaf(d.y, ny, d.z * nz));
                 int sg = c >= 0.f ? 1 : -1;
-                if (fabsf(c) <= 1e-5f * (fabsf(nx) + fabsf(ny) + fabsf(nz))) {
+                if (fabsf(c) <= W.inn[i][e]) {
                     const int ep0[3] = {0, 1, 0}, ep1[3] = {1, 2, 2};
                     const int u0 = W.iid[i][ep0[e]], u1 = W.iid[i][ep1[e]];
                     const bool fl = (meta >> e) & 1;
@@ -2116,9 +2118,12 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
             if (se[0] != se[1] || se[1] != -se[2]) continue;
             const float E1 = ce[0], E2 = ce[1], E3 = -ce[2];
             const float Sm = (E1 + E2) + E3;
-            const float r = W.ivol[i] / Sm;
+            // one reciprocal for the chord and the three weights, as in the
+            // walk's steps
+            const float inv = __builtin_amdgcn_rcpf(Sm);
+            const float r = W.ivol[i] * inv;
             if (!(r > 0.f) || !(r < 3.0e38f)) continue;
-            const float lp_ = E2 / Sm, lq = E3 / Sm, lr = E1 / Sm;
+            const float lp_ = E2 * inv, lq = E3 * inv, lr = E1 * inv;
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 w_in[c] = fmaf(lp_, W.iw[i][c], fmaf(lq, W.iw[i][3 + c], lr * W.iw[i][6 + c]));
