@@ -181,8 +181,11 @@ typedef struct {
 void bs_policy_default(bs_policy *p);
 
 /* Validate and install a policy on a mesh (copied; mlp weights copied to the
- * device).  Errors: BS_E_STATE (NULL mesh), BS_E_POLICY (out of range, bad
- * weight blob size), BS_E_DEVICE. */
+ * device; for BS_FAR_TREECODE the treecode's plan is built here and again
+ * whenever the nodes move).  Errors: BS_E_STATE (NULL mesh), BS_E_POLICY (out
+ * of range, bad weight blob size, the treecode for a policy without 1-point
+ * pairs), BS_E_NOMEM (the treecode's interaction lists beyond 2^31 entries,
+ * or no memory for them), BS_E_DEVICE. */
 int bs_set_policy(bs_mesh *m, const bs_policy *p);
 
 /* Counters of the last evaluation. */

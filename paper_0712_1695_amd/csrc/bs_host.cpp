@@ -871,6 +871,17 @@ int build_tree_plan(bs_mesh *m, hipStream_t s)
             }
         }
     });
+    {
+        // the lists are indexed in 32 bits on the device
+        int64_t na = 0, nd = 0;
+        for (int b = 0; b < nbt; ++b) {
+            na += (int64_t)acc[(size_t)b].size();
+            nd += (int64_t)dir[(size_t)b].size();
+        }
+        if (na > INT32_MAX || nd > INT32_MAX)
+            return fail(BS_E_NOMEM, "treecode interaction lists too long for 32-bit indexing (%lld, %lld entries)",
+                        (long long)na, (long long)nd);
+    }
     std::vector<int> acc_start((size_t)nbt + 1, 0), dir_start((size_t)nbt + 1, 0);
     tp.exp_nodes = tp.dir_nodes = tp.exp_pts = tp.dir_pts = tp.cov_nodes = tp.cov_pts = 0;
     for (int b = 0; b < nbt; ++b) {
