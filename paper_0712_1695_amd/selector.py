@@ -73,13 +73,27 @@ def train(meshes, tau=0.01, pairs_per_mesh=100_000, epochs=30, batch=1024, lr=2e
     blob, losses = bs_mlp_train(F[nval:], Y[nval:], epochs=epochs, batch=batch, lr=lr, class_w=tuple(cw), seed=seed)
     z = bs_mlp_logits(blob, F[:nval]).cpu().numpy()
     yv = Y[:nval].cpu().numpy()
+    rv, bv = recall(np.argmax(z, axis=1), yv)
     info = {"pairs": int(Y.shape[0]), "pairs_by_mesh": [int(y.shape[0]) for y in labels],
             "label_counts": counts.astype(int).tolist(), "tau": tau, "epochs": epochs, "batch": batch,
             "val_accuracy": float(np.mean(np.argmax(z, axis=1) == yv)),
+            "val_recall": rv, "val_balanced_accuracy": bv,
             "val_majority": float(np.max(np.bincount(yv, minlength=4)) / max(1, len(yv))),
             "final_loss": float(losses[-1]) if len(losses) else None, "label_seconds": t_label,
             "seconds": time.perf_counter() - t0}
     return blob, info
+
+
+def recall(pred, labels):
+    """Per-class recall (share of each label's pairs predicted as it, None
+    for an absent label) and balanced accuracy (their mean over present
+    labels), labels and predictions in 0..3."""
+    r = []
+    for c in range(4):
+        k = labels == c
+        r.append(float(np.mean(pred[k] == c)) if np.any(k) else None)
+    present = [x for x in r if x is not None]
+    return r, float(np.mean(present)) if present else None
 
 
 def decide(logits, conf_min):
@@ -100,15 +114,20 @@ def evaluate(blob, mesh_arrays, pairs=1_000_000, tau=0.01, conf_min=0.9, seed=9)
     """The network on pairs of one mesh (held out from training): label
     accuracy and majority share; with the library's decision at conf_min,
     the share of pairs moved to a Gauss rule and the share moved to a rule
-    whose error (against the pair's high-accuracy value) exceeds tau."""
+    whose error (against the pair's high-accuracy value) exceeds tau.  The
+    labels are imbalanced (most pairs take the 4-point rule) and training
+    weights the classes, so per-class recall and balanced accuracy say more
+    than raw accuracy against the majority share."""
     f, y, err = _pairs_of(mesh_arrays, pairs, tau, seed)
     z = bs_mlp_logits(blob, f).cpu().numpy()
     yl = y.cpu().numpy().astype(np.int64)
     e = err.cpu().numpy()
     rule = decide(z, conf_min)
+    rc, bal = recall(np.argmax(z, axis=1), yl)
     moved = rule < 3
     unsafe = moved & (e[np.arange(len(rule)), np.minimum(rule, 2)] > tau)
     return {"pairs": int(len(yl)), "accuracy": float(np.mean(np.argmax(z, axis=1) == yl)),
+            "recall": rc, "balanced_accuracy": bal,
             "majority": float(np.max(np.bincount(yl, minlength=4)) / max(1, len(yl))),
             "label_counts": np.bincount(yl, minlength=4).tolist(), "conf_min": conf_min,
             "moved": float(np.mean(moved)), "moved_with_error_above_tau": float(np.mean(unsafe)),
