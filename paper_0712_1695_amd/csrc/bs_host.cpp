@@ -332,6 +332,8 @@ struct bs_mesh {
         int64_t exp_nodes = 0, dir_nodes = 0, exp_pts = 0, dir_pts = 0; // expansion terms, direct pairs
         int64_t cov_nodes = 0, cov_pts = 0; // pairs the expansions sum
         DBuf nrange, child, leaves, c64, crec, src64, g1t, tidt, M, N, acc_start, acc, dir_start, dir;
+        DBuf torder, tin, x64, rank; // tree order, input connectivity, FP64 positions, node slots (device)
+        bool tin_valid = false;      // the connectivity is on the device (it never changes)
     } tree;
     std::vector<int32_t> h_torig; // evaluation points in their k-d order (host copy)
     int rt_mode = 0; // 0: walk where the boundary is convex, 1: always the candidate kernel
@@ -778,7 +780,7 @@ int build_tree_plan(bs_mesh *m, hipStream_t s)
     tp.valid = false;
     const bs_policy &P = m->pol;
     const int64_t n = m->n, T = m->T, tn = m->tn;
-    const double *X = m->xyz.data(), *Wn = m->omega.data();
+    const double *X = m->xyz.data();
     if (T <= 0) {
         tp.theta = P.tree_theta;
         tp.order = P.tree_order;
@@ -788,27 +790,15 @@ int build_tree_plan(bs_mesh *m, hipStream_t s)
         tp.valid = true;
         return BS_OK;
     }
-    // sources: FP64 centroids and strengths of the 1-point rule
-    std::vector<double> cen((size_t)(3 * T)), wsrc((size_t)(3 * T));
+    // FP64 centroids of the 1-point rule's sources (the tree's points; the
+    // sources themselves are laid out on the device by k_tree_sources)
+    std::vector<double> cen((size_t)(3 * T));
     parallel_for(T, [&](int64_t a, int64_t b) {
         for (int64_t t = a; t < b; ++t) {
             const int32_t *id = &m->tets[(size_t)(4 * t)];
-            double v[4][3];
-            for (int j = 0; j < 4; ++j)
-                for (int c = 0; c < 3; ++c) v[j][c] = X[3 * (int64_t)id[j] + c];
-            double e[3][3];
-            for (int j = 0; j < 3; ++j)
-                for (int c = 0; c < 3; ++c) e[j][c] = v[j + 1][c] - v[0][c];
-            const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
-                               e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
-                               e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
-            const double f = std::fabs(det) / 6.0 / (4.0 * M_PI);
-            for (int c = 0; c < 3; ++c) {
-                cen[(size_t)(3 * t + c)] = (((v[0][c] + v[1][c]) + v[2][c]) + v[3][c]) * 0.25;
-                const double w = (((Wn[3 * (int64_t)id[0] + c] + Wn[3 * (int64_t)id[1] + c]) +
-                                   Wn[3 * (int64_t)id[2] + c]) + Wn[3 * (int64_t)id[3] + c]) * 0.25;
-                wsrc[(size_t)(3 * t + c)] = f * w;
-            }
+            for (int c = 0; c < 3; ++c)
+                cen[(size_t)(3 * t + c)] = (((X[3 * (int64_t)id[0] + c] + X[3 * (int64_t)id[1] + c]) +
+                                             X[3 * (int64_t)id[2] + c]) + X[3 * (int64_t)id[3] + c]) * 0.25;
         }
     });
     std::vector<int32_t> order;
@@ -908,32 +898,15 @@ int build_tree_plan(bs_mesh *m, hipStream_t s)
         std::copy(dir[(size_t)b].begin(), dir[(size_t)b].end(), dir_list.begin() + dir_start[(size_t)b]);
     }
 
-    // per-tet sources in tree order: FP64 (moments) and binary32 (direct
-    // leaves: the rule's centroid fl32(c_t), strength), vertex slots
-    std::vector<double> src64((size_t)8 * T, 0.0);
-    std::vector<float> g1t((size_t)8 * T, 0.f);
-    std::vector<int4> tidt((size_t)T);
-    parallel_for(T, [&](int64_t a, int64_t b) {
-        for (int64_t k = a; k < b; ++k) {
-            const int64_t t = order[(size_t)k];
-            for (int c = 0; c < 3; ++c) {
-                src64[(size_t)(8 * k + c)] = cen[(size_t)(3 * t + c)];
-                src64[(size_t)(8 * k + 3 + c)] = wsrc[(size_t)(3 * t + c)];
-                g1t[(size_t)(8 * k + c)] = (float)cen[(size_t)(3 * t + c)];
-                g1t[(size_t)(8 * k + 3 + c)] = (float)wsrc[(size_t)(3 * t + c)];
-            }
-            const int32_t *id = &m->tets[(size_t)(4 * t)];
-            tidt[(size_t)k] = make_int4(m->h_rank[(size_t)id[0]], m->h_rank[(size_t)id[1]], m->h_rank[(size_t)id[2]],
-                                        m->h_rank[(size_t)id[3]]);
-        }
-    });
 
     const int NK = bsk::tree_ncoef(P.tree_order), NC = bsk::tree_ncoef(P.tree_order + 1) - 1;
     int rc;
     if ((rc = dalloc(tp.nrange, sizeof(int2) * range.size())) || (rc = dalloc(tp.child, sizeof(int2) * child.size())) ||
         (rc = dalloc(tp.leaves, 4 * leaves.size())) || (rc = dalloc(tp.c64, 8 * c64.size())) ||
-        (rc = dalloc(tp.crec, 4 * crec.size())) || (rc = dalloc(tp.src64, 8 * src64.size())) ||
-        (rc = dalloc(tp.g1t, 4 * g1t.size())) || (rc = dalloc(tp.tidt, sizeof(int4) * tidt.size())) ||
+        (rc = dalloc(tp.crec, 4 * crec.size())) || (rc = dalloc(tp.src64, 8 * 8 * (size_t)T)) ||
+        (rc = dalloc(tp.g1t, 4 * 8 * (size_t)T)) || (rc = dalloc(tp.tidt, sizeof(int4) * (size_t)T)) ||
+        (rc = dalloc(tp.torder, 4 * (size_t)T)) || (rc = dalloc(tp.tin, 16 * (size_t)T)) ||
+        (rc = dalloc(tp.x64, 8 * 3 * (size_t)n)) || (rc = dalloc(tp.rank, 4 * (size_t)n)) ||
         (rc = dalloc(tp.M, 8 * 3 * (size_t)nnode * NK)) || (rc = dalloc(tp.N, 4 * 3 * (size_t)nnode * NC)) ||
         (rc = dalloc(tp.acc_start, 4 * acc_start.size())) || (rc = dalloc(tp.acc, 4 * acc_list.size())) ||
         (rc = dalloc(tp.dir_start, 4 * dir_start.size())) || (rc = dalloc(tp.dir, 4 * dir_list.size())))
@@ -948,14 +921,22 @@ int build_tree_plan(bs_mesh *m, hipStream_t s)
     BS_UP(leaves, leaves)
     BS_UP(c64, c64)
     BS_UP(crec, crec)
-    BS_UP(src64, src64)
-    BS_UP(g1t, g1t)
-    BS_UP(tidt, tidt)
+    BS_UP(torder, order)
+    BS_UP(x64, m->xyz)
+    BS_UP(rank, m->h_rank)
+    if (!tp.tin_valid) {
+        BS_UP(tin, m->tets)
+        tp.tin_valid = true;
+    }
     BS_UP(acc_start, acc_start)
     BS_UP(acc, acc_list)
     BS_UP(dir_start, dir_start)
     BS_UP(dir, dir_list)
 #undef BS_UP
+    if ((e = bsk::launch_tree_sources((int)T, (const int *)tp.torder.p, (const int4 *)tp.tin.p, (const double *)tp.x64.p,
+                                      (const double *)m->om64.p, (const int *)tp.rank.p, (double *)tp.src64.p,
+                                      (float *)tp.g1t.p, (int4 *)tp.tidt.p, s)))
+        return hip_fail(e, "treecode sources");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "upload tree");
     tp.nnode = nnode;
     tp.nleaf = (int)leaves.size();
@@ -1625,7 +1606,8 @@ void bs_mesh_free(bs_mesh *m)
                     &m->gvel, &m->tgrad, &m->ngrad, &m->om64, &m->srate,
                     &m->tree.nrange, &m->tree.child, &m->tree.leaves, &m->tree.c64, &m->tree.crec,
                     &m->tree.src64, &m->tree.g1t, &m->tree.tidt, &m->tree.M, &m->tree.N, &m->tree.acc_start,
-                    &m->tree.acc, &m->tree.dir_start, &m->tree.dir};
+                    &m->tree.acc, &m->tree.dir_start, &m->tree.dir, &m->tree.torder, &m->tree.tin, &m->tree.x64,
+                    &m->tree.rank};
     for (DBuf *b : bufs) dfree(*b);
     for (PinnedBuf *b : {&m->h_g1, &m->h_g4, &m->h_g11})
         if (b->p) (void)hipHostFree(b->p);

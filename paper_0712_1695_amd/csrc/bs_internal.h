@@ -154,6 +154,11 @@ struct TreeView {
 };
 // Multi-indices of degree <= d.
 constexpr int tree_ncoef(int d) { return (d + 1) * (d + 2) * (d + 3) / 6; }
+// The sources in tree order (order[k]: input tet at position k; tets: input
+// connectivity; x64, w64: FP64 node positions and vorticity, input order;
+// rank: node slot of every input node) into src64, g1t and tidt.
+hipError_t launch_tree_sources(int T, const int *order, const int4 *tets, const double *x64, const double *w64,
+                               const int *rank, double *src64, float *g1t, int4 *tidt, hipStream_t s);
 // Moments of every cluster for the current sources: P2M at the leaves, then
 // M2M level by level (levels [level_start[L], level_start[L+1]), nlevel of
 // them), then the curl moments.

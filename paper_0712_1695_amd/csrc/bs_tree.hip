@@ -4,7 +4,8 @@
 //
 // The host builds the plan (bs_host.cpp): the k-d tree of the tet centroids,
 // cluster and block spheres, and per 64-node block the list of clusters it
-// accepts and the leaves it sums pair by pair.  Per evaluation, here:
+// accepts and the leaves it sums pair by pair; k_tree_sources lays the
+// sources out in tree order for it.  Per evaluation, here:
 //   k_tree_p2m   moments of every leaf about its centre, FP64:
 //                M_k = sum_t W_t (c_t - c)^k, |k| <= P;
 //   k_tree_m2m   the same for every internal cluster, level by level from
@@ -423,6 +424,51 @@ __global__ void __launch_bounds__(256) k_tree_direct(DevMesh m, TreeView t, floa
     o[2 * np + p] = dz;
 }
 
+// Per-tet sources in tree order (position k, input tet order[k]): FP64
+// centroid (((v0+v1)+v2)+v3)/4 and strength |T|/(4 pi) (((w0+w1)+w2)+w3)/4,
+// their binary32 roundings, and the vertex slots; every operation as the
+// host's, in FP64 without contraction.
+__global__ void __launch_bounds__(256) k_tree_sources(int T, const int *__restrict__ order,
+                                                      const int4 *__restrict__ tets, const double *__restrict__ x64,
+                                                      const double *__restrict__ w64, const int *__restrict__ rank,
+                                                      double *__restrict__ src64, float *__restrict__ g1t,
+                                                      int4 *__restrict__ tidt)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= T) return;
+    const int4 t4 = tets[order[k]];
+    const int id[4] = {t4.x, t4.y, t4.z, t4.w};
+    double v[4][3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[j][c] = x64[3 * (size_t)id[j] + c];
+    double e[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) e[j][c] = v[j + 1][c] - v[0][c];
+    const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                       e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                       e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+    const double f = fabs(det) / 6.0 / (4.0 * M_PI);
+    double *o = src64 + 8 * (size_t)k;
+    float *g = g1t + 8 * (size_t)k;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double cen = (((v[0][c] + v[1][c]) + v[2][c]) + v[3][c]) * 0.25;
+        const double w = (((w64[3 * (size_t)id[0] + c] + w64[3 * (size_t)id[1] + c]) + w64[3 * (size_t)id[2] + c]) +
+                          w64[3 * (size_t)id[3] + c]) * 0.25;
+        o[c] = cen;
+        o[3 + c] = f * w;
+        g[c] = (float)cen;
+        g[3 + c] = (float)(f * w);
+    }
+    o[6] = o[7] = 0.0;
+    g[6] = g[7] = 0.f;
+    tidt[k] = make_int4(rank[id[0]], rank[id[1]], rank[id[2]], rank[id[3]]);
+}
+
 template <int P>
 hipError_t moments_p(const TreeView &t, const int *level_start, int nlevel, hipStream_t s)
 {
@@ -472,6 +518,15 @@ void launch_direct(const DevMesh &m, const TreeView &t, float g4_2, int inc, int
 }
 
 } // namespace
+
+hipError_t launch_tree_sources(int T, const int *order, const int4 *tets, const double *x64, const double *w64,
+                               const int *rank, double *src64, float *g1t, int4 *tidt, hipStream_t s)
+{
+    if (T <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tree_sources, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, T, order, tets, x64, w64, rank,
+                       src64, g1t, tidt);
+    return hipGetLastError();
+}
 
 hipError_t launch_tree_moments(const TreeView &t, const int *level_start, int nlevel, hipStream_t s)
 {
