@@ -284,3 +284,31 @@ def test_heun_step_with_the_treecode():
     ex = np.abs(xt - xa).max() / (dt * np.abs(va).max())
     _say(f"Heun with the treecode (order 6): velocity {ev:.3e}, displacement {ex:.3e} (relative to dt max|v|)")
     assert ev < 2e-6 and ex <= 1.5 * ev + 1e-7
+
+
+def test_treecode_degenerate_meshes():
+    """No tets (no far field at all) and a single tet (the root cluster is a
+    leaf): the treecode gives the all-pairs velocity exactly."""
+    st1 = W.single_tet(seed=3)
+    xyz, omega, tets = st1.xyz, st1.omega, st1.tets
+    rng = np.random.default_rng(24)
+    extra = rng.uniform(-3, 3, size=(40, 3))  # nodes of no tet, far and near
+    xyz = np.vstack([xyz, extra])
+    omega = np.vstack([omega, rng.normal(size=(40, 3))])
+    for t in (tets[:0], tets):
+        h = bs.bs_mesh_upload(xyz, omega, t)
+        try:
+            bs.bs_set_policy(h, near_cut=0.5, d_g11=0.75, d_g4=1.0)
+            va = bs.bs_eval_velocity(h)
+            bs.bs_set_policy(h, near_cut=0.5, d_g11=0.75, d_g4=1.0, far_field="treecode", tree_theta=0.5,
+                             tree_order=4)
+            vt, st = bs.bs_eval_velocity(h, stats=True)
+        finally:
+            bs.bs_mesh_free(h)
+        scale = max(np.abs(va).max(), 1e-300)
+        _say(f"{len(t)} tets: treecode vs all pairs {np.abs(vt - va).max() / scale:.3e}, "
+             f"expansion terms {st['tree_expansions']}, direct pairs {st['tree_direct']}")
+        if len(t) == 0:
+            assert np.all(vt == 0.0) and np.all(va == 0.0)
+        else:
+            assert np.abs(vt - va).max() <= 1e-5 * scale
