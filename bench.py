@@ -27,8 +27,8 @@ Besides the headline, the same JSON line carries:
               (k_gauss_all, the design without matrix cores) and its roofline;
   c2, c3      the vortex-ring workload (97,175 nodes x 540,672 tets; the
               selector's training distribution) and the Fourier-curl box
-              (117,649 x 663,552; held out): fixed and learned timings and
-              errors;
+              (117,649 x 663,552; held out): fixed, learned and learned with
+              the treecode far field, timings and errors;
   lagrangian  Heun steps of the two-ring run with the learned policy
               (bs_advect_heun: mesh rebuild, two evaluations per step);
   roofline    the longest kernel of the headline step alone (HIP events on
@@ -496,15 +496,17 @@ def main():
             B2 = Bench(bs, torch, m2, args.precision)
             B2.probes = load_probes(wl)
             leg = {"workload": f"{wl}: {WORKLOAD_TEXT[wl]}, {m2.n_nodes} nodes x {m2.n_tets} tets"}
-            for name, pol in (("fixed", fixed_pol), ("learned", learned_pol)):
+            for name, pol in (("fixed", fixed_pol), ("learned", learned_pol),
+                              ("learned_treecode", dict(learned_pol, **tree_kw))):
                 B2.set_policy(**pol)
                 t = B2.time(args.steps * 2, args.warmup, **flags)
                 leg[name] = {"ms_per_step": t * 1e3, "value": B2.pairs / t, "probe_error": B2.error()}
             B2.free()
             line[wl.lower()] = leg
             print(f"bench: {wl} fixed {leg['fixed']['ms_per_step']:.2f} ms (error {leg['fixed']['probe_error']:.3e}), "
-                  f"learned {leg['learned']['ms_per_step']:.2f} ms (error {leg['learned']['probe_error']:.3e})",
-                  flush=True)
+                  f"learned {leg['learned']['ms_per_step']:.2f} ms (error {leg['learned']['probe_error']:.3e}), "
+                  f"learned + treecode {leg['learned_treecode']['ms_per_step']:.2f} ms "
+                  f"(error {leg['learned_treecode']['probe_error']:.3e})", flush=True)
 
     if not args.no_cpu_baseline and not args.quick:
         line["cpu_baseline"] = cpu_baseline(mesh)
