@@ -202,6 +202,14 @@ typedef struct {
     int64_t tree_expansions;  /* TREECODE: (node, cluster) expansion terms     */
     int64_t tree_direct;      /* TREECODE: (node, tet) pairs of direct leaves  */
     int64_t tree_covered;     /* TREECODE: (node, tet) pairs the expansions sum */
+    int64_t rt_walk_nodes;    /* nodes ray traced by walking face neighbours   */
+    int64_t rt_candidate_nodes; /* nodes ray traced by candidate rays per pair:
+                                 * off-node points, pure ray tracing on a
+                                 * boundary that is not convex, nodes with no
+                                 * or more than 48 incident tets, and, where the
+                                 * boundary is not convex, nodes with a ray
+                                 * that leaves the mesh before its last
+                                 * ray-traced tet                              */
 } bs_stats;
 
 /* Velocity at every node, written to vel ([n_nodes][3] FP64, input node
@@ -227,7 +235,7 @@ int bs_eval_velocity(bs_mesh *m, double *vel, uint32_t vel_flags, void *stream, 
  * Errors: BS_E_STATE (NULL mesh), BS_E_ARG (NULL vel, host output, unknown
  * flag, or a mesh and policy whose buffers exceed 64 MiB: 24 bytes per
  * node slot for each tet split of the far field (8 splits on the matrix
- * cores), 48 more per node slot, and 520 per node for the learned policy),
+ * cores), 48 more per node slot, and 532 per node for the learned policy),
  * BS_E_DEVICE. */
 int bs_eval_velocity_noalloc(bs_mesh *m, double *vel, uint32_t flags, void *stream);
 

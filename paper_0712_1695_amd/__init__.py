@@ -92,6 +92,8 @@ class Stats(ctypes.Structure):
         ("tree_expansions", ctypes.c_int64),
         ("tree_direct", ctypes.c_int64),
         ("tree_covered", ctypes.c_int64),
+        ("rt_walk_nodes", ctypes.c_int64),
+        ("rt_candidate_nodes", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -99,7 +101,8 @@ class Stats(ctypes.Structure):
                     pairs_by_rule=list(self.pairs_by_rule), rt_hit_lines=self.rt_hit_lines,
                     fp64_retests=self.fp64_retests, reoriented=self.reoriented,
                     nonfinite_out=self.nonfinite_out, hbar=self.hbar, tree_expansions=self.tree_expansions,
-                    tree_direct=self.tree_direct, tree_covered=self.tree_covered)
+                    tree_direct=self.tree_direct, tree_covered=self.tree_covered,
+                    rt_walk_nodes=self.rt_walk_nodes, rt_candidate_nodes=self.rt_candidate_nodes)
 
 
 # every symbol include/bs.h declares

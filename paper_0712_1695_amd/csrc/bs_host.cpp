@@ -302,6 +302,7 @@ struct bs_mesh {
     std::vector<float> h_cen32;                         // binary32 centroids, input tet order
     std::vector<float> h_xh;                            // binary32 node coordinates, input node order
     std::vector<int32_t> nbr_in;  // [T][4] face neighbours (input tet numbering, -1 boundary)
+    std::vector<int32_t> inc_in_start, inc_in_list; // corners 4t + j of every input node, by node (built once)
     std::vector<int64_t> edge_keys; // unique edges, sorted (lo * (n + 1) + hi); built on first use
     PinnedBuf h_g1, h_g4, h_g11; // pinned host staging of the Gauss records (reused between builds)
     std::vector<int4> h_tid;
@@ -319,6 +320,7 @@ struct bs_mesh {
     int t0 = 0, tblk0 = 0, tnblk = 0;
     DBuf torig, tlist, tvel;
     bool last_targets = false; // the last evaluation was of the points
+    int last_rt = 0;           // ray tracing of the last evaluation: 0 none, 1 candidate kernel, 2 walk
     bool vel_valid = false;    // vel holds the nodes' velocities at the current positions and vorticity
     DBuf gvel, tgrad, ngrad;   // velocity gradient: input velocities, per-tet |T| G and |T|, nodal G
     DBuf om64, srate;          // FP64 nodal vorticity (input order) and the stretching rate G omega
@@ -336,7 +338,7 @@ struct bs_mesh {
         bool tin_valid = false;      // the connectivity is on the device (it never changes)
     } tree;
     std::vector<int32_t> h_torig; // evaluation points in their k-d order (host copy)
-    int rt_mode = 0; // 0: walk where the boundary is convex, 1: always the candidate kernel
+    int rt_mode = 0; // 0: walk (face-manifold meshes), 1: always the candidate kernel
     int far_mode = 0; // 0: matrix-core far field (fixed-rule policies, FP32 modes), 1: vector-ALU kernel
     int serial = 0;   // 1: every kernel on the caller's stream
     DBuf dir, dir64, cphi, dia;
@@ -421,52 +423,82 @@ double mean_edge(bs_mesh *m)
     return m->edge_keys.empty() ? 0.0 : sum / (double)m->edge_keys.size();
 }
 
-int validate_geometry(bs_mesh *m)
+// Signed 6-volume of tet t (FP64) and its longest squared edge.
+double tet_det(const bs_mesh *m, int64_t t, double *h2)
 {
-    const int64_t n = m->n, T = m->T;
-    for (int64_t i = 0; i < 3 * n; ++i)
-        if (!std::isfinite(m->xyz[i]) || !std::isfinite(m->omega[i]))
-            return fail(BS_E_NONFINITE, "non-finite coordinate or vorticity at node %lld", (long long)(i / 3));
-    int64_t neg = 0;
-    for (int64_t t = 0; t < T; ++t) {
-        const int32_t *id = &m->tets[4 * t];
-        double v[4][3];
-        for (int j = 0; j < 4; ++j)
-            for (int c = 0; c < 3; ++c) v[j][c] = m->xyz[3 * (int64_t)id[j] + c];
-        double e[3][3], h2 = 0.0;
-        for (int j = 0; j < 3; ++j)
-            for (int c = 0; c < 3; ++c) e[j][c] = v[j + 1][c] - v[0][c];
+    const int32_t *id = &m->tets[4 * t];
+    double v[4][3];
+    for (int j = 0; j < 4; ++j)
+        for (int c = 0; c < 3; ++c) v[j][c] = m->xyz[3 * (int64_t)id[j] + c];
+    double e[3][3];
+    for (int j = 0; j < 3; ++j)
+        for (int c = 0; c < 3; ++c) e[j][c] = v[j + 1][c] - v[0][c];
+    if (h2) {
+        double h = 0.0;
         for (int a = 0; a < 4; ++a)
             for (int b = a + 1; b < 4; ++b) {
                 const double dx = v[b][0] - v[a][0], dy = v[b][1] - v[a][1], dz = v[b][2] - v[a][2];
-                h2 = std::max(h2, dx * dx + dy * dy + dz * dz);
+                h = std::max(h, dx * dx + dy * dy + dz * dz);
             }
-        const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
-                           e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
-                           e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+        *h2 = h;
+    }
+    return e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) - e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+           e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+}
+
+// Lower *cur to v (atomically).
+void atomic_min(std::atomic<int64_t> &cur, int64_t v)
+{
+    int64_t c = cur.load();
+    while (v < c && !cur.compare_exchange_weak(c, v)) {
+    }
+}
+
+// Every coordinate and vorticity finite, every tet of non-zero volume and,
+// after the first call, of the orientation it was uploaded with.  The tets
+// are checked in parallel; the error names the first failing node or tet,
+// as a check in order would.
+int validate_geometry(bs_mesh *m)
+{
+    const int64_t n = m->n, T = m->T;
+    std::atomic<int64_t> bad_x{INT64_MAX};
+    parallel_for(3 * n, [&](int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; ++i)
+            if (!std::isfinite(m->xyz[(size_t)i]) || !std::isfinite(m->omega[(size_t)i])) {
+                atomic_min(bad_x, i);
+                return;
+            }
+    });
+    if (bad_x.load() != INT64_MAX)
+        return fail(BS_E_NONFINITE, "non-finite coordinate or vorticity at node %lld", (long long)(bad_x.load() / 3));
+    const bool have_orient = !m->orient.empty();
+    if (!have_orient) m->orient.resize((size_t)T);
+    std::atomic<int64_t> bad_t{INT64_MAX}, neg{0};
+    parallel_for(T, [&](int64_t a, int64_t b) {
+        int64_t ng = 0;
+        for (int64_t t = a; t < b; ++t) {
+            double h2;
+            const double det = tet_det(m, t, &h2);
+            const int8_t sg = det < 0 ? -1 : 1;
+            if (!(std::fabs(det) > 1e-12 * h2 * std::sqrt(h2)) || (have_orient && m->orient[(size_t)t] != sg)) {
+                atomic_min(bad_t, t);
+                return;
+            }
+            ng += det < 0;
+            if (!have_orient) m->orient[(size_t)t] = sg;
+        }
+        neg += ng;
+    });
+    const int64_t t = bad_t.load();
+    if (t != INT64_MAX) {
+        if (!have_orient) m->orient.clear();
+        double h2;
+        const double det = tet_det(m, t, &h2);
         if (!(std::fabs(det) > 1e-12 * h2 * std::sqrt(h2)))
             return fail(BS_E_DEGENERATE, "tetrahedron %lld has zero volume", (long long)t);
-        if (det < 0) ++neg;
-        const int8_t sg = det < 0 ? -1 : 1;
-        if (!m->orient.empty() && m->orient[(size_t)t] != sg)
-            return fail(BS_E_DEGENERATE, "tetrahedron %lld inverted relative to its uploaded orientation",
-                        (long long)t);
+        return fail(BS_E_DEGENERATE, "tetrahedron %lld inverted relative to its uploaded orientation", (long long)t);
     }
-    if (m->orient.empty()) {
-        m->orient.resize((size_t)T);
-        for (int64_t t = 0; t < T; ++t) {
-            const int32_t *id = &m->tets[4 * t];
-            double e[3][3];
-            for (int j = 0; j < 3; ++j)
-                for (int c = 0; c < 3; ++c)
-                    e[j][c] = m->xyz[3 * (int64_t)id[j + 1] + c] - m->xyz[3 * (int64_t)id[0] + c];
-            const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
-                               e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
-                               e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
-            m->orient[(size_t)t] = det < 0 ? -1 : 1;
-        }
-    }
-    m->reoriented = neg;
+    m->reoriented = neg.load();
     return BS_OK;
 }
 
@@ -1220,13 +1252,24 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
             nbr[(size_t)k] = make_int4(q[0], q[1], q[2], q[3]);
         }
     });
-    // the tets incident to each node, in increasing sorted position: the
-    // corners 4k + j of sorted tet k bucketed by their node
-    std::vector<int32_t> inc_start, inc_list;
-    stable_bucket(4 * T, n, [&](int64_t i) { return rank[(size_t)m->tets[(size_t)(4 * order[(size_t)(i >> 2)] + (i & 3))]]; },
-                  inc_start, inc_list);
-    parallel_for(4 * T, [&](int64_t a, int64_t b) {
-        for (int64_t i = a; i < b; ++i) inc_list[(size_t)i] >>= 2;
+    // the tets incident to each node, in increasing sorted position: each
+    // node's corners (input numbering, fixed with the connectivity: bucketed
+    // once) renumbered and sorted, nodes in parallel
+    if (m->inc_in_start.empty())
+        stable_bucket(4 * T, n, [&](int64_t i) { return m->tets[(size_t)i]; }, m->inc_in_start, m->inc_in_list);
+    std::vector<int32_t> inc_start((size_t)n + 1), inc_list((size_t)(4 * T));
+    inc_start[0] = 0;
+    for (int64_t r = 0; r < n; ++r) {
+        const int32_t i = orig[(size_t)r];
+        inc_start[(size_t)r + 1] = inc_start[(size_t)r] + (m->inc_in_start[(size_t)i + 1] - m->inc_in_start[(size_t)i]);
+    }
+    parallel_for(n, [&](int64_t a, int64_t b) {
+        for (int64_t r = a; r < b; ++r) {
+            const int32_t i = orig[(size_t)r], c0 = m->inc_in_start[(size_t)i], c1 = m->inc_in_start[(size_t)i + 1];
+            int32_t *o = &inc_list[(size_t)inc_start[(size_t)r]];
+            for (int32_t c = c0; c < c1; ++c) o[c - c0] = slot[(size_t)(m->inc_in_list[(size_t)c] >> 2)];
+            std::sort(o, o + (c1 - c0));
+        }
     });
     m->convex = T > 0 && boundary_convex(m);
 
@@ -1824,27 +1867,35 @@ int eval_device(bs_mesh *m, hipStream_t s, bool targets, const EvalBufs *given =
     lp.net = P.kind == BS_POLICY_LEARNED ? (const bsk::PackedNet *)m->mlp.p : nullptr;
     lp.conf_min = P.conf_min;
     lp.hbar = (float)m->hbar;
+    m->last_rt = 0;
     if (m->T > 0 && (fixed_like || P.kind == BS_POLICY_PURE_RT)) {
         const int all = P.kind == BS_POLICY_PURE_RT;
-        if (m->convex && m->rt_mode == 0 && !targets) {
+        m->last_rt = 1;
+        // the walk on face-manifold meshes; where the boundary is not
+        // convex it leaves every node with a ray that exits the mesh early
+        // to the candidate kernel (with every pair ray traced, rays run to
+        // the boundary: there every node goes to the candidate kernel)
+        if (m->manifold && (m->convex || !all) && m->rt_mode == 0 && !targets) {
+            m->last_rt = 2;
             if (!given && (rc = dalloc(m->fallback, 4 * ((size_t)m->n + 1)))) return rc;
             int *fb = given ? given->fallback : (int *)m->fallback.p;
             int *nfb = fb + m->n;
             const float r_stop = all ? 3.0e38f : (float)((std::max(c_rt, m->max_vc) + m->max_vc) * (1.0 + 1e-4) + 1e-6);
-            int *sel_list = nullptr, *sel_n = nullptr;
+            int *sel_list = nullptr, *sel_n = nullptr, *sel_cnt = nullptr;
             float *sel_dmax = nullptr;
             if (lp.net) {
                 const size_t nn = (size_t)m->n;
-                if (!given && (rc = dalloc(m->sel, 4 * (nn * bsk::kSelListCap + 2 * nn)))) return rc;
+                if (!given && (rc = dalloc(m->sel, 4 * (nn * bsk::kSelListCap + 5 * nn)))) return rc;
                 sel_list = given ? given->sel : (int *)m->sel.p;
                 sel_n = sel_list + nn * bsk::kSelListCap;
                 sel_dmax = (float *)(sel_n + nn);
+                sel_cnt = (int *)(sel_dmax + nn);
             }
             if ((e = given ? bsk::launch_fill_zero(nfb, 1, sr) : hipMemsetAsync(nfb, 0, 4, sr)) ||
-                (lp.net && (e = bsk::launch_select(dm, th, lp, P.precision, b_rtv, cnt, sel_list, sel_n,
-                                                   sel_dmax, sr))) ||
-                (e = bsk::launch_rt_walk(dm, th, ang, all, r_stop, P.precision, b_rtv, cnt, fb, nfb, sel_list, sel_n,
-                                         sel_dmax, sr)) ||
+                (lp.net && (e = bsk::launch_select(dm, th, lp, P.precision, b_rtv, sel_list, sel_n, sel_dmax,
+                                                   sel_cnt, sr))) ||
+                (e = bsk::launch_rt_walk(dm, th, ang, all, r_stop, m->convex ? 0 : 1, P.precision, b_rtv, cnt, fb,
+                                         nfb, sel_list, sel_n, sel_dmax, sel_cnt, sr)) ||
                 (e = bsk::launch_rt(dm, th, ang, lp, all, P.precision, b_rtv, cnt, fb, nfb, sr)))
                 return hip_fail(e, "ray-tracing walk");
         } else if ((e = bsk::launch_rt(dm, th, ang, lp, all, P.precision, b_rtv, cnt,
@@ -1854,6 +1905,7 @@ int eval_device(bs_mesh *m, hipStream_t s, bool targets, const EvalBufs *given =
         }
         rtv = b_rtv;
     }
+    if (given) m->last_rt = 0; // (no statistics are read after a call that allocates nothing)
     record(5, sr);
     if (!one_stream && ((e = hipStreamWaitEvent(s, m->ev[3], 0)) || (e = hipStreamWaitEvent(s, m->ev[5], 0))))
         return hip_fail(e, "join streams");
@@ -1876,7 +1928,7 @@ size_t eval_scratch_layout(const bs_mesh *m, size_t off[7])
     const size_t np = (size_t)m->npad, nn = (size_t)m->n;
     const size_t sz[7] = {8 * 3 * np * (size_t)far_splits(m), 8 * 3 * np, 8 * 3 * np, 8 * (size_t)bsk::kNumCounters, 4,
                           4 * (nn + 1),
-                          m->pol.kind == BS_POLICY_LEARNED ? 4 * (nn * bsk::kSelListCap + 2 * nn) : 0};
+                          m->pol.kind == BS_POLICY_LEARNED ? 4 * (nn * bsk::kSelListCap + 5 * nn) : 0};
     size_t o = 0;
     for (int k = 0; k < 7; ++k) {
         off[k] = o;
@@ -1922,6 +1974,16 @@ int read_stats(bs_mesh *m, bs_stats *st)
     st->reoriented = m->reoriented;
     st->nonfinite_out = nf;
     st->hbar = m->hbar;
+    const int64_t nt = m->last_targets ? m->tn : m->n;
+    if (m->last_rt == 2) {
+        int nfb = 0;
+        if ((e = hipMemcpy(&nfb, (const int *)m->fallback.p + m->n, 4, hipMemcpyDeviceToHost)))
+            return hip_fail(e, "read counters");
+        st->rt_candidate_nodes = nfb;
+        st->rt_walk_nodes = nt - nfb;
+    } else if (m->last_rt == 1) {
+        st->rt_candidate_nodes = nt;
+    }
     if (uses_treecode(P) && m->tree.valid) {
         st->tree_expansions = m->last_targets ? m->tree.exp_pts : m->tree.exp_nodes;
         st->tree_direct = m->last_targets ? m->tree.dir_pts : m->tree.dir_nodes;

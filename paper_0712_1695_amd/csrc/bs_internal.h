@@ -114,13 +114,17 @@ hipError_t launch_rt(const DevMesh &m, const Thresholds &th, const AngTab &ang, 
 // (sel_list[n][kSelListCap], sel_n[n] = count or -1: left to launch_rt).
 constexpr int kSelListCap = 128;
 hipError_t launch_select(const DevMesh &m, const Thresholds &th, const LearnParams &lp, int precision, double *rtv,
-                         unsigned long long *cnt, int *sel_list, int *sel_n, float *sel_dmax, hipStream_t s);
-// Walk variant (convex meshes); nodes it cannot hold are appended to
-// fallback[*n_fallback] for launch_rt in node-list mode.  With sel_n the
-// ray-traced tets come from launch_select and the walk adds to rtv.
+                         int *sel_list, int *sel_n, float *sel_dmax, int *sel_cnt, hipStream_t s);
+// Walk variant (face-manifold meshes); nodes it cannot hold are appended to
+// fallback[*n_fallback] for launch_rt in node-list mode: with exit_fb (a
+// boundary that is not convex) also every node with a ray that leaves the
+// mesh before its stop distance.  With sel_n the ray-traced tets come from
+// launch_select, the walk adds to rtv and, for the nodes it completes, adds
+// sel_cnt[3 node + k] (pairs moved to G1, G4, G11) to the counters.
 hipError_t launch_rt_walk(const DevMesh &m, const Thresholds &th, const AngTab &ang, int all_pairs, float r_stop,
-                          int precision, double *rtv, unsigned long long *cnt, int *fallback, int *n_fallback,
-                          const int *sel_list, const int *sel_n, const float *sel_dmax, hipStream_t s);
+                          int exit_fb, int precision, double *rtv, unsigned long long *cnt, int *fallback,
+                          int *n_fallback, const int *sel_list, const int *sel_n, const float *sel_dmax,
+                          const int *sel_cnt, hipStream_t s);
 // Nodal velocity gradient (grad[input node][3][3], FP64) of the linear
 // interpolant of vel ([input node][3]) on each tet, volume-weighted over the
 // node's tets; tg: scratch of 10 doubles per tet.

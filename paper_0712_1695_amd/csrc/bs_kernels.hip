@@ -1672,7 +1672,10 @@ __global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang,
 }
 
 // ---------------------------------------------------------------------------
-// Ray tracing by walking the mesh (for meshes whose boundary is convex).
+// Ray tracing by walking the mesh (face-manifold meshes: every interior
+// face shared by two tets).  Where the boundary is not convex a ray that
+// leaves the mesh may enter it again, so a node with a ray that leaves
+// before its stop distance (or starts outside) is left to k_rt.
 // One wave per node; lane = ray.  Every ray leaves the node through the one
 // incident tet whose opposite face it crosses, then crosses face neighbours
 // outward: the exit face of one tet is the entry face of the next, decided
@@ -1774,9 +1777,11 @@ __device__ __forceinline__ void walk_reach_add(int &n, bool take, const float4 &
 // ones 64 at a time, adds the Gauss terms of the pairs it moves to rtv, and
 // leaves the pairs still ray traced (incident ones included) in
 // sel_list[node][kSelCap] with their count and farthest centroid distance
-// for k_rt_walk.  A node with more than kSelCap such pairs, or without
-// incident tets the walk can start from, is marked with count -1 and left
-// to k_rt (nothing is written for it here).
+// for k_rt_walk, and the node's counts of pairs moved to each Gauss rule
+// (added to the counters by the walk once it completes the node: a node the
+// walk leaves to k_rt is counted there).  A node with more than kSelCap
+// such pairs, or without incident tets the walk can start from, is marked
+// with count -1 and left to k_rt (nothing is written for it here).
 constexpr int kSelCap = kSelListCap;
 
 __device__ __forceinline__ void sel_add(const DevMesh &m, int *list, int &n, bool take, int t, int lane,
@@ -1795,8 +1800,8 @@ __device__ __forceinline__ void sel_add(const DevMesh &m, int *list, int &n, boo
 
 template <int PREC>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_select(DevMesh m, Thresholds th, LearnParams lp, double *__restrict__ rtv,
-                                               unsigned long long *__restrict__ cnt, int *__restrict__ sel_list,
-                                               int *__restrict__ sel_n, float *__restrict__ sel_dmax)
+                                               int *__restrict__ sel_list, int *__restrict__ sel_n,
+                                               float *__restrict__ sel_dmax, int *__restrict__ sel_cnt)
 {
     __shared__ InferLds L;
     __shared__ int cand[128];
@@ -1883,8 +1888,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
         rtv[2 * m.npad + self] = vz;
         sel_n[self] = nlist;
         sel_dmax[self] = dmax;
-        if (cnt)
-            for (int k = 0; k < 3; ++k) atomicAdd(&cnt[5 + k], lr[k]);
+        for (int k = 0; k < 3; ++k) sel_cnt[3 * (size_t)self + k] = (int)lr[k];
     }
 }
 
@@ -1892,10 +1896,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
 // wrote the node's Gauss terms to rtv: the walk adds to them).
 template <int PREC, bool LISTED>
 __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab ang, int all_pairs, float r_stop,
-                                                double *__restrict__ rtv, unsigned long long *__restrict__ cnt,
-                                                int *__restrict__ fallback, int *__restrict__ n_fallback,
-                                                const int *__restrict__ sel_list, const int *__restrict__ sel_n,
-                                                const float *__restrict__ sel_dmax)
+                                                int exit_fb, double *__restrict__ rtv,
+                                                unsigned long long *__restrict__ cnt, int *__restrict__ fallback,
+                                                int *__restrict__ n_fallback, const int *__restrict__ sel_list,
+                                                const int *__restrict__ sel_n, const float *__restrict__ sel_dmax,
+                                                const int *__restrict__ sel_cnt)
 {
     __shared__ typename std::conditional<LISTED, WalkLdsListed, WalkLds>::type W;
     const int lane = threadIdx.x;
@@ -2079,7 +2084,16 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
     // ---- C. rays, 8 x 8 blocks of (row, column) per step so that the rays
     // of the wave point into a small solid angle
     const int bcols = (ang.M2 + 7) >> 3, nblk = ((ang.N + 7) >> 3) * bcols;
+    // exit_fb (a mesh whose boundary is not convex): a ray that leaves the
+    // mesh before its stop distance (or never enters it) could enter it again
+    // beyond; the node is then left to the candidate kernel, which finds
+    // every tet a ray meets
+    bool early = false;
     for (int bi = 0; bi < nblk; ++bi) {
+        if (exit_fb && __ballot(early)) {
+            if (lane == 0) fallback[atomicAdd(n_fallback, 1)] = self;
+            return;
+        }
         const int row = 8 * (bi / bcols) + (lane >> 3), col = 8 * (bi % bcols) + (lane & 7);
         const bool valid = row < ang.N && col < ang.M2;
         const int l = valid ? row * ang.M2 + col : 0;
@@ -2134,7 +2148,11 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
             cf[2] = E3;
             sg = se[0];
         }
-        if (!valid || start < 0) continue;
+        if (!valid) continue;
+        if (start < 0) {
+            early = true;
+            continue;
+        }
         {
             const float h = 0.5f * d.w * rho;
             const float sx = omx[0] + w_in[0], sy = omx[1] + w_in[1], sz = omx[2] + w_in[2];
@@ -2266,6 +2284,11 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
             }
         }
         if (PREC == 1) acc_add<1>(A, ray[0], ray[1], ray[2]);
+        early = early || (T < 0 && rho < stop_r);
+    }
+    if (exit_fb && __ballot(early)) {
+        if (lane == 0) fallback[atomicAdd(n_fallback, 1)] = self;
+        return;
     }
     A.pairs = all_pairs ? (unsigned long long)m.T : (unsigned long long)nlist;
 
@@ -2301,6 +2324,8 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
             atomicAdd(&cnt[2], A.pairs);
             atomicAdd(&cnt[3], hits);
             atomicAdd(&cnt[4], rts);
+            if (LISTED)
+                for (int k = 0; k < 3; ++k) atomicAdd(&cnt[5 + k], (unsigned long long)sel_cnt[3 * (size_t)self + k]);
         }
     }
 }
@@ -2327,27 +2352,28 @@ hipError_t launch_rt(const DevMesh &m, const Thresholds &th, const AngTab &ang, 
 }
 
 hipError_t launch_select(const DevMesh &m, const Thresholds &th, const LearnParams &lp, int precision, double *rtv,
-                         unsigned long long *cnt, int *sel_list, int *sel_n, float *sel_dmax, hipStream_t s)
+                         int *sel_list, int *sel_n, float *sel_dmax, int *sel_cnt, hipStream_t s)
 {
     if (m.n == 0) return hipSuccess;
     if (precision == 0)
-        hipLaunchKernelGGL(k_select<0>, dim3(m.n), dim3(64), 0, s, m, th, lp, rtv, cnt, sel_list, sel_n, sel_dmax);
+        hipLaunchKernelGGL(k_select<0>, dim3(m.n), dim3(64), 0, s, m, th, lp, rtv, sel_list, sel_n, sel_dmax, sel_cnt);
     else if (precision == 1)
-        hipLaunchKernelGGL(k_select<1>, dim3(m.n), dim3(64), 0, s, m, th, lp, rtv, cnt, sel_list, sel_n, sel_dmax);
+        hipLaunchKernelGGL(k_select<1>, dim3(m.n), dim3(64), 0, s, m, th, lp, rtv, sel_list, sel_n, sel_dmax, sel_cnt);
     else
-        hipLaunchKernelGGL(k_select<2>, dim3(m.n), dim3(64), 0, s, m, th, lp, rtv, cnt, sel_list, sel_n, sel_dmax);
+        hipLaunchKernelGGL(k_select<2>, dim3(m.n), dim3(64), 0, s, m, th, lp, rtv, sel_list, sel_n, sel_dmax, sel_cnt);
     return hipGetLastError();
 }
 
 hipError_t launch_rt_walk(const DevMesh &m, const Thresholds &th, const AngTab &ang, int all_pairs, float r_stop,
-                          int precision, double *rtv, unsigned long long *cnt, int *fallback, int *n_fallback,
-                          const int *sel_list, const int *sel_n, const float *sel_dmax, hipStream_t s)
+                          int exit_fb, int precision, double *rtv, unsigned long long *cnt, int *fallback,
+                          int *n_fallback, const int *sel_list, const int *sel_n, const float *sel_dmax,
+                          const int *sel_cnt, hipStream_t s)
 {
     if (m.n == 0) return hipSuccess;
     const bool L = sel_n != nullptr;
 #define BS_RW(P, LL)                                                                                               \
-    hipLaunchKernelGGL((k_rt_walk<P, LL>), dim3(m.n), dim3(64), 0, s, m, th, ang, all_pairs, r_stop, rtv, cnt,     \
-                       fallback, n_fallback, sel_list, sel_n, sel_dmax)
+    hipLaunchKernelGGL((k_rt_walk<P, LL>), dim3(m.n), dim3(64), 0, s, m, th, ang, all_pairs, r_stop, exit_fb, rtv, \
+                       cnt, fallback, n_fallback, sel_list, sel_n, sel_dmax, sel_cnt)
     if (precision == 0) {
         if (L) BS_RW(0, true); else BS_RW(0, false);
     } else if (precision == 1) {

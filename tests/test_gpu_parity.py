@@ -355,17 +355,45 @@ def test_lagrangian_reports_inversion():
 
 
 def test_walk_and_candidate_kernels_agree():
-    """Ray tracing by walking face neighbours (convex meshes) and by testing
-    candidate rays per pair compute the same chords; both match the oracle.
-    A non-convex mesh (ball-clipped) takes the candidate kernel."""
+    """Ray tracing by walking face neighbours and by testing candidate rays
+    per pair compute the same chords; both match the oracle.  On the convex
+    cube every node walks; on the ball clipped from Kuhn cells (a staircase
+    boundary) the nodes whose rays leave the mesh before their last
+    ray-traced tet take the candidate kernel."""
     m = W.make_config("C1")
     ref = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("pure_rt"))
     v, st = gpu_eval(m, kind=bs.BS_POLICY_PURE_RT)
     check(v, ref, "walk")
-    b = W.ball_mesh(cells=8)
+    assert st["rt_walk_nodes"] == m.n_nodes and st["rt_candidate_nodes"] == 0
+    b = W.ball_mesh(cells=12)
     b.omega = W.field_gaussian_swirl(b.xyz)
-    vb, _ = gpu_eval(b)
-    check(vb, oracle.evaluate(b.xyz, b.omega, b.tets), "candidate kernel on the ball")
+    vb, stb = gpu_eval(b)
+    _say(f"  ball: {stb['rt_walk_nodes']} nodes walked, {stb['rt_candidate_nodes']} by candidate rays")
+    check(vb, oracle.evaluate(b.xyz, b.omega, b.tets), "walk and candidate kernel on the ball")
+    assert stb["rt_walk_nodes"] > 0 and stb["rt_candidate_nodes"] > 0
+    assert stb["rt_walk_nodes"] + stb["rt_candidate_nodes"] == b.xyz.shape[0]
+
+
+def test_walk_where_the_boundary_is_not_convex():
+    """The cube with its boundary nodes displaced by up to 0.05 h (as a
+    Lagrangian step leaves it: no longer convex).  Fixed rule: interior
+    nodes walk, nodes with a ray that exits before its last ray-traced tet
+    take candidate rays; pure ray tracing (rays to the boundary): every node
+    takes candidate rays.  Both against the oracle."""
+    m = W.make_config("C1")
+    rng = np.random.default_rng(31)
+    xyz = m.xyz.copy()
+    nb = int(m.boundary.sum())
+    xyz[m.boundary] += rng.uniform(-0.05, 0.05, size=(nb, 3)) * m.h
+    arrays = (xyz, m.omega, m.tets)
+    v, st = gpu_eval(arrays)
+    _say(f"  displaced boundary: {st['rt_walk_nodes']} nodes walked, {st['rt_candidate_nodes']} by candidate rays")
+    check(v, oracle.evaluate(xyz, m.omega, m.tets), "fixed rule, displaced boundary")
+    assert st["rt_walk_nodes"] > 0 and st["rt_candidate_nodes"] >= nb
+    vp, stp = gpu_eval(arrays, kind=bs.BS_POLICY_PURE_RT, n_phi=8, n_theta=8)
+    check(vp, oracle.evaluate(xyz, m.omega, m.tets, oracle.make_policy("pure_rt", n_phi=8, n_theta=8)),
+          "pure ray tracing, displaced boundary")
+    assert stp["rt_walk_nodes"] == 0 and stp["rt_candidate_nodes"] == m.n_nodes
 
 
 def test_concurrent_and_serial_streams_agree():

@@ -74,9 +74,10 @@ def gpu_learned(bs, m, bits, conf_min):
 
 
 def _ball():
-    """A non-convex mesh (the cube's cells clipped to a ball): no walk, the
-    candidate kernel with the selector inside it takes every node."""
-    b = W.ball_mesh(cells=8)
+    """A non-convex mesh (the cube's cells clipped to a ball): the selection
+    pass and the walk take the nodes whose rays stay inside the mesh, the
+    candidate kernel with the selector inside it the rest."""
+    b = W.ball_mesh(cells=12)
     b.omega = W.field_gaussian_swirl(b.xyz)
     return b
 
@@ -105,6 +106,9 @@ def test_learned_policy_matches_oracle(bs, selector, name):
     # the selector moved most ray-traced pairs
     assert counts[3] < 0.5 * np.count_nonzero(fixed_rules == 3)
     assert len(aK) <= 0.01 * max(1, counts[:3].sum() - np.count_nonzero(fixed_rules < 3))
+    if name == "ball":
+        print(f"ball: {st['rt_walk_nodes']} nodes walked, {st['rt_candidate_nodes']} by candidate rays", flush=True)
+        assert st["rt_walk_nodes"] > 0 and st["rt_candidate_nodes"] > 0
     if not sampled:
         # rule counts agree up to the ambiguous pairs
         diff = np.abs(np.array(st["pairs_by_rule"]) - counts)

@@ -75,7 +75,7 @@ def test_noalloc_matches_eval_velocity_two_calls(bs):
 
 def test_noalloc_refuses_meshes_beyond_the_scratch(bs):
     """A host output, and the learned policy on the ring workload (97,175
-    nodes: 24 bytes x 8 splits + 48 per node slot and 520 per node, 74 MB),
+    nodes: 24 bytes x 8 splits + 48 per node slot and 532 per node, 75 MB),
     are refused before any kernel runs."""
     import torch
 
