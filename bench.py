@@ -30,7 +30,10 @@ Besides the headline, the same JSON line carries:
               (117,649 x 663,552; held out): fixed, learned and learned with
               the treecode far field, timings and errors;
   lagrangian  Heun steps of the two-ring run with the learned policy
-              (bs_advect_heun: mesh rebuild, two evaluations per step);
+              (bs_advect_heun: mesh rebuild, two evaluations per step), and
+              step 1 against the FP64 oracle's Heun step at sampled nodes
+              (tests/golden/c5_heun_step1.json, an oracle-only script's
+              output), with the fixed rule and with the learned policy;
   roofline    the longest kernel of the headline step alone (HIP events on
               its launch stream in a pass with every kernel on one stream),
               "roofline_kernels" lists far field, band and ray tracing;
@@ -261,6 +264,27 @@ def walk_executed(st, t):
                              "is left out"}
 
 
+def load_heun_reference(workload):
+    """The FP64 oracle's Heun step 1 of the workload at sampled nodes, if one
+    is stored (written by tests/golden/make_c5_heun_reference.py)."""
+    path = os.path.join(ROOT, "tests", "golden", "c5_heun_step1.json")
+    if workload != "C5" or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        ref = json.load(f)
+    ref["nodes"] = np.asarray(ref["nodes"], dtype=np.int64)
+    ref["x1"] = np.asarray(ref["x1"])
+    return ref
+
+
+def heun_drift(pos, ref, mesh):
+    """Largest position error at the reference's nodes after one step."""
+    nodes = ref["nodes"]
+    err = float(np.abs(pos[nodes] - ref["x1"]).max())
+    step = float(np.abs(ref["x1"] - mesh.xyz[nodes]).max())
+    return {"max_abs": err, "max_rel_to_step": err / step}
+
+
 def tree_roofline(st, kern, order, workload, policy, precision):
     """The treecode far field (moments, expansions and direct leaves
     together, one duration): 26 flops per 1-point pair of the direct leaves,
@@ -464,14 +488,36 @@ def main():
 
         # ---- the Lagrangian run (moves this mesh: last on it)
         if args.heun_steps > 0:
+            drift = None
+            ref = load_heun_reference(args.workload)
+            if ref is not None:
+                # step 1 with the fixed rule against the FP64 oracle's own
+                # step, then back to the initial positions
+                B.set_policy(**fixed_pol)
+                pos, _ = bs.bs_advect_heun(B.h, ref["dt"], 1)
+                drift = {"fixed": heun_drift(pos, ref, mesh)}
+                bs.bs_mesh_update(B.h, xyz=mesh.xyz)
             B.set_policy(**head_pol)
-            _, secs = bs.bs_advect_heun(B.h, 0.005, args.heun_steps)
+            pos, secs1 = bs.bs_advect_heun(B.h, 0.005, 1)
+            if ref is not None:
+                drift[args.policy + "_policy"] = heun_drift(pos, ref, mesh)
+            secs = list(secs1)
+            if args.heun_steps > 1:
+                secs += list(bs.bs_advect_heun(B.h, 0.005, args.heun_steps - 1)[1])
             line["lagrangian"] = {"steps": args.heun_steps, "dt": 0.005, "policy": args.policy,
                                   "seconds_per_step": [float(s) for s in secs],
                                   "median_s_per_step": float(np.median(secs)),
                                   "evaluations_per_step": 2,
                                   "what": "bs_advect_heun: per step two device-mesh rebuilds on the host and two "
                                           "evaluations, connectivity and nodal vorticity kept"}
+            if drift is not None:
+                drift["what"] = ("positions after step 1 at %d sampled nodes against the same Heun step taken by "
+                                 "the FP64 oracle with the fixed rule (tests/golden/c5_heun_step1.json): largest "
+                                 "error, absolute and over the largest displacement of the step; the learned "
+                                 "policy's figure also holds the rule changes the selector makes" % len(ref["nodes"]))
+                line["lagrangian"]["step1_vs_oracle"] = drift
+                print(f"bench: Heun step 1 against the oracle: fixed {drift['fixed']['max_rel_to_step']:.3e}, "
+                      f"{args.policy} {drift[args.policy + '_policy']['max_rel_to_step']:.3e} of the step", flush=True)
             print(f"bench: Heun {np.median(secs):.3f} s per step", flush=True)
             if args.policy == "learned" and args.far == "all_pairs":
                 # three more steps from there with the treecode far field
