@@ -1284,7 +1284,7 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
         (rc = dalloc(m->g11, 4 * (size_t)T * 88)) || (rc = dalloc(m->tid, sizeof(int4) * (size_t)T)) ||
         (rc = dalloc(m->cell_start, 4 * cell_start.size())) || (rc = dalloc(m->band, 8 * 3 * (size_t)npad)) ||
         (rc = dalloc(m->rtv, 8 * 3 * (size_t)npad)) || (rc = dalloc(m->vel, 8 * 3 * (size_t)n)) ||
-        (rc = dalloc(m->cnt, 8 * bsk::kNumCounters)) || (rc = dalloc(m->nonfinite, 4)) ||
+        (rc = dalloc(m->cnt, 8 * bsk::kCntWords)) || (rc = dalloc(m->nonfinite, 4)) ||
         (rc = dalloc(m->nbr, sizeof(int4) * (size_t)T)) ||
         (rc = dalloc(m->tsph, sizeof(float4) * tsph.size())) || (rc = dalloc(m->inc_start, 4 * inc_start.size())) ||
         (rc = dalloc(m->inc_list, 4 * inc_list.size())) || (rc = dalloc(m->om64, 8 * 3 * (size_t)std::max<int64_t>(n, 1))))
@@ -1805,10 +1805,10 @@ int eval_device(bs_mesh *m, hipStream_t s, bool targets, const EvalBufs *given =
 
     hipError_t e;
     if (given) {
-        if ((e = bsk::launch_fill_zero(cnt, 2 * bsk::kNumCounters, s)) ||
+        if ((e = bsk::launch_fill_zero(cnt, 2 * bsk::kCntWords, s)) ||
             (e = bsk::launch_fill_zero(b_nonfinite, 1, s)))
             return hip_fail(e, "clear counters");
-    } else if ((e = hipMemsetAsync(cnt, 0, 8 * bsk::kNumCounters, s)) || (e = hipMemsetAsync(b_nonfinite, 0, 4, s))) {
+    } else if ((e = hipMemsetAsync(cnt, 0, 8 * bsk::kCntWords, s)) || (e = hipMemsetAsync(b_nonfinite, 0, 4, s))) {
         return hip_fail(e, "clear counters");
     }
     const double *part = nullptr, *band = nullptr, *rtv = nullptr;
@@ -1926,7 +1926,7 @@ size_t eval_scratch_layout(const bs_mesh *m, size_t off[7])
 {
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
     const size_t np = (size_t)m->npad, nn = (size_t)m->n;
-    const size_t sz[7] = {8 * 3 * np * (size_t)far_splits(m), 8 * 3 * np, 8 * 3 * np, 8 * (size_t)bsk::kNumCounters, 4,
+    const size_t sz[7] = {8 * 3 * np * (size_t)far_splits(m), 8 * 3 * np, 8 * 3 * np, 8 * (size_t)bsk::kCntWords, 4,
                           4 * (nn + 1),
                           m->pol.kind == BS_POLICY_LEARNED ? 4 * (nn * bsk::kSelListCap + 5 * nn) : 0};
     size_t o = 0;
@@ -1939,12 +1939,15 @@ size_t eval_scratch_layout(const bs_mesh *m, size_t off[7])
 
 int read_stats(bs_mesh *m, bs_stats *st)
 {
-    unsigned long long c[bsk::kNumCounters];
+    std::vector<unsigned long long> cc((size_t)bsk::kCntWords);
     int nf = 0;
     hipError_t e;
-    if ((e = hipMemcpy(c, m->cnt.p, sizeof c, hipMemcpyDeviceToHost)) ||
+    if ((e = hipMemcpy(cc.data(), m->cnt.p, 8 * cc.size(), hipMemcpyDeviceToHost)) ||
         (e = hipMemcpy(&nf, m->nonfinite.p, 4, hipMemcpyDeviceToHost)))
         return hip_fail(e, "read counters");
+    unsigned long long c[bsk::kNumCounters] = {};
+    for (int k = 0; k < bsk::kCntStripes; ++k)
+        for (int j = 0; j < bsk::kNumCounters; ++j) c[j] += cc[(size_t)(k * bsk::kCntStride + j)];
     const bs_policy &P = m->pol;
     std::memset(st, 0, sizeof *st);
     float ms = 0.f;

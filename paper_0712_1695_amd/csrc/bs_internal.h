@@ -94,8 +94,15 @@ struct DevMesh {
 
 // Counters accumulated by the kernels (device, 64-bit):
 // [0] G4 pairs, [1] G11 pairs, [2] RT pairs, [3] RT hit lines, [4] FP64 retests,
-// [5..7] pairs the learned selector moved from RT to G1 / G4 / G11
+// [5..7] pairs the learned selector moved from RT to G1 / G4 / G11.
+// Kept in kCntStripes copies, one 128-byte cache line each, a node or block
+// adding to copy (its index mod kCntStripes): atomics of every node on one
+// line serialise in the L2 and bound the per-node kernels.  The host sums
+// the copies.
 constexpr int kNumCounters = 8;
+constexpr int kCntStripes = 64;
+constexpr int kCntStride = 16; // 64-bit counters per copy (128 bytes)
+constexpr int kCntWords = kCntStripes * kCntStride;
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_gauss_all(const DevMesh &m, int rule_pts, int precision, int splits, double *part,

@@ -63,6 +63,12 @@ __device__ __forceinline__ void two_sum(float &s, float &c, float a)
 // Rule of the pair (node `self` at (x, y, z), tetrahedron with centroid c
 // and vertex ids id) under the fixed distance policy.  Every operation is
 // rounded separately (the file is built without FP contraction).
+// The copy of the counters a node or block adds to.
+__device__ __forceinline__ unsigned long long *cnt_copy(unsigned long long *cnt, int key)
+{
+    return cnt + kCntStride * (key & (kCntStripes - 1));
+}
+
 __device__ __forceinline__ int fixed_rule(float x, float y, float z, float cx, float cy, float cz, int4 id,
                                           int self, const Thresholds &th)
 {
@@ -782,8 +788,9 @@ __global__ void __launch_bounds__(64 * kBandWaves) k_band(DevMesh m, Thresholds 
     n4 = wave_sum_u64(n4);
     n11 = wave_sum_u64(n11);
     if (lane == 0 && cnt) {
-        atomicAdd(&cnt[0], n4);
-        atomicAdd(&cnt[1], n11);
+        unsigned long long *c = cnt_copy(cnt, blockIdx.x);
+        atomicAdd(&c[0], n4);
+        atomicAdd(&c[1], n11);
     }
     __syncthreads();
     if (wave == 0) {
@@ -954,8 +961,9 @@ __global__ void __launch_bounds__(64 * kBandWaves) k_band_piece(DevMesh m, Thres
     n4 = wave_sum_u64(n4);
     n11 = wave_sum_u64(n11);
     if (lane == 0 && cnt) {
-        atomicAdd(&cnt[0], n4);
-        atomicAdd(&cnt[1], n11);
+        unsigned long long *c = cnt_copy(cnt, blockIdx.x);
+        atomicAdd(&c[0], n4);
+        atomicAdd(&c[1], n11);
     }
     __syncthreads();
     if (wave == 0) {
@@ -1660,11 +1668,12 @@ __global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang,
             rtv[m.npad + self] = vy;
             rtv[2 * m.npad + self] = vz;
             if (cnt) {
-                atomicAdd(&cnt[2], A.pairs);
-                atomicAdd(&cnt[3], hits);
-                atomicAdd(&cnt[4], rts);
+                unsigned long long *c = cnt_copy(cnt, self);
+                atomicAdd(&c[2], A.pairs);
+                atomicAdd(&c[3], hits);
+                atomicAdd(&c[4], rts);
                 if (LEARNED)
-                    for (int k = 0; k < 3; ++k) atomicAdd(&cnt[5 + k], lr[k]);
+                    for (int k = 0; k < 3; ++k) atomicAdd(&c[5 + k], lr[k]);
             }
         }
         __syncthreads(); // the next node reuses the shared arrays
@@ -2321,11 +2330,12 @@ __global__ void __launch_bounds__(64) k_rt_walk(DevMesh m, Thresholds th, AngTab
         rtv[m.npad + self] = vy;
         rtv[2 * m.npad + self] = vz;
         if (cnt) {
-            atomicAdd(&cnt[2], A.pairs);
-            atomicAdd(&cnt[3], hits);
-            atomicAdd(&cnt[4], rts);
+            unsigned long long *c = cnt_copy(cnt, self);
+            atomicAdd(&c[2], A.pairs);
+            atomicAdd(&c[3], hits);
+            atomicAdd(&c[4], rts);
             if (LISTED)
-                for (int k = 0; k < 3; ++k) atomicAdd(&cnt[5 + k], (unsigned long long)sel_cnt[3 * (size_t)self + k]);
+                for (int k = 0; k < 3; ++k) atomicAdd(&c[5 + k], (unsigned long long)sel_cnt[3 * (size_t)self + k]);
         }
     }
 }
