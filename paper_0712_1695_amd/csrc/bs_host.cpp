@@ -1209,6 +1209,26 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
                                        rank[(size_t)id[3]]);
         }
     });
+    // the records (most of the bytes uploaded) go to the device now, from
+    // pinned memory, while the host builds the rest; every later return
+    // first waits for these copies (the staging is rewritten by the next
+    // build)
+    if ((rc = dalloc(m->g1, 4 * (size_t)T * 8)) || (rc = dalloc(m->g4, 4 * (size_t)T * 32)) ||
+        (rc = dalloc(m->g11, 4 * (size_t)T * 88)))
+        return rc;
+    {
+        hipError_t e;
+        if (T > 0 && ((e = hipMemcpyAsync(m->g1.p, g1, 4 * (size_t)T * 8, hipMemcpyHostToDevice, s)) ||
+                      (e = hipMemcpyAsync(m->g4.p, g4, 4 * (size_t)T * 32, hipMemcpyHostToDevice, s)) ||
+                      (e = hipMemcpyAsync(m->g11.p, g11, 4 * (size_t)T * 88, hipMemcpyHostToDevice, s)))) {
+            (void)hipStreamSynchronize(s);
+            return hip_fail(e, "upload Gauss records");
+        }
+    }
+    auto wait_records = [&](int r) {
+        (void)hipStreamSynchronize(s);
+        return r;
+    };
 
     // ---- bounding sphere of the binary32 centroids of every tile of 16
     // consecutive (sorted) tets, for the far kernel's band flags
@@ -1279,22 +1299,20 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
         (rc = dalloc(m->nrec, sizeof(float4) * nrec.size())) ||
         (rc = dalloc(m->blk, sizeof(float4) * blk.size())) || (rc = dalloc(m->node_orig, 4 * (size_t)n)) ||
         (rc = dalloc(m->torig, 4 * torig.size())) || (rc = dalloc(m->tlist, 4 * tlist.size())) ||
-        (rc = dalloc(m->tvel, 8 * 3 * (size_t)tn)) ||
-        (rc = dalloc(m->g1, 4 * (size_t)T * 8)) || (rc = dalloc(m->g4, 4 * (size_t)T * 32)) ||
-        (rc = dalloc(m->g11, 4 * (size_t)T * 88)) || (rc = dalloc(m->tid, sizeof(int4) * (size_t)T)) ||
+        (rc = dalloc(m->tvel, 8 * 3 * (size_t)tn)) || (rc = dalloc(m->tid, sizeof(int4) * (size_t)T)) ||
         (rc = dalloc(m->cell_start, 4 * cell_start.size())) || (rc = dalloc(m->band, 8 * 3 * (size_t)npad)) ||
         (rc = dalloc(m->rtv, 8 * 3 * (size_t)npad)) || (rc = dalloc(m->vel, 8 * 3 * (size_t)n)) ||
         (rc = dalloc(m->cnt, 8 * bsk::kCntWords)) || (rc = dalloc(m->nonfinite, 4)) ||
         (rc = dalloc(m->nbr, sizeof(int4) * (size_t)T)) ||
         (rc = dalloc(m->tsph, sizeof(float4) * tsph.size())) || (rc = dalloc(m->inc_start, 4 * inc_start.size())) ||
         (rc = dalloc(m->inc_list, 4 * inc_list.size())) || (rc = dalloc(m->om64, 8 * 3 * (size_t)std::max<int64_t>(n, 1))))
-        return rc;
+        return wait_records(rc);
     hipError_t e;
 #define BS_UP(buf, vec)                                                                                            \
     if (!(vec).empty() &&                                                                                          \
         (e = hipMemcpyAsync(m->buf.p, (vec).data(), sizeof((vec)[0]) * (vec).size(), hipMemcpyHostToDevice, s)) != \
             hipSuccess)                                                                                            \
-        return hip_fail(e, "upload " #buf);
+        return wait_records(hip_fail(e, "upload " #buf));
     BS_UP(xh, xh)
     BS_UP(xl, xl)
     BS_UP(om, om)
@@ -1303,10 +1321,6 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
     BS_UP(node_orig, orig)
     BS_UP(torig, torig)
     BS_UP(tlist, tlist)
-    if (T > 0 && ((e = hipMemcpyAsync(m->g1.p, g1, 4 * (size_t)T * 8, hipMemcpyHostToDevice, s)) ||
-                  (e = hipMemcpyAsync(m->g4.p, g4, 4 * (size_t)T * 32, hipMemcpyHostToDevice, s)) ||
-                  (e = hipMemcpyAsync(m->g11.p, g11, 4 * (size_t)T * 88, hipMemcpyHostToDevice, s))))
-        return hip_fail(e, "upload Gauss records");
     BS_UP(tid, tid)
     BS_UP(cell_start, cell_start)
     BS_UP(nbr, nbr)
