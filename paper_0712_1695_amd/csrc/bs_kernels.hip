@@ -1549,9 +1549,11 @@ __device__ __forceinline__ void list_shift(int *list, int &n, int used, int lane
     n = rest;
 }
 
-// workgroups of k_rt over a node list: enough to fill the chip, few enough
-// that an empty list costs nothing beside the kernels that run concurrently
-constexpr int kRtListGrid = 2048;
+// workgroups of k_rt over a node list: two rounds of the chip's wave slots
+// at this kernel's four waves per SIMD (the walk's fallback on a moved
+// mesh is about 30% of the nodes), few enough that an empty list costs
+// nothing beside the kernels that run concurrently
+constexpr int kRtListGrid = 8192;
 
 template <int PREC, bool LEARNED>
 __global__ void __launch_bounds__(64) k_rt(DevMesh m, Thresholds th, AngTab ang, LearnParams lp, int all_pairs,
