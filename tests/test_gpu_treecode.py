@@ -9,7 +9,8 @@ differ by binary32 rounding only.  The interaction counts the library
 reports must equal the reference's exactly, so both took the same
 acceptance decisions on every (block, cluster).  At the two-ring size the
 library's treecode is compared with its own all-pairs sum within the
-truncation bound, per node.
+truncation bound, per node; at theta 0.2, order 6 with the all-pairs FP64
+oracle itself, at the full ring and two-ring sizes, within the same 1e-6.
 """
 import numpy as np
 import pytest
@@ -312,3 +313,25 @@ def test_treecode_degenerate_meshes():
             assert np.all(vt == 0.0) and np.all(va == 0.0)
         else:
             assert np.abs(vt - va).max() <= 1e-5 * scale
+
+
+@pytest.mark.parametrize("name", ["C2", "C5"])
+def test_treecode_equals_all_pairs_at_tight_settings(name):
+    """At theta 0.2, order 6 the treecode's expansions are exact to FP32
+    rounding on the full ring and two-ring workloads: its velocities match
+    the all-pairs FP64 oracle (the method without a treecode) at 256 seeded
+    nodes within the library's 1e-6 parity bound, as the all-pairs GPU
+    evaluation does."""
+    m = W.make_config(name)
+    rng = np.random.default_rng(17)
+    tg = np.unique(np.concatenate([[0, m.n_nodes - 1], rng.choice(m.n_nodes, size=254, replace=False)]))
+    h = bs.bs_mesh_upload(m.xyz, m.omega, m.tets)
+    try:
+        bs.bs_set_policy(h, far_field="treecode", tree_theta=0.2, tree_order=6)
+        v, st = bs.bs_eval_velocity(h, stats=True)
+    finally:
+        bs.bs_mesh_free(h)
+    _say(f"{name}: treecode 0.2/6, expansion terms {st['tree_expansions']:.3e}, direct pairs {st['tree_direct']:.3e}")
+    assert st["tree_expansions"] > 0
+    ref = oracle.evaluate(m.xyz, m.omega, m.tets, oracle.make_policy("fixed"), targets=tg)
+    check(v[tg], ref, f"{name} treecode 0.2/6 against the all-pairs oracle, {len(tg)} nodes")
