@@ -73,6 +73,26 @@ def test_noalloc_matches_eval_velocity_two_calls(bs):
             _check(v, ref, f"{label}, C1 at {cells} ({m.n_nodes} nodes)")
 
 
+def test_noalloc_where_the_boundary_is_not_convex(bs):
+    """Meshes whose boundary is not convex (the ball clipped from Kuhn
+    cells; the cube with displaced boundary nodes): the walk leaves nodes to
+    the candidate kernel through the node list in the static scratch, and
+    the learned policy's selection lists live there too."""
+    blob = json.load(open(os.path.join(HERE, "golden", "selector_blob.json")))
+    bits = np.array(blob["blob_bf16_bits"], dtype=np.uint16)
+    learned = dict(kind=bs.BS_POLICY_LEARNED, mlp_bf16=bits, conf_min=float(blob["conf_min"]))
+    ball = W.ball_mesh(cells=12)
+    ball.omega = W.field_gaussian_swirl(ball.xyz)
+    cube = W.make_config("C1", scale=(8, 8, 8))
+    rng = np.random.default_rng(31)
+    cube.xyz = cube.xyz.copy()
+    cube.xyz[cube.boundary] += rng.uniform(-0.05, 0.05, size=(int(cube.boundary.sum()), 3)) * cube.h
+    for label, pol in (("fixed", dict(kind=bs.BS_POLICY_FIXED)), ("learned", learned)):
+        for name, m in (("ball", ball), ("displaced cube", cube)):  # second call smaller
+            v, ref = _both(bs, m, pol)
+            _check(v, ref, f"{label}, {name} ({m.xyz.shape[0]} nodes)")
+
+
 def test_noalloc_refuses_meshes_beyond_the_scratch(bs):
     """A host output, and the learned policy on the ring workload (97,175
     nodes: 24 bytes x 8 splits + 48 per node slot and 532 per node, 75 MB),
