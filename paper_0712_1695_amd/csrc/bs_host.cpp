@@ -1011,13 +1011,34 @@ bsk::TreeView tree_view(bs_mesh *m)
     return t;
 }
 
+// A thread joined when the object goes out of scope (every return path).
+struct JoinedThread {
+    std::thread t;
+    template <class F>
+    explicit JoinedThread(F &&f) : t(std::forward<F>(f))
+    {
+    }
+    void join()
+    {
+        if (t.joinable()) t.join();
+    }
+    ~JoinedThread() { join(); }
+};
+
 int build_device_mesh(bs_mesh *m, hipStream_t s)
 {
     int rc;
     m->vel_valid = false;
     const int64_t n = m->n, T = m->T;
     const double *X = m->xyz.data(), *W = m->omega.data();
-    m->hbar = T > 0 ? mean_edge(m) : 0.0;
+    // two serial passes that depend on the positions and connectivity only
+    // run beside the node ordering: the mean edge length (summed in the
+    // sorted order of the unique edges, as the oracle sums it) and the
+    // boundary's convexity
+    double hbar = 0.0;
+    bool convex = false;
+    JoinedThread th_hbar([&] { hbar = T > 0 ? mean_edge(m) : 0.0; });
+    JoinedThread th_convex([&] { convex = T > 0 && boundary_convex(m); });
 
     // ---- nodes ordered by a k-d split into leaves of 64 (one band-kernel
     // block per leaf); evaluation points (bs_eval_points) follow the nodes
@@ -1065,6 +1086,9 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
     std::vector<int32_t> tlist((size_t)tn + 1);
     for (int64_t k = 0; k < tn; ++k) tlist[(size_t)k] = (int32_t)(t0 + k);
     tlist[(size_t)tn] = (int32_t)tn;
+
+    th_hbar.join();
+    m->hbar = hbar;
 
     // ---- tets: centroids, bins
     std::vector<double> cen((size_t)(3 * T));
@@ -1291,7 +1315,8 @@ int build_device_mesh(bs_mesh *m, hipStream_t s)
             std::sort(o, o + (c1 - c0));
         }
     });
-    m->convex = T > 0 && boundary_convex(m);
+    th_convex.join();
+    m->convex = convex;
 
     // ---- upload
     const size_t nb = sizeof(float) * 3 * (size_t)npad;
