@@ -819,8 +819,11 @@ struct BandPieceLds {
     float4 pb[kBandPiece][2];   // G4 points 2e, 2e + 1: W.y, W.z of each
 };
 
+// Seven waves per SIMD (72 registers, a few spilled outside the point
+// loop): the kernel waits on its record loads and LDS reads as well as
+// issuing; at six waves it took 74.5 ms on the two-ring mesh, at seven 72.0.
 template <int PREC>
-__global__ void __launch_bounds__(64 * kBandWaves) k_band_piece(DevMesh m, Thresholds th, double *__restrict__ band,
+__global__ void __launch_bounds__(64 * kBandWaves) __attribute__((amdgpu_waves_per_eu(7))) k_band_piece(DevMesh m, Thresholds th, double *__restrict__ band,
                                                                 unsigned long long *__restrict__ cnt)
 {
     __shared__ double red[kBandWaves][3][64];
